@@ -1,0 +1,242 @@
+"""ctypes wrapper over the C oracle ``liboracle.so`` (FP64, CPU).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Functions and the passages they follow (paper = arXiv 1511.00152):
+
+* ``philox4x64_10`` -- block function of Philox4x64-10 (Salmon et al., SC'11);
+  pinned bit-exactly to ``numpy.random.Philox``.
+* ``lemire_from_words`` -- Lemire's multiply-and-reject uniform integer; pinned
+  by exhaustive enumeration at 8-bit word width.
+* ``floyd_from_draws`` / ``sample_indices`` -- exact-m sampling without
+  replacement (Sec. I setup; App. B); pinned by enumerating every draw sequence
+  at tiny (p, m), by inclusion frequencies m/p (Lemma in App. B) and pair
+  frequencies m(m-1)/(p(p-1)) (Thm. in App. B), and against ``oracle_def``
+  which draws with numpy's own Philox.
+* ``signs`` -- the random diagonal D (Sec. III, eq. ROS); pinned against
+  ``oracle_def`` (numpy Philox) and E[D]=0 statistics.
+* ``fwht_normalized`` -- y = H x with H the normalized Sylvester Hadamard
+  matrix (Sec. III); pinned against ``scipy.linalg.hadamard``.
+* ``compress`` -- Alg. 1 first loop; pinned against ``oracle_def`` and norm
+  preservation.
+* ``gram_accumulate`` / ``cov_finalize`` -- Sec. V estimators; pinned by exact
+  enumeration of all m-subsets (unbiasedness, App. C expectations), by the
+  m = p special case, and against ``oracle_def``.
+* ``kmeans_step`` / ``unmix`` / ``kmeanspp`` -- Sec. VI and Alg. 1; pinned by
+  the m = p reduction to Lloyd's algorithm (scikit-learn and a brute-force
+  loop), monotone objective, and ``oracle_def``.  The seeding itself follows
+  Arthur & Vassilvitskii with a reading of the sparse case: parity unpinned
+  beyond "it returns K distinct compressed samples".
+* ``y_entry`` -- one entry of H D x from the definition (row of H times D x).
+* ``mean_estimate`` -- Thm. "sampleMean"; pinned by enumeration (unbiased).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        u64 = ctypes.c_uint64
+        i32 = ctypes.c_int
+        L.orc_philox4x64_10.argtypes = [P, P, P]
+        L.orc_lemire_from_words.argtypes = [ctypes.c_uint32, i32, P, i32, P]
+        L.orc_lemire_from_words.restype = ctypes.c_uint32
+        L.orc_floyd_from_draws.argtypes = [i64, i64, P, P]
+        L.orc_floyd_from_draws.restype = i32
+        L.orc_sample_indices.argtypes = [u64, u64, i64, i64, P]
+        L.orc_signs.argtypes = [u64, i64, P]
+        L.orc_fwht_normalized.argtypes = [P, i64]
+        L.orc_y_entry_f64.argtypes = [P, i64, i64, P]
+        L.orc_y_entry_f64.restype = ctypes.c_double
+        L.orc_y_entry_f32.argtypes = [P, i64, i64, P]
+        L.orc_y_entry_f32.restype = ctypes.c_double
+        L.orc_compress_f64.argtypes = [u64, i64, i64, P, i64, i64, u64, P, P, i32]
+        L.orc_compress_f32.argtypes = [u64, i64, i64, P, i64, i64, u64, P, P, i32]
+        L.orc_gram_accumulate.argtypes = [i64, i64, P, P, i64, P, i32]
+        L.orc_cov_finalize.argtypes = [i64, i64, i64, P, P]
+        L.orc_kmeans_step.argtypes = [i64, i64, P, P, i64, i32, P, P, P, P, P, i32]
+        L.orc_unmix.argtypes = [u64, i64, P, i32, P]
+        L.orc_kmeanspp.argtypes = [u64, i64, i64, P, P, i64, i32, P, P]
+        L.orc_mean_estimate.argtypes = [i64, i64, P, P, i64, P]
+        L.orc_max_threads.restype = i32
+        L.orc_sample_batch.argtypes = [u64, u64, i64, i64, i64, P, i32]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+def philox4x64_10(counter, key):
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def lemire_from_words(rng: int, bits: int, words):
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    used = ctypes.c_int(0)
+    r = lib().orc_lemire_from_words(rng, bits, _ptr(w), len(w), ctypes.byref(used))
+    return int(r), int(used.value)
+
+
+def floyd_from_draws(p: int, m: int, draws):
+    d = np.ascontiguousarray(draws, dtype=np.uint32)
+    idx = np.zeros(m, dtype=np.uint16)
+    rc = lib().orc_floyd_from_draws(p, m, _ptr(d), _ptr(idx))
+    if rc != 0:
+        raise ValueError("invalid draw sequence")
+    return idx
+
+
+def sample_indices(seed: int, i: int, p: int, m: int):
+    idx = np.zeros(m, dtype=np.uint16)
+    lib().orc_sample_indices(seed, i, p, m, _ptr(idx))
+    return idx
+
+
+def sample_batch(seed: int, i0: int, n: int, p: int, m: int, nthreads: int = 0):
+    idx = np.zeros((n, m), dtype=np.uint16)
+    lib().orc_sample_batch(seed, i0, n, p, m, _ptr(idx), nthreads)
+    return idx
+
+
+def signs(seed: int, p: int):
+    D = np.zeros(p, dtype=np.int8)
+    lib().orc_signs(seed, p, _ptr(D))
+    return D
+
+
+def fwht_normalized(v):
+    a = np.array(v, dtype=np.float64, copy=True)
+    lib().orc_fwht_normalized(_ptr(a), a.shape[-1])
+    return a
+
+
+def y_entry(seed: int, x, j: int, D=None):
+    if D is None:
+        D = signs(seed, x.shape[-1])
+    D = np.ascontiguousarray(D, dtype=np.int8)
+    if x.dtype == np.float32:
+        xx = np.ascontiguousarray(x)
+        return float(lib().orc_y_entry_f32(_ptr(D), xx.shape[-1], j, _ptr(xx)))
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    return float(lib().orc_y_entry_f64(_ptr(D), xx.shape[-1], j, _ptr(xx)))
+
+
+def compress(X, seed: int, m: int, i0: int = 0, nthreads: int = 0):
+    """Returns (vals float64 n x m, idx uint16 n x m)."""
+    n, p = X.shape
+    vals = np.zeros((n, m), dtype=np.float64)
+    idx = np.zeros((n, m), dtype=np.uint16)
+    if X.dtype == np.float32:
+        Xc = np.ascontiguousarray(X)
+        lib().orc_compress_f32(seed, p, m, _ptr(Xc), n, p, i0, _ptr(vals), _ptr(idx), nthreads)
+    else:
+        Xc = np.ascontiguousarray(X, dtype=np.float64)
+        lib().orc_compress_f64(seed, p, m, _ptr(Xc), n, p, i0, _ptr(vals), _ptr(idx), nthreads)
+    return vals, idx
+
+
+def gram_accumulate(p: int, vals, idx, G=None, nthreads: int = 0):
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.uint16)
+    n, m = vals.shape
+    if G is None:
+        G = np.zeros((p, p), dtype=np.float64)
+    lib().orc_gram_accumulate(p, m, _ptr(vals), _ptr(idx), n, _ptr(G), nthreads)
+    return G
+
+
+def cov_finalize(p: int, m: int, n: int, G):
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    C = np.zeros((p, p), dtype=np.float64)
+    lib().orc_cov_finalize(p, m, n, _ptr(G), _ptr(C))
+    return C
+
+
+def covariance(p: int, vals, idx, nthreads: int = 0):
+    n, m = vals.shape
+    return cov_finalize(p, m, n, gram_accumulate(p, vals, idx, nthreads=nthreads))
+
+
+def kmeans_step(p: int, vals, idx, centers, nthreads: int = 0):
+    """Returns (centers_out, assign int32, objective, margin)."""
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.uint16)
+    cin = np.ascontiguousarray(centers, dtype=np.float64)
+    n, m = vals.shape
+    K = cin.shape[0]
+    cout = np.zeros_like(cin)
+    assign = np.zeros(n, dtype=np.int32)
+    margin = np.zeros(n, dtype=np.float64)
+    obj = ctypes.c_double(0.0)
+    lib().orc_kmeans_step(p, m, _ptr(vals), _ptr(idx), n, K, _ptr(cin), _ptr(cout), _ptr(assign),
+                          ctypes.byref(obj), _ptr(margin), nthreads)
+    return cout, assign, float(obj.value), margin
+
+
+def unmix(seed: int, centers_pre):
+    c = np.ascontiguousarray(centers_pre, dtype=np.float64)
+    K, p = c.shape
+    out = np.zeros_like(c)
+    lib().orc_unmix(seed, p, _ptr(c), K, _ptr(out))
+    return out
+
+
+def kmeanspp(seed: int, p: int, vals, idx, K: int):
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.uint16)
+    n, m = vals.shape
+    centers = np.zeros((K, p), dtype=np.float64)
+    chosen = np.zeros(K, dtype=np.int64)
+    lib().orc_kmeanspp(seed, p, m, _ptr(vals), _ptr(idx), n, K, _ptr(centers), _ptr(chosen))
+    return centers, chosen
+
+
+def mean_estimate(p: int, vals, idx):
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.uint16)
+    n, m = vals.shape
+    mean = np.zeros(p, dtype=np.float64)
+    lib().orc_mean_estimate(p, m, _ptr(vals), _ptr(idx), n, _ptr(mean))
+    return mean
+
+
+def sparsified_kmeans(X, seed: int, m: int, K: int, T: int, init_centers=None, nthreads: int = 0):
+    """Alg. 1: compress once, seed, T assignment/update rounds, unmix.
+
+    Returns dict with vals, idx, centers_pre (per step list), assign, objectives,
+    centers (unmixed).
+    """
+    n, p = X.shape
+    vals, idx = compress(X, seed, m, nthreads=nthreads)
+    if init_centers is None:
+        init_centers, _ = kmeanspp(seed, p, vals, idx, K)
+    mu = init_centers
+    objs = []
+    assign = None
+    for _ in range(T):
+        mu, assign, J, _ = kmeans_step(p, vals, idx, mu, nthreads=nthreads)
+        objs.append(J)
+    return {"vals": vals, "idx": idx, "centers_pre": mu, "assign": assign,
+            "objectives": objs, "centers": unmix(seed, mu), "init": init_centers}

@@ -1,0 +1,154 @@
+"""Seeded synthetic inputs for the workloads (shared by tests and the bench).
+
+This module holds no step of the method: it only draws data matrices X (one
+sample per row, row-major n x p) and model parameters.  Both the GPU path and
+the CPU oracle receive the same bytes from here.
+
+Workloads (shapes and distributions follow the paper's synthetic generators;
+the paper's public datasets are not used):
+
+* ``spiked`` -- x_i = U diag(sqrt(lam)) kappa_i + eps_i, U the Q factor of a
+  p x k standard-normal matrix, kappa, eps ~ N(0, 1): the principal-component
+  generator of Sec. V (numerical experiment of Thm. "covariance").
+  Small case: p = 256, k = 5, lam = (50, 40, 30, 20, 10), n = 2000, FP64.
+  Precision case: p = 4096, k = 20, lam_k = 50 / k, n = 2^20, FP32.
+* ``mixture`` -- K Gaussian clusters, centers N(0, 4 I), unit within-cluster
+  variance, each entry replaced with probability 1% by 20 * t_3 (heavy-tailed
+  spikes, the "few large entries" case that motivates preconditioning):
+  p = 1024, K = 10, n = 2^20, FP32.
+
+Row blocks are drawn from per-block generators (block = 65536 rows) so any
+leading slice of a workload is identical to the same rows of the full one.
+"""
+import math
+
+import numpy as np
+
+BLOCK = 65536
+
+WORKLOADS = {
+    # name: dict of shape/distribution parameters
+    "small_f64": dict(kind="spiked", n=2000, p=256, lam=(50.0, 40.0, 30.0, 20.0, 10.0),
+                      dtype="f64", data_seed=0, gamma=0.1, K=5, T=10),
+    "mixture_f32": dict(kind="mixture", n=1 << 20, p=1024, K=10, center_std=2.0, spike_prob=0.01,
+                        spike_scale=20.0, spike_dof=3, dtype="f32", data_seed=1, gamma=0.05, T=20),
+    "spiked4096_f32": dict(kind="spiked", n=1 << 20, p=4096, lam=tuple(50.0 / k for k in range(1, 21)),
+                           dtype="f32", data_seed=2, gamma=0.1),
+}
+
+
+def m_from_gamma(gamma, p):
+    """m = floor(gamma * p + 1/2): m must be a natural number (Cor. sampleMean)."""
+    return int(math.floor(gamma * p + 0.5))
+
+
+def model(name):
+    """Model parameters (numpy float64), from the workload's data seed."""
+    w = WORKLOADS[name]
+    rng = np.random.default_rng([w["data_seed"], 0xA11CE])
+    p = w["p"]
+    if w["kind"] == "spiked":
+        k = len(w["lam"])
+        U, _ = np.linalg.qr(rng.standard_normal((p, k)))
+        return {"U": U, "lam": np.asarray(w["lam"], dtype=np.float64)}
+    centers = w["center_std"] * rng.standard_normal((w["K"], p))
+    return {"centers": centers}
+
+
+def _block_numpy(name, b, rows, mdl):
+    w = WORKLOADS[name]
+    p = w["p"]
+    rng = np.random.default_rng([w["data_seed"], 0xB10C, b])
+    if w["kind"] == "spiked":
+        U, lam = mdl["U"], mdl["lam"]
+        kappa = rng.standard_normal((rows, len(lam)))
+        X = (kappa * np.sqrt(lam)) @ U.T + rng.standard_normal((rows, p))
+        labels = None
+    else:
+        labels = rng.integers(0, w["K"], size=rows)
+        X = mdl["centers"][labels] + rng.standard_normal((rows, p))
+        mask = rng.random((rows, p)) < w["spike_prob"]
+        nspk = int(mask.sum())
+        X[mask] = w["spike_scale"] * rng.standard_t(w["spike_dof"], size=nspk)
+    return X, labels
+
+
+def rows_numpy(name, n=None, mdl=None, with_labels=False):
+    """First n rows of the workload as a numpy array of the workload dtype."""
+    w = WORKLOADS[name]
+    n = w["n"] if n is None else n
+    mdl = model(name) if mdl is None else mdl
+    dt = np.float64 if w["dtype"] == "f64" else np.float32
+    X = np.empty((n, w["p"]), dtype=dt)
+    labels = np.empty(n, dtype=np.int64) if w["kind"] == "mixture" else None
+    for b in range((n + BLOCK - 1) // BLOCK):
+        r0 = b * BLOCK
+        r1 = min(n, r0 + BLOCK)
+        Xb, lb = _block_numpy(name, b, BLOCK, mdl)
+        X[r0:r1] = Xb[: r1 - r0]
+        if labels is not None:
+            labels[r0:r1] = lb[: r1 - r0]
+    if with_labels:
+        return X, labels
+    return X
+
+
+def rows_torch(name, n=None, device="cuda", seed_offset=0):
+    """The workload drawn with torch on `device` (fast for the full sizes).
+
+    Same distribution and model parameters as rows_numpy, different random
+    stream (torch's generator), so the bytes differ from rows_numpy's.
+    """
+    import torch
+
+    w = WORKLOADS[name]
+    n = w["n"] if n is None else n
+    p = w["p"]
+    mdl = model(name)
+    dt = torch.float64 if w["dtype"] == "f64" else torch.float32
+    g = torch.Generator(device=device)
+    g.manual_seed(w["data_seed"] * 1000003 + 17 + seed_offset)
+    X = torch.empty((n, p), dtype=dt, device=device)
+    step = BLOCK
+    if w["kind"] == "spiked":
+        U = torch.as_tensor(mdl["U"], dtype=torch.float32, device=device)
+        sl = torch.as_tensor(np.sqrt(mdl["lam"]), dtype=torch.float32, device=device)
+        for r0 in range(0, n, step):
+            r1 = min(n, r0 + step)
+            kappa = torch.randn((r1 - r0, len(sl)), generator=g, device=device)
+            blk = (kappa * sl) @ U.T
+            blk += torch.randn((r1 - r0, p), generator=g, device=device)
+            X[r0:r1] = blk.to(dt)
+    else:
+        C = torch.as_tensor(mdl["centers"], dtype=torch.float32, device=device)
+        for r0 in range(0, n, step):
+            r1 = min(n, r0 + step)
+            rows = r1 - r0
+            lab = torch.randint(0, w["K"], (rows,), generator=g, device=device)
+            blk = C[lab] + torch.randn((rows, p), generator=g, device=device)
+            mask = torch.rand((rows, p), generator=g, device=device) < w["spike_prob"]
+            # Student t with nu dof: Z / sqrt(chi2_nu / nu), chi2 from nu squared normals
+            z = torch.randn((rows, p), generator=g, device=device)
+            chi = torch.zeros((rows, p), device=device)
+            for _ in range(w["spike_dof"]):
+                chi += torch.randn((rows, p), generator=g, device=device) ** 2
+            t = z / torch.sqrt(chi / w["spike_dof"])
+            blk = torch.where(mask, w["spike_scale"] * t, blk)
+            X[r0:r1] = blk.to(dt)
+    return X
+
+
+def random_compressed(n, p, m, seed, dtype=np.float32, K=None):
+    """Synthetic compressed data for step-level tests: sorted distinct indices
+    per row (numpy's own sampler) and normal values, plus optional K centers.
+    The values are representable in `dtype` (so both sides can read the same
+    numbers)."""
+    rng = np.random.default_rng([seed, 0xC0DE])
+    idx = np.empty((n, m), dtype=np.uint16)
+    for i in range(n):
+        idx[i] = np.sort(rng.choice(p, size=m, replace=False))
+    vals = rng.standard_normal((n, m)).astype(dtype)
+    out = {"vals": vals, "idx": idx}
+    if K is not None:
+        out["centers"] = rng.standard_normal((K, p)) * 0.5
+    return out

@@ -1,0 +1,462 @@
+"""Pins of the CPU oracle to facts outside itself (no GPU needed).
+
+Each test checks the oracle against something the paper or mathematics fixes:
+an independent library routine, exhaustive enumeration on tiny inputs, a
+closed form, or a value the paper prints.  A plausible slip in the oracle (a
+dropped term, a wrong sign or index, a transposed operand, an off-by-one in
+the sampler) fails at least one of them.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import bounds, oracle_def, ref
+
+ROOT_GOLDEN = __file__.rsplit("/", 1)[0] + "/golden/"
+
+
+# ---------------------------------------------------------------- Philox --
+def test_philox_block_matches_numpy():
+    """The C block function equals numpy's Philox4x64-10 (which advances its
+    counter before producing each block)."""
+    rng = np.random.default_rng(123)
+    cases = [([0, 0, 0, 0], [0, 0]), ([1, 2, 3, 4], [5, 6]),
+             ([2 ** 64 - 1, 7, 0, 0], [2 ** 63, 1])]
+    for _ in range(20):
+        cases.append((rng.integers(0, 2 ** 63, 4, dtype=np.uint64).tolist(),
+                      rng.integers(0, 2 ** 63, 2, dtype=np.uint64).tolist()))
+    for ctr, key in cases:
+        c = 0
+        for w in reversed(ctr):
+            c = (c << 64) | int(w)
+        c = (c - 1) % (1 << 256)
+        words = np.array([(c >> (64 * k)) & (2 ** 64 - 1) for k in range(4)], dtype=np.uint64)
+        g = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=words)
+        expect = g.random_raw(4)
+        got = ref.philox4x64_10(ctr, key)
+        assert np.array_equal(got, expect), (ctr, key)
+
+
+# ---------------------------------------------------------------- Lemire --
+@pytest.mark.parametrize("rng_", [1, 2, 3, 5, 6, 7, 10, 17, 100, 127, 128, 129, 200, 255, 256])
+def test_lemire_exhaustive_8bit(rng_):
+    """Every value in [0, range) has the same number of accepting first words,
+    and exactly 2^8 mod range first words are rejected."""
+    counts = np.zeros(rng_, dtype=np.int64)
+    rejected = 0
+    for w in range(256):
+        r, used = ref.lemire_from_words(rng_, 8, [w] + list(range(255, -1, -1)))
+        if used > 1:
+            rejected += 1
+        else:
+            counts[r] += 1
+    assert rejected == 256 % rng_
+    assert np.all(counts == counts[0])
+    assert counts.sum() + rejected == 256
+
+
+def test_lemire_rejection_consumes_next_word():
+    """A rejected first word is replaced by the next word of the stream."""
+    rng_ = 3  # 256 mod 3 = 1 word rejected: the word whose low part is 0
+    rej = [w for w in range(256) if ref.lemire_from_words(rng_, 8, [w, 200])[1] > 1]
+    assert len(rej) == 1
+    r, used = ref.lemire_from_words(rng_, 8, [rej[0], 200])
+    assert used == 2 and r == (200 * rng_) >> 8
+
+
+def test_lemire_32bit_matches_definition():
+    rng = np.random.default_rng(5)
+    for _ in range(2000):
+        rg = int(rng.integers(1, 2 ** 20))
+        w = int(rng.integers(0, 2 ** 32))
+        r, used = ref.lemire_from_words(rg, 32, [w, w ^ 0x5555])
+        if used == 1:
+            assert r == (w * rg) >> 32
+
+
+# ----------------------------------------------------------------- Floyd --
+@pytest.mark.parametrize("p,m", [(6, 3), (7, 4), (5, 1), (4, 4), (6, 5), (8, 2)])
+def test_floyd_all_draw_sequences_uniform(p, m):
+    """Enumerating every draw sequence (draw k uniform on {0..p-m+k}) yields
+    every m-subset equally often: prod_{t=p-m}^{p-1}(t+1) / C(p, m) times."""
+    ranges = [range(t + 1) for t in range(p - m, p)]
+    seen = {}
+    total = 0
+    for draws in itertools.product(*ranges):
+        idx = tuple(ref.floyd_from_draws(p, m, list(draws)).tolist())
+        assert len(set(idx)) == m and list(idx) == sorted(idx)
+        seen[idx] = seen.get(idx, 0) + 1
+        total += 1
+    assert len(seen) == math.comb(p, m)
+    assert set(seen.values()) == {total // math.comb(p, m)}
+
+
+def test_sampler_matches_literal_oracle():
+    """The C sampler equals the Python one that draws from numpy's Philox."""
+    for seed, i, p, m in [(0, 0, 16, 5), (0, 1, 16, 16), (3, 99, 64, 7), (11, 2 ** 40, 256, 26),
+                          (0, 5, 1024, 51), (7, 12345, 4096, 410), (1, 3, 2, 1), (1, 4, 100, 30)]:
+        assert ref.sample_indices(seed, i, p, m).tolist() == oracle_def.kept_set(seed, i, p, m)
+
+
+def test_sampler_inclusion_frequencies():
+    """Lemma (App. B): each coordinate is kept with probability m/p; Thm. (App.
+    B): each pair with probability m(m-1)/(p(p-1)).  Chi-square at p=32, m=8."""
+    p, m, n = 32, 8, 40000
+    idx = ref.sample_batch(9, 0, n, p, m)
+    assert np.all(np.diff(idx.astype(np.int64), axis=1) > 0)
+    cnt = np.bincount(idx.ravel(), minlength=p)
+    e = n * m / p
+    chi2 = float(((cnt - e) ** 2 / e).sum())
+    assert chi2 < 70.0  # 31 dof; P(chi2 > 70) ~ 1e-4
+    onehot = np.zeros((n, p))
+    np.put_along_axis(onehot, idx.astype(np.int64), 1.0, axis=1)
+    pair = onehot.T @ onehot
+    ep = n * m * (m - 1) / (p * (p - 1))
+    off = pair[~np.eye(p, dtype=bool)]
+    z = (off - ep) / math.sqrt(ep)
+    assert abs(z.mean()) < 0.05 and np.abs(z).max() < 5.5
+
+
+def test_thm7_exceedance_rate():
+    """Thm. RRT at the setup of its figure (p=100, gamma=0.3): ||H_k - I||_2 =
+    max_j |(p/m) cnt_j / n_k - 1| exceeds t(delta3=0.001) in about 0.1% of runs."""
+    p, m, nk, runs = 100, 30, 400, 1000
+    idx = ref.sample_batch(21, 0, nk * runs, p, m).reshape(runs, nk, m)
+    t = bounds.t_for_delta3(1e-3, nk, m, p)
+    exceed = 0
+    for r in range(runs):
+        cnt = np.bincount(idx[r].ravel(), minlength=p)
+        if np.max(np.abs(p / m * cnt / nk - 1.0)) > t:
+            exceed += 1
+    assert exceed <= 5
+
+
+# ----------------------------------------------------------------- signs --
+def test_signs_match_literal_oracle():
+    for seed, p in [(0, 16), (0, 256), (5, 300), (2 ** 40 + 3, 1024)]:
+        assert np.array_equal(ref.signs(seed, p).astype(np.float64), oracle_def.signs(seed, p))
+
+
+def test_signs_balanced():
+    D = ref.signs(0, 1 << 16).astype(np.float64)
+    assert set(np.unique(D)) == {-1.0, 1.0}
+    assert abs(D.mean()) < 4.0 / math.sqrt(1 << 16)
+
+
+# ------------------------------------------------------------------ FWHT --
+@pytest.mark.parametrize("logp", list(range(1, 13)))
+def test_fwht_equals_dense_hadamard(logp):
+    """y = H x with H = scipy.linalg.hadamard(p) / sqrt(p) (Sylvester order)."""
+    p = 1 << logp
+    rng = np.random.default_rng(logp)
+    x = rng.standard_normal(p)
+    H = scipy.linalg.hadamard(p).astype(np.float64) / math.sqrt(p)
+    y = ref.fwht_normalized(x)
+    assert np.max(np.abs(y - H @ x)) <= 1e-13 * max(1.0, np.max(np.abs(H @ x))) * logp
+    # orthonormal and an involution: ||Hx|| = ||x||, H(Hx) = x
+    assert abs(np.linalg.norm(y) - np.linalg.norm(x)) <= 1e-13 * np.linalg.norm(x) * logp
+    assert np.max(np.abs(ref.fwht_normalized(y) - x)) <= 1e-13 * logp * np.max(np.abs(x)) + 1e-15
+
+
+@pytest.mark.parametrize("a,b", [(64, 64), (32, 32), (64, 32), (16, 64), (8, 8)])
+def test_fwht_kronecker_factorisation(a, b):
+    """H_{ab} = H_a (x) H_b, so y = vec(H_a Xt H_b^T) for the row-major a x b
+    reshape Xt of x (the ordering the two-stage matrix-core transform uses)."""
+    p = a * b
+    rng = np.random.default_rng(p)
+    x = rng.standard_normal(p)
+    Ha = scipy.linalg.hadamard(a).astype(np.float64) / math.sqrt(a)
+    Hb = scipy.linalg.hadamard(b).astype(np.float64) / math.sqrt(b)
+    y = (Ha @ x.reshape(a, b) @ Hb.T).reshape(-1)
+    assert np.max(np.abs(y - ref.fwht_normalized(x))) < 1e-12
+
+
+def test_second_moment_of_preconditioned_entry_by_enumeration():
+    """Sec. III: for ||x|| = 1, E_D[y_j^2] = 1/p exactly (all 2^p sign vectors)."""
+    p = 8
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(p)
+    x /= np.linalg.norm(x)
+    acc = np.zeros(p)
+    for bits in range(2 ** p):
+        D = np.array([-1.0 if (bits >> k) & 1 else 1.0 for k in range(p)])
+        acc += ref.fwht_normalized(D * x) ** 2
+    assert np.max(np.abs(acc / 2 ** p - 1.0 / p)) < 1e-14
+
+
+# -------------------------------------------------------------- compress --
+def test_compress_matches_literal_oracle():
+    p, n, m, seed = 16, 12, 5, 3
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((n, p))
+    vals, idx = ref.compress(X, seed, m)
+    Y, W, ix = oracle_def.compress(X.T, seed, m)
+    for i in range(n):
+        assert idx[i].tolist() == ix[i]
+        assert np.max(np.abs(vals[i] - W[ix[i], i])) < 1e-13
+        assert np.count_nonzero(W[:, i]) <= m
+
+
+def test_compress_float_input_widens_exactly():
+    p, n, m = 64, 20, 9
+    X = np.random.default_rng(2).standard_normal((n, p)).astype(np.float32)
+    v32, i32 = ref.compress(X, 0, m)
+    v64, i64 = ref.compress(X.astype(np.float64), 0, m)
+    assert np.array_equal(i32, i64) and np.array_equal(v32, v64)
+
+
+def test_compress_offset_rows_are_global_samples():
+    """Row r of a chunk starting at i0 is sample i0 + r: chunked == one shot."""
+    p, n, m = 32, 30, 6
+    X = np.random.default_rng(3).standard_normal((n, p))
+    v, i = ref.compress(X, 1, m)
+    v2, i2 = ref.compress(X[10:], 1, m, i0=10)
+    assert np.array_equal(i[10:], i2) and np.array_equal(v[10:], v2)
+
+
+def test_y_entry_definition_matches_transform():
+    p = 128
+    x = np.random.default_rng(4).standard_normal(p)
+    D = ref.signs(7, p).astype(np.float64)
+    y = ref.fwht_normalized(D * x)
+    for j in [0, 1, 5, 64, 127]:
+        assert abs(ref.y_entry(7, x, j) - y[j]) < 1e-13
+
+
+def test_norm_reduction_cor_rho():
+    """Cor. cor-rho: ||w||^2 <= (m/p)(2/eta) log(2np/alpha) ||x||^2 for all
+    samples with probability >= 1 - alpha (alpha = 1/100), here on a spiky input."""
+    p, n, m = 256, 500, 26
+    rng = np.random.default_rng(8)
+    X = np.zeros((n, p))
+    X[np.arange(n), rng.integers(0, p, n)] = 1.0  # canonical basis vectors
+    vals, _ = ref.compress(X, 0, m)
+    bound = bounds.cor_rho_norm_bound(m, p, 0.01, n=n)
+    assert np.all((vals ** 2).sum(axis=1) <= bound * (X ** 2).sum(axis=1) + 1e-12)
+
+
+# ------------------------------------------------------------ covariance --
+def _all_subsets(p, m):
+    return [np.array(c, dtype=np.uint16) for c in itertools.combinations(range(p), m)]
+
+
+@pytest.mark.parametrize("p,m", [(6, 3), (6, 2), (8, 5), (5, 4)])
+def test_covariance_unbiased_by_enumeration(p, m):
+    """Thm. covariance / App. C: averaging C_n over every m-subset gives y y^T;
+    the rescaled matrix alone has expectation C + (p-m)/(m-1) diag(C)."""
+    y = np.random.default_rng(p * 10 + m).standard_normal(p)
+    acc_n = np.zeros((p, p))
+    acc_e = np.zeros((p, p))
+    subs = _all_subsets(p, m)
+    for s in subs:
+        G = ref.gram_accumulate(p, y[s][None, :], s[None, :])
+        acc_n += ref.cov_finalize(p, m, 1, G)
+        acc_e += (p * (p - 1)) / (m * (m - 1)) * G
+    C = np.outer(y, y)
+    assert np.max(np.abs(acc_n / len(subs) - C)) < 1e-13 * np.max(np.abs(C)) * 10
+    expect_e = C + (p - m) / (m - 1) * np.diag(np.diag(C))
+    assert np.max(np.abs(acc_e / len(subs) - expect_e)) < 1e-12 * np.max(np.abs(C)) * 10
+
+
+def test_mean_estimator_unbiased_by_enumeration():
+    p, m = 7, 3
+    y = np.random.default_rng(0).standard_normal(p)
+    acc = np.zeros(p)
+    subs = _all_subsets(p, m)
+    for s in subs:
+        acc += ref.mean_estimate(p, y[s][None, :], s[None, :])
+    assert np.max(np.abs(acc / len(subs) - y)) < 1e-14
+
+
+def test_covariance_matches_literal_oracle():
+    p, n, m, seed = 16, 40, 6, 2
+    X = np.random.default_rng(5).standard_normal((n, p))
+    vals, idx = ref.compress(X, seed, m)
+    C = ref.covariance(p, vals, idx)
+    Y, W, ix = oracle_def.compress(X.T, seed, m)
+    Cd = oracle_def.cov_n(Y, ix, m)
+    assert np.max(np.abs(C - Cd)) < 1e-12 * np.max(np.abs(Cd))
+
+
+def test_covariance_m_equals_p_is_empirical_covariance():
+    """m = p keeps everything: C_n = (1/n) Y Y^T, and unmixing with (HD) gives
+    (1/n) X X^T."""
+    p, n = 32, 50
+    X = np.random.default_rng(6).standard_normal((n, p))
+    vals, idx = ref.compress(X, 4, p)
+    C = ref.covariance(p, vals, idx)
+    Y = (oracle_def.ros_matrix(4, p) @ X.T)
+    assert np.max(np.abs(C - Y @ Y.T / n)) < 1e-12
+    HD = oracle_def.ros_matrix(4, p)
+    assert np.max(np.abs(HD.T @ C @ HD - X.T @ X / n)) < 1e-12
+
+
+def test_covariance_closed_form_scalings():
+    """C_n[j,j] = p/(m n) G[j,j] and C_n[j,k] = p(p-1)/(m(m-1) n) G[j,k]:
+    the two displayed steps collapse to two scalings."""
+    p, m, n = 64, 7, 13
+    G = np.random.default_rng(7).standard_normal((p, p))
+    C = ref.cov_finalize(p, m, n, G)
+    off = p * (p - 1) / (m * (m - 1) * n)
+    dia = p / (m * n)
+    E = G * off
+    np.fill_diagonal(E, np.diag(G) * dia)
+    assert np.max(np.abs(C - E)) < 1e-13 * np.max(np.abs(E))
+
+
+def test_covariance_monte_carlo_unbiased():
+    """Many seeds at tiny p: the mean of C_n over independent samplings is
+    within a few standard errors of Y Y^T / n entry by entry."""
+    p, n, m, runs = 8, 4, 3, 3000
+    X = np.random.default_rng(9).standard_normal((n, p))
+    Y = oracle_def.ros_matrix(0, p) @ X.T
+    Cemp = Y @ Y.T / n
+    samples = np.empty((runs, p, p))
+    for r in range(runs):
+        idx = ref.sample_batch(0, r * n, n, p, m)
+        vals = np.take_along_axis(Y.T, idx.astype(np.int64), axis=1)
+        samples[r] = ref.covariance(p, vals, idx)
+    mean = samples.mean(axis=0)
+    se = samples.std(axis=0) / math.sqrt(runs) + 1e-12
+    z = (mean - Cemp) / se
+    assert np.abs(z).max() < 5.0
+
+
+def test_cor5_printed_values():
+    rows = [l.split() for l in open(ROOT_GOLDEN + "cor5_m_lower_bound.txt") if not l.startswith("#")]
+    for n, printed, mint in rows:
+        v = bounds.cor5_m_lower_bound(float(n), 512, 0.01, eta=1.0)
+        assert round(v, 1) == float(printed)
+        assert math.ceil(v) == int(mint)
+
+
+# --------------------------------------------------------------- K-means --
+def test_kmeans_step_matches_literal_oracle():
+    p, n, m, K, seed = 16, 60, 5, 3, 1
+    X = np.random.default_rng(10).standard_normal((n, p)) + np.repeat(np.eye(3, p) * 4, 20, axis=0)
+    vals, idx = ref.compress(X, seed, m)
+    c0 = np.random.default_rng(11).standard_normal((K, p))
+    Y, W, ix = oracle_def.compress(X.T, seed, m)
+    c1, a1, J1, _ = ref.kmeans_step(p, vals, idx, c0)
+    c1d, a1d, J1d = oracle_def.kmeans_step(Y, ix, c0.T.copy())
+    assert np.array_equal(a1, a1d)
+    assert abs(J1 - J1d) < 1e-12 * J1d
+    assert np.max(np.abs(c1 - c1d.T)) < 1e-13
+
+
+def test_kmeans_zero_count_keeps_previous_center_entry():
+    p, m = 8, 2
+    vals = np.array([[1.0, 2.0], [3.0, 4.0]])
+    idx = np.array([[0, 1], [0, 1]], dtype=np.uint16)
+    c0 = np.arange(16, dtype=np.float64).reshape(2, 8)  # sample 0,1 both nearest to 0
+    c1, a, J, _ = ref.kmeans_step(p, vals, idx, c0)
+    assert a.tolist() == [0, 0]
+    assert c1[0, 0] == 2.0 and c1[0, 1] == 3.0
+    assert np.array_equal(c1[0, 2:], c0[0, 2:]) and np.array_equal(c1[1], c0[1])
+
+
+def test_kmeans_tie_goes_to_lowest_index():
+    p = 4
+    vals = np.array([[1.0, 1.0]])
+    idx = np.array([[0, 2]], dtype=np.uint16)
+    c0 = np.array([[2.0, 9, 0.0, 9], [0.0, 9, 2.0, 9]])
+    _, a, J, margin = ref.kmeans_step(p, vals, idx, c0)
+    assert a[0] == 0 and margin[0] == 0.0 and J == 2.0
+
+
+def test_kmeans_m_equals_p_is_lloyd():
+    """With R_i = I the sparsified objective is the K-means objective
+    (Sec. VI); the unmixed iterates equal Lloyd's algorithm on X (scikit-learn
+    and a brute-force loop)."""
+    from sklearn.cluster import KMeans
+
+    p, n, K, T, seed = 16, 300, 4, 6, 5
+    rng = np.random.default_rng(12)
+    centers_true = rng.standard_normal((K, p)) * 3
+    X = centers_true[rng.integers(0, K, n)] + rng.standard_normal((n, p))
+    mu0 = X[[0, 1, 2, 3]].copy()
+    HD = oracle_def.ros_matrix(seed, p)
+    vals, idx = ref.compress(X, seed, p)
+    mu = (HD @ mu0.T).T
+    objs = []
+    for _ in range(T):
+        mu, assign, J, _ = ref.kmeans_step(p, vals, idx, mu)
+        objs.append(J)
+    mu_x = ref.unmix(seed, mu)
+    bf = mu0.T.copy()
+    for _ in range(T):
+        bf, a_bf, J_bf = oracle_def.lloyd_step(X.T, bf)
+    assert np.array_equal(assign, a_bf)
+    assert np.max(np.abs(mu_x - bf.T)) < 1e-10
+    km = KMeans(n_clusters=K, init=mu0, n_init=1, max_iter=T, tol=0.0, algorithm="lloyd").fit(X)
+    assert np.max(np.abs(np.sort(mu_x, axis=0) - np.sort(km.cluster_centers_, axis=0))) < 1e-8
+    assert all(b <= a + 1e-9 * abs(a) for a, b in zip(objs, objs[1:]))
+
+
+def test_kmeans_objective_nonincreasing_sparse():
+    p, n, m, K = 64, 400, 9, 5
+    rng = np.random.default_rng(13)
+    X = (rng.standard_normal((K, p)) * 2)[rng.integers(0, K, n)] + rng.standard_normal((n, p))
+    vals, idx = ref.compress(X, 2, m)
+    mu, _ = ref.kmeanspp(2, p, vals, idx, K)
+    prev = math.inf
+    for _ in range(10):
+        mu, assign, J, _ = ref.kmeans_step(p, vals, idx, mu)
+        assert J <= prev * (1 + 1e-12)
+        prev = J
+
+
+def test_unmix_matches_literal_oracle():
+    p, K = 32, 3
+    c = np.random.default_rng(14).standard_normal((K, p))
+    assert np.max(np.abs(ref.unmix(6, c) - oracle_def.unmix(6, c.T).T)) < 1e-13
+
+
+def test_kmeanspp_picks_distinct_samples():
+    p, n, m, K = 64, 200, 10, 6
+    X = np.random.default_rng(15).standard_normal((n, p))
+    vals, idx = ref.compress(X, 0, m)
+    C, chosen = ref.kmeanspp(0, p, vals, idx, K)
+    assert len(set(chosen.tolist())) == K
+    for k, c in enumerate(chosen):
+        z = np.zeros(p)
+        z[idx[c].astype(np.int64)] = vals[c]
+        assert np.array_equal(C[k], z)
+    C2, chosen2 = ref.kmeanspp(0, p, vals, idx, K)
+    assert np.array_equal(chosen, chosen2)
+
+
+# --------------------------------------------------------- end to end PCA --
+@pytest.mark.slow
+def test_table1_preconditioning_helps_pca():
+    """Table "num-recovered-precon", qualitatively: p=512, n=1024, 10 canonical
+    PCs, lambda = 10..1, x_i = sum_j kappa_ij lambda_j u_j.  With
+    preconditioning more PCs are recovered (|<u_hat, u>| > 0.95) than without,
+    at gamma = 0.1 and 0.3, and the count grows with gamma.  The printed means
+    are not reproduced in absolute terms under this reading of the generator
+    (they are listed with this reading's values in the design notes)."""
+    p, n, k, runs = 512, 1024, 10, 8
+    lam = np.arange(10, 0, -1, dtype=np.float64)
+    means = {}
+    for gamma in (0.1, 0.3):
+        m = int(round(gamma * p))
+        with_p, without_p = [], []
+        for r in range(runs):
+            rng = np.random.default_rng([77, r])
+            U = np.eye(p)[:, rng.choice(p, k, replace=False)]
+            X = (rng.standard_normal((n, k)) * lam) @ U.T
+            seed = 1000 + r
+            vals, idx = ref.compress(X, seed, m)
+            V = np.linalg.eigh(ref.covariance(p, vals, idx))[1][:, ::-1][:, :k]
+            Up = oracle_def.ros_matrix(seed, p) @ U  # true PCs, preconditioned domain
+            with_p.append(int(np.sum(np.abs(np.sum(V * Up, axis=0)) > 0.95)))
+            idx0 = ref.sample_batch(seed, 0, n, p, m)
+            vals0 = np.take_along_axis(X, idx0.astype(np.int64), axis=1)
+            V0 = np.linalg.eigh(ref.covariance(p, vals0, idx0))[1][:, ::-1][:, :k]
+            without_p.append(int(np.sum(np.abs(np.sum(V0 * U, axis=0)) > 0.95)))
+        assert np.mean(with_p) > np.mean(without_p), (gamma, with_p, without_p)
+        means[gamma] = np.mean(with_p)
+    assert means[0.3] > means[0.1]
