@@ -1,0 +1,212 @@
+"""Preconditioned data sparsification on MI355X (gfx950).
+
+Python face of libpds (C ABI in include/pds.h).  Tensors are torch tensors on
+the current HIP device; every call enqueues the library's kernels on
+``torch.cuda.current_stream()`` and returns without synchronising.
+
+    plan = Plan(p, m, seed, PDS_F32)
+    vals, idx = compress(plan, X)              # Alg. 1 first loop (Sec. III, eq. ROS)
+    C = covariance(plan, vals, idx)            # Sec. V, unbiased C_n (preconditioned domain)
+    mu, c, J = kmeans_step(plan, vals, idx, mu0)   # Sec. VI, one Lloyd round
+    centers = unmix(plan, mu)                  # eq. mu-mu'
+"""
+import ctypes
+
+from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_F32, PDS_F64,
+                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_SPLIT_BF16, EXPORTS, PdsError,
+                   check, lib)
+
+__all__ = [
+    "Plan", "compress", "covariance", "CovarianceAccumulator", "kmeans_step", "unmix", "sparsified_kmeans",
+    "PdsError", "PDS_F64", "PDS_F32", "PDS_SPLIT_BF16", "lib", "EXPORTS",
+]
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Plan:
+    """pds_plan: dimension p, kept coordinates m, seed, precision."""
+
+    def __init__(self, p: int, m: int, seed: int = 0, prec: int = PDS_F32):
+        self.p, self.m, self.seed, self.prec = int(p), int(m), int(seed), int(prec)
+        h = ctypes.c_void_p()
+        check(lib().pds_plan_create(ctypes.byref(h), self.p, self.m, self.seed, self.prec), "pds_plan_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().pds_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dtype(self):
+        import torch
+
+        return torch.float64 if self.prec == PDS_F64 else torch.float32
+
+    def signs(self):
+        import numpy as np
+
+        D = np.zeros(self.p, dtype=np.int8)
+        check(lib().pds_signs(self._h, D.ctypes.data_as(ctypes.c_void_p)), "pds_signs")
+        return D
+
+    def workspace_size(self, op: int, n: int, K: int = 1) -> int:
+        b = ctypes.c_size_t(0)
+        check(lib().pds_workspace_size(self._h, int(op), int(n), int(K), ctypes.byref(b)), "pds_workspace_size")
+        return int(b.value)
+
+    def workspace(self, op: int, n: int, K: int = 1, device=None):
+        import torch
+
+        nb = self.workspace_size(op, n, K)
+        if nb == 0:
+            return None
+        return torch.empty(nb, dtype=torch.uint8, device=device or "cuda")
+
+
+def compress(plan: Plan, X, i0: int = 0, vals=None, idx=None, ws=None):
+    """Returns (vals n x m, idx n x m uint16 as torch.int16 storage)."""
+    import torch
+
+    n, p = X.shape
+    if p != plan.p:
+        raise ValueError(f"X has {p} columns, plan has p={plan.p}")
+    if X.dtype != plan.dtype:
+        raise TypeError(f"X dtype {X.dtype} does not match plan dtype {plan.dtype}")
+    if X.stride(1) != 1:
+        raise ValueError("X rows must be contiguous")
+    if vals is None:
+        vals = torch.empty((n, plan.m), dtype=plan.dtype, device=X.device)
+    if idx is None:
+        idx = torch.empty((n, plan.m), dtype=torch.int16, device=X.device)
+    if ws is None:
+        ws = plan.workspace(PDS_OP_COMPRESS, n, device=X.device)
+    wsb = ws.numel() if ws is not None else 0
+    check(lib().pds_compress(plan.handle, _ptr(X), n, X.stride(0), int(i0), _ptr(vals), _ptr(idx), _ptr(ws), wsb,
+                             _stream()), "pds_compress")
+    return vals, idx
+
+
+class CovarianceAccumulator:
+    """Streaming covariance (Sec. V): add batches, then finalize."""
+
+    def __init__(self, plan: Plan, device=None):
+        import torch
+
+        self.plan = plan
+        self.acc = torch.zeros((plan.p, plan.p), dtype=torch.float64, device=device or "cuda")
+        self.n = 0
+        self._ws = None
+
+    def _workspace(self, n, device):
+        need = self.plan.workspace_size(PDS_OP_COVARIANCE, n)
+        if need and (self._ws is None or self._ws.numel() < need):
+            import torch
+
+            self._ws = torch.empty(need, dtype=torch.uint8, device=device)
+        return self._ws
+
+    def add(self, vals, idx):
+        n = vals.shape[0]
+        ws = self._workspace(n, vals.device)
+        check(lib().pds_covariance(self.plan.handle, _ptr(vals), _ptr(idx), n, _ptr(self.acc), 0, 0,
+                                   ctypes.c_void_p(0), _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
+              "pds_covariance")
+        self.n += n
+        return self
+
+    def finalize(self, C=None):
+        import torch
+
+        if C is None:
+            C = torch.empty((self.plan.p, self.plan.p), dtype=torch.float64, device=self.acc.device)
+        check(lib().pds_covariance(self.plan.handle, ctypes.c_void_p(0), ctypes.c_void_p(0), 0, _ptr(self.acc), 1,
+                                   self.n, _ptr(C), ctypes.c_void_p(0), 0, _stream()), "pds_covariance")
+        return C
+
+
+def covariance(plan: Plan, vals, idx, acc=None, ws=None, C=None):
+    """Unbiased covariance estimate C_n (p x p FP64) of the compressed samples."""
+    import torch
+
+    n = vals.shape[0]
+    dev = vals.device
+    if acc is None:
+        acc = torch.zeros((plan.p, plan.p), dtype=torch.float64, device=dev)
+    if C is None:
+        C = torch.empty((plan.p, plan.p), dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = plan.workspace(PDS_OP_COVARIANCE, n, device=dev)
+    check(lib().pds_covariance(plan.handle, _ptr(vals), _ptr(idx), n, _ptr(acc), 1, n, _ptr(C), _ptr(ws),
+                               ws.numel() if ws is not None else 0, _stream()), "pds_covariance")
+    return C
+
+
+def kmeans_step(plan: Plan, vals, idx, centers, out=None, assign=None, objective=None, ws=None):
+    """One sparsified Lloyd round; returns (centers_out, assign int32, objective (1,) FP64)."""
+    import torch
+
+    n = vals.shape[0]
+    K = centers.shape[0]
+    dev = vals.device
+    if out is None:
+        out = torch.empty_like(centers)
+    if assign is None:
+        assign = torch.empty(n, dtype=torch.int32, device=dev)
+    if objective is None:
+        objective = torch.empty(1, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = plan.workspace(PDS_OP_KMEANS, n, K, device=dev)
+    check(lib().pds_kmeans_step(plan.handle, _ptr(vals), _ptr(idx), n, K, _ptr(centers), _ptr(out), _ptr(assign),
+                                _ptr(objective), _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
+          "pds_kmeans_step")
+    return out, assign, objective
+
+
+def unmix(plan: Plan, centers_pre, out=None):
+    """mu = (H D)^T mu' for each row of centers_pre (FP64)."""
+    import torch
+
+    if out is None:
+        out = torch.empty_like(centers_pre)
+    check(lib().pds_unmix(plan.handle, _ptr(centers_pre), centers_pre.shape[0], _ptr(out), _stream()), "pds_unmix")
+    return out
+
+
+def sparsified_kmeans(plan: Plan, X, init_centers, iterations: int):
+    """Alg. 1 with given initial centers (preconditioned domain, K x p FP64):
+    one compression pass, `iterations` assignment/update rounds, unmixing.
+    Returns dict(vals, idx, assign, centers_pre, centers, objectives)."""
+    import torch
+
+    vals, idx = compress(plan, X)
+    K = init_centers.shape[0]
+    ws = plan.workspace(PDS_OP_KMEANS, X.shape[0], K, device=X.device)
+    a = init_centers.clone()
+    b = torch.empty_like(a)
+    assign = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+    objs = torch.empty(iterations, dtype=torch.float64, device=X.device)
+    for t in range(iterations):
+        kmeans_step(plan, vals, idx, a, out=b, assign=assign, objective=objs[t:t + 1], ws=ws)
+        a, b = b, a
+    return {"vals": vals, "idx": idx, "assign": assign, "centers_pre": a, "centers": unmix(plan, a),
+            "objectives": objs}

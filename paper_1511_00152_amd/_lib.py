@@ -1,0 +1,79 @@
+"""ctypes binding of libpds.so (the C ABI in include/pds.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Importing this module fails loudly when the library has not been
+built; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpds.so")
+
+PDS_OK = 0
+PDS_E_ARG = -1
+PDS_E_UNSUPPORTED = -2
+PDS_E_M = -3
+PDS_E_WORKSPACE = -4
+PDS_E_HIP = -5
+
+PDS_F64 = 0
+PDS_F32 = 1
+PDS_SPLIT_BF16 = 2
+
+PDS_OP_COMPRESS = 0
+PDS_OP_COVARIANCE = 1
+PDS_OP_KMEANS = 2
+
+# every entry point declared in include/pds.h
+EXPORTS = (
+    "pds_plan_create", "pds_plan_destroy", "pds_signs", "pds_workspace_size", "pds_covariance_acc_size",
+    "pds_compress", "pds_covariance", "pds_kmeans_step", "pds_unmix", "pds_last_error", "pds_version",
+)
+
+
+class PdsError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib().pds_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with status {status}: {msg}")
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpds.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    u64 = ctypes.c_uint64
+    i32 = ctypes.c_int32
+    sz = ctypes.c_size_t
+    st = ctypes.c_int
+    L.pds_plan_create.argtypes = [ctypes.POINTER(P), i64, i64, u64, i32]
+    L.pds_plan_destroy.argtypes = [P]
+    L.pds_signs.argtypes = [P, P]
+    L.pds_workspace_size.argtypes = [P, i32, i64, i32, ctypes.POINTER(sz)]
+    L.pds_covariance_acc_size.argtypes = [P, ctypes.POINTER(sz)]
+    L.pds_compress.argtypes = [P, P, i64, i64, u64, P, P, P, sz, P]
+    L.pds_covariance.argtypes = [P, P, P, i64, P, i32, i64, P, P, sz, P]
+    L.pds_kmeans_step.argtypes = [P, P, P, i64, i32, P, P, P, P, P, sz, P]
+    L.pds_unmix.argtypes = [P, P, i32, P, P]
+    L.pds_last_error.restype = ctypes.c_char_p
+    L.pds_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("pds_last_error", "pds_version"):
+            f.restype = st
+    _lib = L
+    return L
+
+
+def check(status, where):
+    if status != PDS_OK:
+        raise PdsError(status, where)

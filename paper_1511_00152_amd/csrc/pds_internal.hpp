@@ -1,0 +1,47 @@
+// Internal launch interface between the C ABI (api.hip) and the kernels.
+// Arguments are validated by the caller; launchers only size grids and launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pds {
+
+struct DeviceInfo {
+    int cus;       // compute units
+    int device;    // ordinal
+};
+
+hipError_t device_info(DeviceInfo& info);
+
+// ---- compression --------------------------------------------------------
+// Kept coordinates (ascending) of samples i0 .. i0+n-1 into idx (n x m).
+hipError_t launch_sample_indices(uint64_t seed, int p, int m, int64_t n, uint64_t i0, uint16_t* idx,
+                                 const DeviceInfo& dev, hipStream_t s);
+
+// y = H D x per row, then vals[r][t] = y[idx[r][t]].  prec: 0 f64, 1 f32,
+// 2 split-bf16 (matrix-core transform).  ws: scratch for very large p.
+hipError_t launch_compress(int prec, uint64_t seed, int p, int m, const void* X, int64_t n, int64_t ldx,
+                           const uint16_t* idx, void* vals, void* ws, size_t ws_bytes, const DeviceInfo& dev,
+                           hipStream_t s);
+size_t compress_workspace(int prec, int p, int64_t n, const DeviceInfo& dev);
+
+// ---- covariance -----------------------------------------------------------
+size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo& dev);
+hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n,
+                                        double* acc, void* ws, size_t ws_bytes, const DeviceInfo& dev,
+                                        hipStream_t s);
+hipError_t launch_covariance_finalize(int prec, int p, int m, int64_t n_total, const double* acc, double* C,
+                                      hipStream_t s);
+
+// ---- K-means ----------------------------------------------------------------
+size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceInfo& dev);
+hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, int K,
+                              const double* cin, double* cout, int32_t* assign, double* objective, void* ws,
+                              size_t ws_bytes, const DeviceInfo& dev, hipStream_t s);
+
+// ---- unmix ------------------------------------------------------------------
+hipError_t launch_unmix(uint64_t seed, int p, const double* cpre, int K, double* cout, hipStream_t s);
+
+}  // namespace pds

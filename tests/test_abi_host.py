@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point include/pds.h declares, validates arguments before touching the
+device, and its host-computed sign diagonal equals the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1511_00152_amd as pds
+from paper_1511_00152_amd import _lib
+from oracle import ref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "pds.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pds_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pds.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTS)
+    assert pds.lib().pds_version().startswith(b"pds")
+
+
+def _plan_status(p, m, prec=pds.PDS_F32):
+    h = ctypes.c_void_p()
+    st = pds.lib().pds_plan_create(ctypes.byref(h), p, m, 0, prec)
+    if st == 0:
+        pds.lib().pds_plan_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("p,m,expect", [
+    (256, 26, 0), (2, 1, 0), (2, 2, 0), (65536, 100, 0),
+    (6, 3, _lib.PDS_E_UNSUPPORTED), (1, 1, _lib.PDS_E_UNSUPPORTED), (131072, 5, _lib.PDS_E_UNSUPPORTED),
+    (0, 0, _lib.PDS_E_UNSUPPORTED), (784, 40, _lib.PDS_E_UNSUPPORTED),
+    (256, 0, _lib.PDS_E_M), (256, 257, _lib.PDS_E_M), (256, -1, _lib.PDS_E_M),
+])
+def test_plan_validation(p, m, expect):
+    assert _plan_status(p, m) == expect
+
+
+def test_plan_rejects_unknown_precision_and_null_out():
+    assert _plan_status(256, 26, prec=7) == _lib.PDS_E_ARG
+    assert pds.lib().pds_plan_create(None, 256, 26, 0, 1) == _lib.PDS_E_ARG
+    assert b"NULL" in pds.lib().pds_last_error()
+
+
+@pytest.mark.parametrize("seed,p", [(0, 256), (0, 4096), (123456789, 1024), (2 ** 63 + 5, 65536), (3, 2)])
+def test_host_signs_equal_oracle(seed, p):
+    plan = pds.Plan(p, 1, seed=seed)
+    assert np.array_equal(plan.signs(), ref.signs(seed, p))
+
+
+def test_hot_calls_validate_before_device_work():
+    L = pds.lib()
+    plan = pds.Plan(256, 26, prec=pds.PDS_F32)
+    h = plan.handle
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    # compress
+    assert L.pds_compress(None, fake, 4, 256, 0, fake, fake, null, 0, null) == _lib.PDS_E_ARG
+    assert L.pds_compress(h, fake, -1, 256, 0, fake, fake, null, 0, null) == _lib.PDS_E_ARG
+    assert L.pds_compress(h, null, 4, 256, 0, fake, fake, null, 0, null) == _lib.PDS_E_ARG
+    assert L.pds_compress(h, fake, 4, 255, 0, fake, fake, null, 0, null) == _lib.PDS_E_ARG
+    assert L.pds_compress(h, null, 0, 0, 0, null, null, null, 0, null) == _lib.PDS_OK  # n == 0 no-op
+    # covariance
+    plan1 = pds.Plan(256, 1, prec=pds.PDS_F32)
+    assert L.pds_covariance(plan1.handle, fake, fake, 4, fake, 1, 4, fake, fake, 1 << 30, null) == _lib.PDS_E_M
+    assert L.pds_covariance(h, fake, fake, 4, null, 0, 0, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_covariance(h, null, fake, 4, fake, 0, 0, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_covariance(h, fake, fake, 4, fake, 1, 0, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_covariance(h, fake, fake, 4, fake, 1, 4, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_covariance(h, null, null, 0, fake, 0, 0, null, null, 0, null) == _lib.PDS_OK
+    # kmeans
+    assert L.pds_kmeans_step(h, fake, fake, 4, 0, fake, fake, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_step(h, fake, fake, 4, 1025, fake, fake, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_step(h, fake, fake, 4, 3, fake, fake, null, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_step(h, fake, fake, 4, 3, fake, fake, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG  # alias
+    assert L.pds_kmeans_step(h, null, null, 0, 3, null, null, null, null, null, 0, null) == _lib.PDS_OK
+    # unmix
+    assert L.pds_unmix(h, fake, 0, ctypes.c_void_p(0x2000), null) == _lib.PDS_E_ARG
+    assert L.pds_unmix(h, null, 2, fake, null) == _lib.PDS_E_ARG
+    assert L.pds_unmix(h, fake, 2, fake, null) == _lib.PDS_E_ARG
+
+
+def test_workspace_queries():
+    plan = pds.Plan(4096, 410, prec=pds.PDS_SPLIT_BF16)
+    assert plan.workspace_size(pds.PDS_OP_COMPRESS if hasattr(pds, "PDS_OP_COMPRESS") else 0, 1 << 20) == 0
+    cov = plan.workspace_size(1, 1 << 20)
+    # block offsets (17 per sample) + FP32 partial tiles
+    assert cov >= (1 << 20) * 17 * 4
+    assert plan.workspace_size(1, 0) == 0
+    km = pds.Plan(1024, 51).workspace_size(2, 1 << 20, 10)
+    assert km > 0
+    b = ctypes.c_size_t()
+    assert pds.lib().pds_workspace_size(plan.handle, 2, 10, 0, ctypes.byref(b)) == _lib.PDS_E_ARG
+    assert pds.lib().pds_workspace_size(plan.handle, 9, 10, 1, ctypes.byref(b)) == _lib.PDS_E_ARG
+    assert pds.lib().pds_covariance_acc_size(plan.handle, ctypes.byref(b)) == 0 and b.value == 4096 * 4096 * 8
+    # huge p needs a compress workspace (transform staging outside LDS)
+    assert pds.Plan(65536, 10).workspace_size(0, 1000) > 0
