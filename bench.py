@@ -1,0 +1,284 @@
+"""Benchmark: samples/s of precondition + sample + covariance at p = 4096.
+
+One step = one pass of the hot path over the whole synthetic batch resident in
+HBM: compress (signs, normalized Walsh-Hadamard transform, exact-m sampling,
+gather) and the covariance estimator (Gram accumulation, FP64 split
+reduction, diagonal-corrected scaling).  Workload: n = 2^20 samples, p = 4096,
+m = 410 (gamma = 0.1), FP32 input with a rank-20 spiked covariance
+(lam_k = 50 / k) plus unit noise.  Two variants run back to back: the
+split-BF16 matrix-core form (reported as `value`) and plain FP32 (reported
+under `fp32_variant`).
+
+Prints one JSON line on stdout.  Per-kernel durations come from HIP events the
+library records around each launch on the launch stream (pds_profile_*).
+`cpu_baseline` times the FP64 CPU oracle on a bounded prefix of the same
+workload on this host, and the GPU's error against it on that prefix is
+reported under `errors`.
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "samples/s precondition+sample+cov at p=4096: split-BF16 MFMA vs FP32, rel err≤1e-5"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def profile_report(lib):
+    need = ctypes.c_size_t(0)
+    buf = ctypes.create_string_buffer(1 << 16)
+    lib.pds_profile_report(buf, len(buf), ctypes.byref(need))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, tot, mn, mx = line.split()
+        out[name] = {"launches": int(cnt), "total_ms": float(tot), "avg_ms": float(tot) / int(cnt),
+                     "min_ms": float(mn), "max_ms": float(mx)}
+    return out
+
+
+def algorithmic_work(name, n, p, m, prec):
+    """(bound, units per launch, unit, peak) for a kernel: bytes for HBM-bound
+    kernels, flops for matrix-core kernels (2 flops per multiply-add)."""
+    eb = 8 if prec == "f64" else 4
+    if name.startswith("gram_"):
+        dt = {"gram_bf16x3": "bf16", "gram_f32": "f32", "gram_f64": "f64"}[name]
+        # G = sum_i w_i w_i^T: m^2 multiply-adds per sample (upper + lower)
+        return "mfma", 2.0 * n * m * m, "TFLOP/s", PEAK_TFLOPS[dt]
+    if name == "compress":
+        return "hbm", n * (p * eb + m * eb), "GB/s", PEAK_HBM_GBS  # read x_i, write kept values
+    if name == "sample_indices":
+        return "hbm", n * m * 2.0, "GB/s", PEAK_HBM_GBS  # write kept indices
+    if name == "block_offsets":
+        return "hbm", n * m * 2.0, "GB/s", PEAK_HBM_GBS
+    if name == "gram_reduce":
+        return "hbm", 2.0 * p * p * 8, "GB/s", PEAK_HBM_GBS
+    if name == "cov_finalize":
+        return "hbm", 2.0 * p * p * 8, "GB/s", PEAK_HBM_GBS
+    return "hbm", 0.0, "GB/s", PEAK_HBM_GBS
+
+
+def source_digest():
+    h = hashlib.sha1()
+    d = os.path.join(ROOT, "paper_1511_00152_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def load_traffic(kernel, launches_per_step):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def run_variant(pds, X, p, m, prec_name, steps, warmup):
+    import torch
+
+    prec = {"split": pds.PDS_SPLIT_BF16, "f32": pds.PDS_F32}[prec_name]
+    n = X.shape[0]
+    plan = pds.Plan(p, m, seed=0, prec=prec)
+    vals = torch.empty((n, m), dtype=torch.float32, device=X.device)
+    idx = torch.empty((n, m), dtype=torch.int16, device=X.device)
+    ws = plan.workspace(pds.PDS_OP_COVARIANCE if hasattr(pds, "PDS_OP_COVARIANCE") else 1, n, device=X.device)
+    acc = torch.zeros((p, p), dtype=torch.float64, device=X.device)
+    C = torch.empty((p, p), dtype=torch.float64, device=X.device)
+
+    def step():
+        pds.compress(plan, X, vals=vals, idx=idx)
+        acc.zero_()
+        pds.covariance(plan, vals, idx, acc=acc, ws=ws, C=C)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lib = pds.lib()
+    lib.pds_profile_enable(1)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.pds_profile_enable(0)
+    kern = profile_report(lib)
+    wall_ms = (t1 - t0) * 1e3 / steps
+    return {"ms_per_step": wall_ms, "gpu_ms_per_step": ev0.elapsed_time(ev1) / steps,
+            "value": n / (wall_ms / 1e3), "kernels": kern, "plan": plan, "vals": vals, "idx": idx, "C": C}
+
+
+def roofline(kern, n, p, m, prec_name, steps):
+    name, info = max(kern.items(), key=lambda kv: kv[1]["total_ms"])
+    bound, units, unit, peak = algorithmic_work(name, n, p, m, prec_name)
+    avg_s = info["avg_ms"] / 1e3
+    achieved = units / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
+    traffic = load_traffic(name, info["launches"] // max(steps, 1))
+    return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": traffic, "avg_ms": info["avg_ms"],
+            "algorithmic_per_launch": units}
+
+
+def cpu_baseline_and_errors(pds, X, p, m, nsamp, variants):
+    """Oracle on the first nsamp rows (timed), and each GPU variant's error
+    against it on the same rows."""
+    import numpy as np
+    import torch
+
+    from oracle import ref
+
+    Xs = X[:nsamp].cpu().numpy()
+    t0 = time.perf_counter()
+    v_o, i_o = ref.compress(Xs, 0, m)
+    C_o = ref.covariance(p, v_o, i_o)
+    dt = time.perf_counter() - t0
+    base = {"value": nsamp / dt, "unit": "samples/s", "cores": ref.max_threads(), "kind": "oracle",
+            "sample": f"first {nsamp} samples of the workload: compress + covariance, FP64 C oracle, OpenMP",
+            "seconds": dt}
+    ev_o = np.linalg.eigvalsh(C_o)[::-1][:20]
+    errs = {"sample": f"first {nsamp} samples, vs the FP64 oracle"}
+    for name in variants:
+        prec = {"split": pds.PDS_SPLIT_BF16, "f32": pds.PDS_F32}[name]
+        plan = pds.Plan(p, m, seed=0, prec=prec)
+        vals, idx = pds.compress(plan, X[:nsamp])
+        C = pds.covariance(plan, vals, idx)
+        torch.cuda.synchronize()
+        Cg = C.cpu().numpy()
+        ev = np.linalg.eigvalsh(Cg)[::-1][:20]
+        same_idx = bool(np.array_equal(idx.cpu().numpy().view(np.uint16), i_o))
+        errs[name] = {
+            "idx_bit_exact": same_idx,
+            "vals_max_rel": float(np.max(np.abs(vals.cpu().numpy() - v_o)) / np.max(np.abs(v_o))),
+            "cov_max_rel": float(np.max(np.abs(Cg - C_o)) / np.max(np.abs(C_o))),
+            "cov_fro_rel": float(np.linalg.norm(Cg - C_o) / np.linalg.norm(C_o)),
+            "eig20_max_rel": float(np.max(np.abs(ev - ev_o) / np.abs(ev_o))),
+        }
+    return base, errs
+
+
+def calibrate_copy(nbytes=1 << 30):
+    """A plain device copy of known size, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters of a profiled run."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=None, help="samples (default: the workload's 2^20)")
+    ap.add_argument("--variants", default="split,f32")
+    ap.add_argument("--cpu-samples", type=int, default=32768)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py is single-process, single-GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1511_00152_amd as pds
+    import synth
+
+    torch.cuda.set_device(0)
+    name = "spiked4096_f32"
+    w = synth.WORKLOADS[name]
+    p = w["p"]
+    m = synth.m_from_gamma(w["gamma"], p)
+    n = args.n or w["n"]
+    log(f"generating {name}: n={n} p={p} m={m}")
+    X = synth.rows_torch(name, n, device="cuda")
+    torch.cuda.synchronize()
+    if args.calibrate_copy:
+        calibrate_copy()
+
+    variants = [v for v in args.variants.split(",") if v]
+    res = {}
+    for v in variants:
+        log(f"variant {v}: warmup {args.warmup}, steps {args.steps}")
+        res[v] = run_variant(pds, X, p, m, v, args.steps, args.warmup)
+        log(f"  {res[v]['ms_per_step']:.3f} ms/step, {res[v]['value']:.4g} samples/s; kernels: " +
+            ", ".join(f"{k} {d['avg_ms']:.3f} ms" for k, d in res[v]["kernels"].items()))
+
+    head = variants[0]
+    out = {
+        "metric": METRIC,
+        "value": res[head]["value"],
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res[head]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if head == "split" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{name}: n={n}, p={p}, m={m} (gamma={w['gamma']}), FP32 input, rank-20 spiked "
+                               "covariance lam_k=50/k + unit noise; step = compress + covariance",
+                   "n": n, "p": p, "m": m, "variant": head},
+        "roofline": roofline(res[head]["kernels"], n, p, m, head, args.steps),
+        "kernels_ms": {k: d["avg_ms"] for k, d in res[head]["kernels"].items()},
+        "gpu_ms_per_step": res[head]["gpu_ms_per_step"],
+    }
+    for v in variants[1:]:
+        out[f"{v}_variant"] = {"value": res[v]["value"], "ms_per_step": res[v]["ms_per_step"],
+                               "kernels_ms": {k: d["avg_ms"] for k, d in res[v]["kernels"].items()},
+                               "roofline": roofline(res[v]["kernels"], n, p, m, v, args.steps)}
+    if len(variants) > 1:
+        out["split_over_f32"] = res["split"]["value"] / res["f32"]["value"] if "f32" in res and "split" in res else None
+    for v in res.values():
+        v.pop("vals", None), v.pop("idx", None), v.pop("C", None)
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on {args.cpu_samples} samples")
+        base, errs = cpu_baseline_and_errors(pds, X, p, m, args.cpu_samples, variants)
+        out["cpu_baseline"] = base
+        out["errors"] = errs
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

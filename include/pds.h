@@ -159,6 +159,19 @@ pds_status pds_kmeans_step(pds_plan plan, const void* vals, const uint16_t* idx,
  * Errors: PDS_E_ARG (null pointers, K < 1). */
 pds_status pds_unmix(pds_plan plan, const double* centers_pre, int32_t K, double* centers_out, void* stream);
 
+/* Measurement hooks (not part of the method).  pds_profile_enable(1) clears
+ * any previous records and starts bracketing every kernel the library launches
+ * with a pair of HIP events on the launch stream; pds_profile_enable(0) stops
+ * recording.  pds_profile_report waits for the recorded events, writes one
+ * text line per kernel name, "name launches total_ms min_ms max_ms\n", into
+ * buf (host, len bytes, NUL-terminated, truncated if short; *needed receives
+ * the full length + 1 when non-NULL) and clears the records.  Recording costs
+ * two event records per launch and allocates host-side event objects, so leave
+ * it off outside measurement.  Errors: PDS_E_ARG (buf NULL with len > 0),
+ * PDS_E_HIP. */
+pds_status pds_profile_enable(int32_t on);
+pds_status pds_profile_report(char* buf, size_t len, size_t* needed);
+
 /* Text of the last error reported to the calling thread ("" if none). */
 const char* pds_last_error(void);
 

@@ -184,6 +184,19 @@ void orc_sample_indices(uint64_t seed, uint64_t i, int64_t p, int64_t m, uint16_
     free(draws);
 }
 
+/* Number of 32-bit words sample i's draws consume (m when no draw was
+ * rejected by Lemire's method).                                             */
+int64_t orc_sample_words_used(uint64_t seed, uint64_t i, int64_t p, int64_t m)
+{
+    orc_stream s;
+    stream_init(&s, seed, i, 0);
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t t = p - m + k;
+        (void)lemire_bits((uint32_t)(t + 1), 32, stream_word_fn, &s);
+    }
+    return (int64_t)(s.ctr[0] - 1) * 8 + s.pos;
+}
+
 /* ------------------------------------------------------------------------- */
 /* The random sign diagonal D of the ROS (Sec. III, eq. ROS): one sign per
  * coordinate, shared by every sample (Alg. 1 applies one HD to all of X).

@@ -72,6 +72,8 @@ def lib():
         L.orc_mean_estimate.argtypes = [i64, i64, P, P, i64, P]
         L.orc_max_threads.restype = i32
         L.orc_sample_batch.argtypes = [u64, u64, i64, i64, i64, P, i32]
+        L.orc_sample_words_used.argtypes = [u64, u64, i64, i64]
+        L.orc_sample_words_used.restype = i64
         _lib = L
     return _lib
 
@@ -118,6 +120,10 @@ def sample_batch(seed: int, i0: int, n: int, p: int, m: int, nthreads: int = 0):
     idx = np.zeros((n, m), dtype=np.uint16)
     lib().orc_sample_batch(seed, i0, n, p, m, _ptr(idx), nthreads)
     return idx
+
+
+def sample_words_used(seed: int, i: int, p: int, m: int) -> int:
+    return int(lib().orc_sample_words_used(seed, i, p, m))
 
 
 def signs(seed: int, p: int):

@@ -28,7 +28,8 @@ PDS_OP_KMEANS = 2
 # every entry point declared in include/pds.h
 EXPORTS = (
     "pds_plan_create", "pds_plan_destroy", "pds_signs", "pds_workspace_size", "pds_covariance_acc_size",
-    "pds_compress", "pds_covariance", "pds_kmeans_step", "pds_unmix", "pds_last_error", "pds_version",
+    "pds_compress", "pds_covariance", "pds_kmeans_step", "pds_unmix", "pds_profile_enable", "pds_profile_report",
+    "pds_last_error", "pds_version",
 )
 
 
@@ -64,6 +65,8 @@ def lib():
     L.pds_covariance.argtypes = [P, P, P, i64, P, i32, i64, P, P, sz, P]
     L.pds_kmeans_step.argtypes = [P, P, P, i64, i32, P, P, P, P, P, sz, P]
     L.pds_unmix.argtypes = [P, P, i32, P, P]
+    L.pds_profile_enable.argtypes = [i32]
+    L.pds_profile_report.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(sz)]
     L.pds_last_error.restype = ctypes.c_char_p
     L.pds_version.restype = ctypes.c_char_p
     for name in EXPORTS:

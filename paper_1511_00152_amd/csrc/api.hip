@@ -6,8 +6,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "../../include/pds.h"
 #include "pds_device.hpp"
@@ -70,6 +73,35 @@ hipError_t device_info(DeviceInfo& info)
     info.cus = 256;
     info.device = dev;
     return hipSuccess;
+}
+
+// ---- per-kernel event timing ------------------------------------------------
+namespace {
+struct ProfRecord {
+    const char* name;
+    hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof;
+}  // namespace
+
+ProfScope::ProfScope(const char* name, hipStream_t s) : slot_(-1), s_(s)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    ProfRecord r{name, nullptr, nullptr};
+    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
+    if (hipEventRecord(r.start, s) != hipSuccess) return;
+    g_prof.push_back(r);
+    slot_ = (int)g_prof.size() - 1;
+}
+
+ProfScope::~ProfScope()
+{
+    if (slot_ < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (slot_ < (int)g_prof.size()) (void)hipEventRecord(g_prof[slot_].stop, s_);
 }
 
 }  // namespace pds
@@ -255,6 +287,64 @@ pds_status pds_unmix(pds_plan plan, const double* centers_pre, int32_t K, double
                                      reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "unmix");
     return PDS_OK;
+}
+
+pds_status pds_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(pds::g_prof_mu);
+    if (on) {
+        for (auto& r : pds::g_prof) {
+            (void)hipEventDestroy(r.start);
+            (void)hipEventDestroy(r.stop);
+        }
+        pds::g_prof.clear();
+    }
+    pds::g_prof_on = on != 0;
+    return PDS_OK;
+}
+
+pds_status pds_profile_report(char* buf, size_t len, size_t* needed)
+{
+    if (!buf && len > 0) return fail(PDS_E_ARG, "buf is NULL");
+    struct Agg {
+        int count = 0;
+        double total = 0, mn = 1e300, mx = 0;
+    };
+    std::map<std::string, Agg> agg;
+    std::vector<std::string> order;
+    pds_status st = PDS_OK;
+    {
+        std::lock_guard<std::mutex> lk(pds::g_prof_mu);
+        for (auto& r : pds::g_prof) {
+            float ms = 0.0f;
+            hipError_t e = hipEventSynchronize(r.stop);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+            if (e != hipSuccess) st = hip_fail(e, "pds_profile_report");
+            if (!agg.count(r.name)) order.push_back(r.name);
+            Agg& a = agg[r.name];
+            a.count += 1;
+            a.total += ms;
+            a.mn = ms < a.mn ? ms : a.mn;
+            a.mx = ms > a.mx ? ms : a.mx;
+            (void)hipEventDestroy(r.start);
+            (void)hipEventDestroy(r.stop);
+        }
+        pds::g_prof.clear();
+    }
+    std::string out;
+    char line[256];
+    for (auto& nm : order) {
+        const Agg& a = agg[nm];
+        snprintf(line, sizeof(line), "%s %d %.6f %.6f %.6f\n", nm.c_str(), a.count, a.total, a.mn, a.mx);
+        out += line;
+    }
+    if (needed) *needed = out.size() + 1;
+    if (len > 0) {
+        size_t c = out.size() < len - 1 ? out.size() : len - 1;
+        memcpy(buf, out.data(), c);
+        buf[c] = 0;
+    }
+    return st;
 }
 
 const char* pds_last_error(void) { return g_err; }

@@ -9,8 +9,7 @@
 // bits it holds in registers; the remaining bits (spread across lanes) are
 // brought into registers by transposes through LDS, R bits at a time.  The
 // last layout is written to LDS once more and the kept entries are gathered
-// from there.  X is read once, coalesced, and the next sample's row is loaded
-// while the current one is transformed.  Persistent: each wave loops over
+// from there.  X is read once, coalesced; latency is hidden by the many resident waves.  Persistent: each wave loops over
 // samples with a grid-wide stride.
 //
 // Generic path (any p, any alignment): one workgroup per sample, all
@@ -198,9 +197,6 @@ __global__ __launch_bounds__(64) void k_compress_fast(uint64_t seed, int m, cons
     load_row<T, L>(x, X + i * ldx, lane);
 
     for (; i < n; i += stride) {
-        T nx[E];
-        const bool more = (i + stride) < n;
-        if (more) load_row<T, L>(nx, X + (i + stride) * ldx, lane);
 
 #pragma unroll
         for (int ri = 0; ri < E; ++ri) x[ri] = flip_sign<T>(x[ri], (uint32_t)((negmask >> ri) & 1u));
@@ -209,33 +205,33 @@ __global__ __launch_bounds__(64) void k_compress_fast(uint64_t seed, int m, cons
         for (int ph = 0; ph < NPH; ++ph) {
             if (ph > 0) {
                 // transpose: current layout out, next layout in
+                // lane and register parts of an element index have disjoint
+                // bits, so pad(lane | reg) = pad(lane) + pad(reg): one base
+                // register per phase plus compile-time offsets
                 __syncthreads();
-                const int lp_old = Lay::lane_part(ph - 1, lane);
+                T* base_old = buf + lds_pad<T>(Lay::lane_part(ph - 1, lane));
 #pragma unroll
-                for (int ri = 0; ri < E; ++ri) buf[lds_pad<T>(lp_old | Lay::reg_part(ph - 1, ri))] = x[ri];
+                for (int ri = 0; ri < E; ++ri) base_old[lds_pad<T>(Lay::reg_part(ph - 1, ri))] = x[ri];
                 __syncthreads();
-                const int lp_new = Lay::lane_part(ph, lane);
+                const T* base_new = buf + lds_pad<T>(Lay::lane_part(ph, lane));
 #pragma unroll
-                for (int ri = 0; ri < E; ++ri) x[ri] = buf[lds_pad<T>(lp_new | Lay::reg_part(ph, ri))];
+                for (int ri = 0; ri < E; ++ri) x[ri] = base_new[lds_pad<T>(Lay::reg_part(ph, ri))];
             }
             butterflies<E, T>(x, Lay::group_size(ph));
         }
 
         __syncthreads();
         {
-            const int lp = Lay::lane_part(NPH - 1, lane);
+            T* base = buf + lds_pad<T>(Lay::lane_part(NPH - 1, lane));
 #pragma unroll
-            for (int ri = 0; ri < E; ++ri) buf[lds_pad<T>(lp | Lay::reg_part(NPH - 1, ri))] = x[ri] * scale;
+            for (int ri = 0; ri < E; ++ri) base[lds_pad<T>(Lay::reg_part(NPH - 1, ri))] = x[ri] * scale;
         }
+        // the registers are free again: start loading the next row under the gather
+        if (i + stride < n) load_row<T, L>(x, X + (i + stride) * ldx, lane);
         __syncthreads();
         const uint16_t* ix = idx + i * (int64_t)m;
         T* out = vals + i * (int64_t)m;
         for (int t = lane; t < m; t += 64) out[t] = buf[lds_pad<T>((int)ix[t])];
-
-        if (more) {
-#pragma unroll
-            for (int ri = 0; ri < E; ++ri) x[ri] = nx[ri];
-        }
     }
 }
 
@@ -346,8 +342,8 @@ static hipError_t launch_fast(int L, uint64_t seed, int m, const T* X, int64_t n
         }                                                                                                 \
         int64_t grid = (int64_t)dev.cus * per_cu;                                                         \
         if (grid > n) grid = n;                                                                           \
-        hipLaunchKernelGGL((k_compress_fast<T, LL>), dim3((unsigned)grid), dim3(64), 0, s, seed, m, X, n, \
-                           ldx, idx, vals);                                                               \
+        { ProfScope ps_("compress", s); hipLaunchKernelGGL((k_compress_fast<T, LL>), dim3((unsigned)grid), dim3(64), 0, s, seed, m, X, n, \
+                           ldx, idx, vals); }                                                               \
         break;                                                                                            \
     }
         PDS_FAST_CASE(8)
@@ -371,8 +367,11 @@ static hipError_t launch_generic(uint64_t seed, int p, int m, const T* X, int64_
     const size_t sign_bytes = ((size_t)nwords * 4 + 15) & ~(size_t)15;
     const bool use_lds = sign_bytes + (size_t)p * sizeof(T) <= kGenericLdsLimit;
     const size_t lds = generic_lds_bytes(p, sizeof(T));
-    hipLaunchKernelGGL((k_compress_generic<T>), dim3((unsigned)grid), dim3(kGenericThreads), lds, s, seed, p, m, X,
+    {
+        ProfScope ps_("compress", s);
+        hipLaunchKernelGGL((k_compress_generic<T>), dim3((unsigned)grid), dim3(kGenericThreads), lds, s, seed, p, m, X,
                        n, ldx, idx, vals, reinterpret_cast<T*>(ws), use_lds ? 1 : 0);
+    }
     return hipGetLastError();
 }
 

@@ -101,6 +101,7 @@ struct MfmaLds<true> {
     unsigned short alo[kTileMfma * kBfStride];
     unsigned short bhi[kTileMfma * kBfStride];
     unsigned short blo[kTileMfma * kBfStride];
+    double diag[kTileMfma];  // exact sum of squares per coordinate (diagonal tiles)
 };
 template <>
 struct MfmaLds<false> {
@@ -124,38 +125,112 @@ __device__ inline void scatter_entry(MfmaLds<SPLIT>& L, bool to_b, int coord, in
     }
 }
 
-// Scatters (or clears, when clear=true) the chunk's entries of block A (and B
-// when not a diagonal tile).  8 threads per sample, strided over its entries.
-template <bool SPLIT>
-__device__ inline void scatter_chunk(MfmaLds<SPLIT>& L, bool clear, const float* __restrict__ vals,
-                                     const uint16_t* __restrict__ idx, const uint32_t* __restrict__ off, int m,
-                                     int nb, int64_t n, int64_t s0, int ta, int tb, int tw)
+// Per-thread share of one chunk: thread t serves sample slot s = t / 8 and
+// entries e0 + (t % 8) + 8 k, k < kPre, of each of the tile's two blocks
+// (coordinate relative to the block, -1 = none).  Entries beyond 8 kPre per
+// sample and block are rare; they are read and scattered directly.
+constexpr int kPre = 4;
+
+struct ChunkOffsets {
+    uint32_t a0, a1, b0, b1;
+    bool ok;  // the sample belongs to this range (else the offsets are not used)
+};
+// Raw loaded words; the arithmetic on them waits until the scatter so that
+// the loads stay in flight while the matrix cores run.
+struct ChunkEntries {
+    uint16_t ia[kPre], ib[kPre];
+    float va[kPre], vb[kPre];
+    uint32_t valid;  // bit k: a-entry k, bit kPre + k: b-entry k
+};
+
+// Offsets of sample i's blocks (zero when i is outside [.., send)); the load
+// address is always a valid row so no branch guards it.
+__device__ inline ChunkOffsets load_offsets(const uint32_t* __restrict__ off, int nb, int64_t send, int64_t i,
+                                            int64_t i_safe, int ta, int tb)
 {
-    const int t = threadIdx.x;
-    const int s = t >> 3;
-    const int sub = t & 7;
-    const int64_t i = s0 + s;
-    if (i >= n) return;
-    const uint32_t* o = off + i * (nb + 1);
+    const uint32_t* r = off + (i < send ? i : i_safe) * (nb + 1);
+    ChunkOffsets o;
+    o.a0 = r[ta];
+    o.a1 = r[ta + 1];
+    o.b0 = r[tb];
+    o.b1 = r[tb + 1];
+    o.ok = i < send;
+    return o;
+}
+
+__device__ inline ChunkEntries load_entries(const float* __restrict__ vals, const uint16_t* __restrict__ idx, int m,
+                                            int64_t send, int64_t i, int64_t i_safe, const ChunkOffsets& o, int sub,
+                                            bool diag)
+{
+    ChunkEntries c;
+    const int64_t row = (i < send ? i : i_safe) * (int64_t)m;
+    const float* v = vals + row;
+    const uint16_t* ix = idx + row;
+    c.valid = 0;
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        const uint32_t ea = o.a0 + sub + 8 * k;
+        const uint32_t eb = o.b0 + sub + 8 * k;
+        const uint32_t sa = ea < (uint32_t)m ? ea : (uint32_t)(m - 1);
+        const uint32_t sb = eb < (uint32_t)m ? eb : (uint32_t)(m - 1);
+        c.ia[k] = ix[sa];
+        c.va[k] = v[sa];
+        c.ib[k] = ix[sb];
+        c.vb[k] = v[sb];
+        c.valid |= (uint32_t)(o.ok && ea < o.a1) << k;
+        c.valid |= (uint32_t)(o.ok && !diag && eb < o.b1) << (kPre + k);
+    }
+    return c;
+}
+
+// The split products hi*hi + hi*lo + lo*hi drop lo*lo, which biases every
+// diagonal entry low by the mean of lo^2 (about 2.5e-6 relative); diagonal
+// tiles therefore also sum the squares v*v of their entries exactly in FP64
+// and write those sums over the matrix-core diagonal.
+template <bool SPLIT>
+__device__ inline void add_square(MfmaLds<SPLIT>& L, int coord, float v)
+{
+    if constexpr (SPLIT) atomicAdd(&L.diag[coord], (double)v * (double)v);
+}
+
+template <bool SPLIT>
+__device__ inline void put_entries(MfmaLds<SPLIT>& L, const ChunkEntries& c, int s, bool clear, bool diag, int a_base,
+                                   int b_base)
+{
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        if ((c.valid >> k) & 1u) {
+            const int coord = (int)c.ia[k] - a_base;
+            scatter_entry<SPLIT>(L, false, coord, s, clear ? 0.0f : c.va[k]);
+            if (diag && !clear) add_square<SPLIT>(L, coord, c.va[k]);
+        }
+        if ((c.valid >> (kPre + k)) & 1u) scatter_entry<SPLIT>(L, true, (int)c.ib[k] - b_base, s, clear ? 0.0f : c.vb[k]);
+    }
+}
+
+// entries past the register share of a sample (rare): direct loads
+template <bool SPLIT>
+__device__ inline void put_overflow(MfmaLds<SPLIT>& L, const float* __restrict__ vals, const uint16_t* __restrict__ idx,
+                                    int m, int64_t n, int64_t i, const ChunkOffsets& o, int s, int sub, int a_base,
+                                    int b_base, bool diag, bool clear)
+{
+    if (i >= n || !o.ok) return;
     const float* v = vals + i * (int64_t)m;
     const uint16_t* ix = idx + i * (int64_t)m;
-    {
-        const int a0 = ta * tw;
-        const uint32_t e0 = o[ta], e1 = o[ta + 1];
-        for (uint32_t e = e0 + sub; e < e1; e += 8) scatter_entry<SPLIT>(L, false, (int)ix[e] - a0, s, clear ? 0.0f : v[e]);
+    for (uint32_t e = o.a0 + 8 * kPre + sub; e < o.a1; e += 8) {
+        scatter_entry<SPLIT>(L, false, (int)ix[e] - a_base, s, clear ? 0.0f : v[e]);
+        if (diag && !clear) add_square<SPLIT>(L, (int)ix[e] - a_base, v[e]);
     }
-    if (ta != tb) {
-        const int b0 = tb * tw;
-        const uint32_t e0 = o[tb], e1 = o[tb + 1];
-        for (uint32_t e = e0 + sub; e < e1; e += 8) scatter_entry<SPLIT>(L, true, (int)ix[e] - b0, s, clear ? 0.0f : v[e]);
-    }
+    if (!diag)
+        for (uint32_t e = o.b0 + 8 * kPre + sub; e < o.b1; e += 8)
+            scatter_entry<SPLIT>(L, true, (int)ix[e] - b_base, s, clear ? 0.0f : v[e]);
 }
 
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_gram_mfma(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
                                                    const uint32_t* __restrict__ off, int m, int nb, int tw,
                                                    int64_t n, int ntiles, int nsplit, int64_t split_len,
-                                                   float* __restrict__ part)
+                                                   float* __restrict__ part, double* __restrict__ pdiag)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     MfmaLds<SPLIT>& L = *reinterpret_cast<MfmaLds<SPLIT>*>(smem_raw);
@@ -168,11 +243,13 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const float* __restrict__ val
     int ta, tb;
     decode_tile(tile, nb, ta, tb);
     const bool diag = (ta == tb);
+    const int a_base = ta * tw, b_base = tb * tw;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
+    const int s = tid >> 3, sub = tid & 7;
 
     // zero the LDS tiles once
     {
@@ -193,10 +270,38 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const float* __restrict__ val
     int64_t send = sbeg + split_len;
     if (send > n) send = n;
 
+    // pipeline: offsets two chunks ahead, entries one chunk ahead.  Samples at
+    // or past `send` belong to other ranges: their slots are marked empty (the
+    // loads themselves read a valid row of this range and are discarded).
+    const int64_t i_safe = sbeg;
+    ChunkOffsets o_cur = load_offsets(off, nb, send, sbeg + s, i_safe, ta, tb);
+    ChunkEntries e_cur = load_entries(vals, idx, m, send, sbeg + s, i_safe, o_cur, sub, diag);
+    ChunkOffsets o_next = load_offsets(off, nb, send, sbeg + kChunk + s, i_safe, ta, tb);
+    ChunkEntries e_prev;
+    e_prev.valid = 0;
+    ChunkOffsets o_prev{0, 0, 0, 0, false};
+    int64_t i_prev = send;
+
     for (int64_t s0 = sbeg; s0 < send; s0 += kChunk) {
+        const int64_t i_cur = s0 + s;
         __syncthreads();
-        scatter_chunk<SPLIT>(L, false, vals, idx, off, m, nb, n, s0, ta, tb, tw);
+        // clear the previous chunk's slots, then scatter this chunk (the
+        // writers of a sample slot are one wave, so their LDS writes stay ordered)
+        put_entries<SPLIT>(L, e_prev, s, true, diag, a_base, b_base);
+        put_overflow<SPLIT>(L, vals, idx, m, send, i_prev, o_prev, s, sub, a_base, b_base, diag, true);
+        put_entries<SPLIT>(L, e_cur, s, false, diag, a_base, b_base);
+        put_overflow<SPLIT>(L, vals, idx, m, send, i_cur, o_cur, s, sub, a_base, b_base, diag, false);
         __syncthreads();
+        e_prev = e_cur;
+        o_prev = o_cur;
+        i_prev = i_cur;
+        // loads for the next chunks fly while this chunk runs on the matrix cores
+        e_cur = load_entries(vals, idx, m, send, s0 + kChunk + s, i_safe, o_next, sub, diag);
+        o_cur = o_next;
+        o_next = load_offsets(off, nb, send, s0 + 2 * kChunk + s, i_safe, ta, tb);
+        // keep the scheduler from sinking those loads (or their address math)
+        // into the matrix-core block, where their waits would stall it
+        __builtin_amdgcn_sched_barrier(0);
         if constexpr (SPLIT) {
             const unsigned short* bh = diag ? L.ahi : L.bhi;
             const unsigned short* bl = diag ? L.alo : L.blo;
@@ -216,14 +321,23 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const float* __restrict__ val
                     bhv[cb] = *reinterpret_cast<const bf16x8*>(&bh[col * kBfStride + koff]);
                     blv[cb] = *reinterpret_cast<const bf16x8*>(&bl[col * kBfStride + koff]);
                 }
+                // product-outer order: consecutive MFMAs write different
+                // accumulators, so none waits on the one before it
 #pragma unroll
                 for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb) {
+                    for (int cb = 0; cb < 4; ++cb)
                         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], bhv[cb], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
                         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], blv[cb], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
                         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rb], bhv[cb], acc[rb][cb], 0, 0, 0);
-                    }
             }
         } else {
             const float* bsrc = diag ? L.a : L.b;
@@ -242,8 +356,6 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const float* __restrict__ val
                         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
             }
         }
-        __syncthreads();
-        scatter_chunk<SPLIT>(L, true, vals, idx, off, m, nb, n, s0, ta, tb, tw);
     }
 
     // write this range's FP32 tile: part[split][tile][i][j], i, j < tw
@@ -256,8 +368,18 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const float* __restrict__ val
             for (int r = 0; r < 16; ++r) {
                 const int i = wr * 128 + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const int j = wc * 128 + cb * 32 + (lane & 31);
-                if (i < tw && j < tw) out[(int64_t)i * tw + j] = acc[rb][cb][r];
+                if (i < tw && j < tw && !(SPLIT && diag && i == j)) out[(int64_t)i * tw + j] = acc[rb][cb][r];
             }
+    if constexpr (SPLIT) {
+        if (diag) {
+            __syncthreads();
+            double* dout = pdiag + ((int64_t)split * ntiles + tile) * tw;
+            for (int c = tid; c < tw; c += 256) {
+                dout[c] = L.diag[c];
+                out[(int64_t)c * tw + c] = 0.0f;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -342,8 +464,9 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ val
 // finalize: scaling and mirroring of the upper tiles into a full matrix.
 // ---------------------------------------------------------------------------
 template <typename PT>
-__global__ __launch_bounds__(256) void k_gram_reduce(const PT* __restrict__ part, int nsplit, int ntiles, int nb,
-                                                     int tw, int p, double* __restrict__ acc)
+__global__ __launch_bounds__(256) void k_gram_reduce(const PT* __restrict__ part, const double* __restrict__ pdiag,
+                                                     int nsplit, int ntiles, int nb, int tw, int p,
+                                                     double* __restrict__ acc)
 {
     const int64_t per_tile = (int64_t)tw * tw;
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -355,6 +478,8 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const PT* __restrict__ part
     decode_tile(tile, nb, ta, tb);
     double sum = 0.0;
     for (int s = 0; s < nsplit; ++s) sum += (double)part[((int64_t)s * ntiles + tile) * per_tile + e];
+    if (pdiag && ta == tb && i == j)
+        for (int s = 0; s < nsplit; ++s) sum += pdiag[((int64_t)s * ntiles + tile) * tw + i];
     acc[(int64_t)(ta * tw + i) * p + (tb * tw + j)] += sum;
 }
 
@@ -377,7 +502,7 @@ __global__ __launch_bounds__(256) void k_cov_finalize(const double* __restrict__
 struct GramPlan {
     int tw, nb, ntiles, nsplit;
     int64_t split_len;
-    size_t off_bytes, part_bytes;
+    size_t off_bytes, part_bytes, diag_bytes;
 };
 
 static GramPlan gram_plan(int prec, int p, int64_t n, const DeviceInfo& dev)
@@ -399,7 +524,8 @@ static GramPlan gram_plan(int prec, int p, int64_t n, const DeviceInfo& dev)
     if (g.nsplit < 1) g.nsplit = 1;
     g.off_bytes = (((size_t)(n > 0 ? n : 0) * (g.nb + 1) * 4) + 255) & ~(size_t)255;
     const size_t pe = (prec == 0) ? sizeof(double) : sizeof(float);
-    g.part_bytes = (size_t)g.nsplit * g.ntiles * (size_t)g.tw * g.tw * pe;
+    g.part_bytes = (((size_t)g.nsplit * g.ntiles * (size_t)g.tw * g.tw * pe) + 255) & ~(size_t)255;
+    g.diag_bytes = (prec == 2) ? (size_t)g.nsplit * g.ntiles * (size_t)g.tw * sizeof(double) : 0;
     return g;
 }
 
@@ -408,7 +534,7 @@ size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo&
     (void)m;
     if (n <= 0) return 0;
     GramPlan g = gram_plan(prec, p, n, dev);
-    return g.off_bytes + g.part_bytes;
+    return g.off_bytes + g.part_bytes + g.diag_bytes;
 }
 
 hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n,
@@ -420,10 +546,15 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
     GramPlan g = gram_plan(prec, p, n, dev);
     uint32_t* off = reinterpret_cast<uint32_t*>(ws);
     void* part = reinterpret_cast<unsigned char*>(ws) + g.off_bytes;
+    double* pdiag = (prec == 2) ? reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(ws) + g.off_bytes + g.part_bytes)
+                                : nullptr;
     {
         const int64_t threads = n * (int64_t)(g.nb + 1);
+        {
+        ProfScope ps_("block_offsets", s);
         hipLaunchKernelGGL(k_block_offsets, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, idx, n, m, g.tw,
                            g.nb, off);
+    }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -438,26 +569,42 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
         attr_set = true;
     }
     if (prec == 0) {
+        {
+        ProfScope ps_("gram_f64", s);
         hipLaunchKernelGGL(k_gram_f64, dim3((unsigned)grid), dim3(256), 0, s, reinterpret_cast<const double*>(vals),
                            idx, off, m, g.nb, g.tw, n, g.ntiles, g.nsplit, g.split_len, reinterpret_cast<double*>(part));
+    }
     } else if (prec == 2) {
+        {
+        ProfScope ps_("gram_bf16x3", s);
         hipLaunchKernelGGL(k_gram_mfma<true>, dim3((unsigned)grid), dim3(256), sizeof(MfmaLds<true>), s,
                            reinterpret_cast<const float*>(vals), idx, off, m, g.nb, g.tw, n, g.ntiles, g.nsplit,
-                           g.split_len, reinterpret_cast<float*>(part));
+                           g.split_len, reinterpret_cast<float*>(part), pdiag);
+    }
     } else {
+        {
+        ProfScope ps_("gram_f32", s);
         hipLaunchKernelGGL(k_gram_mfma<false>, dim3((unsigned)grid), dim3(256), sizeof(MfmaLds<false>), s,
                            reinterpret_cast<const float*>(vals), idx, off, m, g.nb, g.tw, n, g.ntiles, g.nsplit,
-                           g.split_len, reinterpret_cast<float*>(part));
+                           g.split_len, reinterpret_cast<float*>(part), pdiag);
+    }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nred = (int64_t)g.ntiles * g.tw * g.tw;
     if (prec == 0)
+        {
+        ProfScope ps_("gram_reduce", s);
         hipLaunchKernelGGL(k_gram_reduce<double>, dim3((unsigned)((nred + 255) / 256)), dim3(256), 0, s,
-                           reinterpret_cast<const double*>(part), g.nsplit, g.ntiles, g.nb, g.tw, p, acc);
+                           reinterpret_cast<const double*>(part), (const double*)nullptr, g.nsplit, g.ntiles, g.nb,
+                           g.tw, p, acc);
+    }
     else
+        {
+        ProfScope ps_("gram_reduce", s);
         hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)((nred + 255) / 256)), dim3(256), 0, s,
-                           reinterpret_cast<const float*>(part), g.nsplit, g.ntiles, g.nb, g.tw, p, acc);
+                           reinterpret_cast<const float*>(part), pdiag, g.nsplit, g.ntiles, g.nb, g.tw, p, acc);
+    }
     return hipGetLastError();
 }
 
@@ -468,8 +615,11 @@ hipError_t launch_covariance_finalize(int prec, int p, int m, int64_t n_total, c
     const double sdiag = (double)p / ((double)m * (double)n_total);
     const double soff = ((double)p * (double)(p - 1)) / ((double)m * (double)(m - 1) * (double)n_total);
     const int64_t tot = (int64_t)p * p;
-    hipLaunchKernelGGL(k_cov_finalize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, acc, p, sdiag, soff,
+    {
+        ProfScope ps_("cov_finalize", s);
+        hipLaunchKernelGGL(k_cov_finalize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, acc, p, sdiag, soff,
                        C);
+    }
     return hipGetLastError();
 }
 

@@ -318,16 +318,25 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
     uint32_t* gcnt = reinterpret_cast<uint32_t*>(w);
     const int64_t KP = (int64_t)K * p;
     if (k.global) {
+        {
+        ProfScope ps_("kmeans_prep", s);
         hipLaunchKernelGGL(k_kmeans_prep_global<T>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, cin, K, p,
                            cT, gsum, gcnt);
+    }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        {
+        ProfScope ps_("kmeans_assign", s);
         hipLaunchKernelGGL((k_kmeans_assign<T, true>), dim3(k.nwg), dim3(kKmThreads), 0, s, vals, idx, n, m, p, K,
                            cin, cT, k.per_wg, assign, psum, pcnt, gsum, gcnt, pobj);
+    }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        {
+        ProfScope ps_("kmeans_update", s);
         hipLaunchKernelGGL(k_kmeans_update<double>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, gsum, gcnt, 1,
                            KP, cin, cout, pobj, k.nwg, objective);
+    }
         return hipGetLastError();
     }
     static bool attr_set[2] = {false, false};
@@ -336,13 +345,19 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kKmLdsMax);
         attr_set[sizeof(T) == 8] = true;
     }
-    hipLaunchKernelGGL((k_kmeans_assign<T, false>), dim3(k.nwg), dim3(kKmThreads), k.lds, s, vals, idx, n, m, p, K,
+    {
+        ProfScope ps_("kmeans_assign", s);
+        hipLaunchKernelGGL((k_kmeans_assign<T, false>), dim3(k.nwg), dim3(kKmThreads), k.lds, s, vals, idx, n, m, p, K,
                        cin, (const T*)nullptr, k.per_wg, assign, psum, pcnt, (double*)nullptr, (uint32_t*)nullptr,
                        pobj);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_kmeans_update<S>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, psum, pcnt, k.nwg, KP,
+    {
+        ProfScope ps_("kmeans_update", s);
+        hipLaunchKernelGGL(k_kmeans_update<S>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, psum, pcnt, k.nwg, KP,
                        cin, cout, pobj, k.nwg, objective);
+    }
     return hipGetLastError();
 }
 
@@ -403,7 +418,10 @@ __global__ __launch_bounds__(256) void k_unmix(uint64_t seed, int p, const doubl
 hipError_t launch_unmix(uint64_t seed, int p, const double* cpre, int K, double* cout, hipStream_t s)
 {
     if (K <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_unmix, dim3(K), dim3(256), 0, s, seed, p, cpre, cout);
+    {
+        ProfScope ps_("unmix", s);
+        hipLaunchKernelGGL(k_unmix, dim3(K), dim3(256), 0, s, seed, p, cpre, cout);
+    }
     return hipGetLastError();
 }
 

@@ -84,6 +84,22 @@ struct WordStream {
         block = 0;
         pos = 8;
     }
+    // position the stream at 32-bit word index widx
+    __device__ inline void seek(uint64_t widx)
+    {
+        block = widx >> 3;
+        pos = 8;
+        const int skip = (int)(widx & 7);
+        if (skip) {
+            u64x4 b = philox_block(block, sample, 0, 0, seed, 0);
+            buf[0] = b.w[0];
+            buf[1] = b.w[1];
+            buf[2] = b.w[2];
+            buf[3] = b.w[3];
+            ++block;
+            pos = skip;
+        }
+    }
     __device__ inline uint32_t next()
     {
         if (pos == 8) {

@@ -15,6 +15,18 @@ struct DeviceInfo {
 
 hipError_t device_info(DeviceInfo& info);
 
+// Optional per-kernel event timing (pds_profile_enable).  Construct right
+// before a launch and destroy right after it, on the launch stream.
+class ProfScope {
+public:
+    ProfScope(const char* name, hipStream_t s);
+    ~ProfScope();
+
+private:
+    int slot_;
+    hipStream_t s_;
+};
+
 // ---- compression --------------------------------------------------------
 // Kept coordinates (ascending) of samples i0 .. i0+n-1 into idx (n x m).
 hipError_t launch_sample_indices(uint64_t seed, int p, int m, int64_t n, uint64_t i0, uint16_t* idx,

@@ -74,6 +74,20 @@ def test_compress_matches_oracle(p, m, n, prec):
     assert nerr(vals.cpu().numpy().astype(np.float64), v_o) <= vtol
 
 
+def test_sampler_rejection_path_bit_exact():
+    """p = 65536, m = 32768: about one sample in five needs an extra word after
+    a Lemire rejection; those rows still match the oracle bit for bit."""
+    p, m, n = 65536, 32768, 20
+    assert sum(ref.sample_words_used(0, i, p, m) > m for i in range(n)) >= 2
+    X = np.random.default_rng(0).standard_normal((n, p)).astype(np.float32)
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F32)
+    vals, idx = pds.compress(plan, to_dev(X))
+    torch.cuda.synchronize()
+    v_o, i_o = ref.compress(X, 0, m)
+    assert np.array_equal(u16(idx), i_o)
+    assert nerr(vals.cpu().numpy().astype(np.float64), v_o) <= 1e-6
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_compress_chunked_equals_one_shot(prec):
     pr, dt, _, _ = PRECS[prec]

@@ -101,6 +101,16 @@ def test_sampler_matches_literal_oracle():
         assert ref.sample_indices(seed, i, p, m).tolist() == oracle_def.kept_set(seed, i, p, m)
 
 
+def test_sampler_rejection_path_matches_literal_oracle():
+    """Samples whose draws hit a Lemire rejection (one extra word) still equal
+    the literal sampler, which re-draws from numpy's Philox stream."""
+    p, m = 65536, 32768
+    hits = [i for i in range(20) if ref.sample_words_used(0, i, p, m) > m]
+    assert len(hits) >= 2
+    for i in hits[:2]:
+        assert ref.sample_indices(0, i, p, m).tolist() == oracle_def.kept_set(0, i, p, m)
+
+
 def test_sampler_inclusion_frequencies():
     """Lemma (App. B): each coordinate is kept with probability m/p; Thm. (App.
     B): each pair with probability m(m-1)/(p(p-1)).  Chi-square at p=32, m=8."""
