@@ -525,3 +525,60 @@ void orc_sample_batch(uint64_t seed, uint64_t i0, int64_t n, int64_t p, int64_t 
 #pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < n; ++r) orc_sample_indices(seed, i0 + (uint64_t)r, p, m, idx + r * m);
 }
+
+/* Principal submatrix G[J][J] of G = sum_i w_i w_i^T straight from the
+ * definitions, for spot checks at sizes where the whole Gram is out of reach:
+ * for every sample, its kept set (the sampler above) and, for each coordinate
+ * of J that it keeps, y_ij = row j of H times D x_i (no fast transform).
+ * X is float, row-major n x p (ld ldx); sample i0 + r is row r.
+ * Gsub is nJ x nJ, added into.                                             */
+void orc_gram_submatrix_f32(uint64_t seed, int64_t p, int64_t m, const float* X, int64_t n, int64_t ldx, uint64_t i0,
+                            const int64_t* J, int64_t nJ, double* Gsub, int nthreads)
+{
+    int8_t* D = (int8_t*)malloc((size_t)p);
+    orc_signs(seed, p, D);
+    int64_t* slot = (int64_t*)malloc(sizeof(int64_t) * (size_t)p);
+    for (int64_t j = 0; j < p; ++j) slot[j] = -1;
+    for (int64_t a = 0; a < nJ; ++a) slot[J[a]] = a;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    int T = omp_get_max_threads();
+#else
+    (void)nthreads;
+    int T = 1;
+#endif
+    double* part = (double*)calloc((size_t)T * (size_t)(nJ * nJ), sizeof(double));
+#pragma omp parallel num_threads(T)
+    {
+#ifdef _OPENMP
+        int t = omp_get_thread_num();
+#else
+        int t = 0;
+#endif
+        double* Gt = part + (size_t)t * (size_t)(nJ * nJ);
+        uint16_t* ix = (uint16_t*)malloc(sizeof(uint16_t) * (size_t)m);
+        int64_t* hit = (int64_t*)malloc(sizeof(int64_t) * (size_t)nJ);
+        double* yv = (double*)malloc(sizeof(double) * (size_t)nJ);
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < n; ++r) {
+            orc_sample_indices(seed, i0 + (uint64_t)r, p, m, ix);
+            int64_t h = 0;
+            for (int64_t k = 0; k < m; ++k)
+                if (slot[ix[k]] >= 0) {
+                    hit[h] = slot[ix[k]];
+                    yv[h] = y_entry_from(D, p, ix[k], NULL, X + r * ldx);
+                    ++h;
+                }
+            for (int64_t a = 0; a < h; ++a)
+                for (int64_t b = 0; b < h; ++b) Gt[hit[a] * nJ + hit[b]] += yv[a] * yv[b];
+        }
+        free(ix);
+        free(hit);
+        free(yv);
+    }
+    for (int t = 0; t < T; ++t)
+        for (int64_t e = 0; e < nJ * nJ; ++e) Gsub[e] += part[(size_t)t * (size_t)(nJ * nJ) + e];
+    free(part);
+    free(slot);
+    free(D);
+}

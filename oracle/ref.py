@@ -73,6 +73,7 @@ def lib():
         L.orc_max_threads.restype = i32
         L.orc_sample_batch.argtypes = [u64, u64, i64, i64, i64, P, i32]
         L.orc_sample_words_used.argtypes = [u64, u64, i64, i64]
+        L.orc_gram_submatrix_f32.argtypes = [u64, i64, i64, P, i64, i64, u64, P, i64, P, i32]
         L.orc_sample_words_used.restype = i64
         _lib = L
     return _lib
@@ -170,6 +171,16 @@ def gram_accumulate(p: int, vals, idx, G=None, nthreads: int = 0):
     if G is None:
         G = np.zeros((p, p), dtype=np.float64)
     lib().orc_gram_accumulate(p, m, _ptr(vals), _ptr(idx), n, _ptr(G), nthreads)
+    return G
+
+
+def gram_submatrix(seed: int, m: int, X, J, i0: int = 0, nthreads: int = 0):
+    """G[J][J] from the definitions (explicit Hadamard rows, kept sets); X float32."""
+    Xc = np.ascontiguousarray(X, dtype=np.float32)
+    n, p = Xc.shape
+    Jc = np.ascontiguousarray(J, dtype=np.int64)
+    G = np.zeros((len(Jc), len(Jc)), dtype=np.float64)
+    lib().orc_gram_submatrix_f32(seed, p, m, _ptr(Xc), n, p, i0, _ptr(Jc), len(Jc), _ptr(G), nthreads)
     return G
 
 

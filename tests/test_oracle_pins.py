@@ -470,3 +470,16 @@ def test_table1_preconditioning_helps_pca():
         assert np.mean(with_p) > np.mean(without_p), (gamma, with_p, without_p)
         means[gamma] = np.mean(with_p)
     assert means[0.3] > means[0.1]
+
+
+def test_gram_submatrix_from_definitions_matches_fast_path():
+    """The definition-based principal submatrix (explicit Hadamard rows, used for
+    spot checks at full size) equals the corresponding block of the Gram built
+    from the fast transform."""
+    p, m, n = 1024, 51, 500
+    X = np.random.default_rng(7).standard_normal((n, p)).astype(np.float32)
+    vals, idx = ref.compress(X, 5, m)
+    G = ref.gram_accumulate(p, vals, idx)
+    J = np.array([0, 3, 64, 511, 512, 1023])
+    Gs = ref.gram_submatrix(5, m, X, J)
+    assert np.max(np.abs(Gs - G[np.ix_(J, J)])) <= 1e-12 * np.max(np.abs(G))
