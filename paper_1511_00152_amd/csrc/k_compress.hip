@@ -392,6 +392,7 @@ hipError_t launch_compress(int prec, uint64_t seed, int p, int m, const void* X,
     }
     const float* Xf = reinterpret_cast<const float*>(X);
     float* vf = reinterpret_cast<float*>(vals);
+    if (prec == 2 && kron_transform_ok(p, X, ldx)) return launch_compress_kron(seed, m, Xf, n, ldx, idx, vf, dev, s);
     if (fast_path_ok(p, X, ldx, sizeof(float))) return launch_fast<float>(L, seed, m, Xf, n, ldx, idx, vf, dev, s);
     return launch_generic<float>(seed, p, m, Xf, n, ldx, idx, vf, ws, dev, s);
 }

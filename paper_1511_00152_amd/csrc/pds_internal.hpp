@@ -38,6 +38,10 @@ hipError_t launch_compress(int prec, uint64_t seed, int p, int m, const void* X,
                            const uint16_t* idx, void* vals, void* ws, size_t ws_bytes, const DeviceInfo& dev,
                            hipStream_t s);
 size_t compress_workspace(int prec, int p, int64_t n, const DeviceInfo& dev);
+// split-BF16 matrix-core transform (p = 4096)
+bool kron_transform_ok(int p, const void* X, int64_t ldx);
+hipError_t launch_compress_kron(uint64_t seed, int m, const float* X, int64_t n, int64_t ldx, const uint16_t* idx,
+                                float* vals, const DeviceInfo& dev, hipStream_t s);
 
 // ---- covariance -----------------------------------------------------------
 size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo& dev);
