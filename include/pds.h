@@ -159,6 +159,177 @@ pds_status pds_kmeans_step(pds_plan plan, const void* vals, const uint16_t* idx,
  * Errors: PDS_E_ARG (null pointers, K < 1). */
 pds_status pds_unmix(pds_plan plan, const double* centers_pre, int32_t K, double* centers_out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned m-selector.  Not part of the paper's method: a small model that
+ * chooses m for a data block so that the covariance estimator of Sec. V meets
+ * a relative Frobenius error target, trained on labels the method itself
+ * defines.  All calls below are asynchronous on `stream`, validate on the host
+ * first and return PDS_E_ARG on null pointers or out-of-range sizes.
+ * ------------------------------------------------------------------------- */
+
+/* Per-row moments (FP64): out[3r] = sum_j X[r][j]^2, out[3r+1] = sum_j
+ * X[r][j]^4, out[3r+2] = max_j X[r][j]^2.  X: device float, n x p, leading
+ * dimension ldx >= p; out: device, n x 3 doubles.  p >= 1. */
+pds_status pds_row_moments(const float* X, int64_t n, int64_t p, int64_t ldx, double* out, void* stream);
+
+/* Frobenius distance, FP64 with a fixed summation order: out2[0] =
+ * sum_e (A[e] - B[e])^2, out2[1] = sum_e B[e]^2 over len >= 1 doubles.
+ * A, B, out2: device.  ws: device, >= PDS_FROB_WS_BYTES bytes.  A may equal B. */
+#define PDS_FROB_WS_BYTES 4096
+pds_status pds_frob_diff(const double* A, const double* B, int64_t len, double* out2, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Device workspace bytes for pds_msel_label on n rows or pds_msel_features
+ * with nsub = n rows.  The plan must keep every coordinate (m = p) and be
+ * PDS_F32: with m = p the compression is the exact transform y = H D x and the
+ * estimator of Sec. V is exactly C_emp (Sec. V setup).  Host-only. */
+pds_status pds_msel_workspace_size(pds_plan plan, int64_t n, size_t* bytes);
+
+/* Training label of a block X (device float, n x p, ldx >= p, n >= 2): the
+ * smallest m in [2, p] whose expected squared relative Frobenius error
+ *   E||C_n - C_emp||_F^2 / ||C_emp||_F^2
+ *     = [(1/q2 - 1) sum_i (||y_i||^4 - sum_j y_ij^4) + (1/q1 - 1) sum_ij y_ij^4]
+ *       / (n^2 ||C_emp||_F^2),      q1 = m/p, q2 = m(m-1)/(p(p-1)),
+ * is at most target^2, with y_i = H D x_i under the plan's D.  The inclusion
+ * probabilities are those of Lemma B and Thm. B; the expectation is over the
+ * sampling only, the data and D being fixed.  m_out: device, one int32.
+ * C_out: NULL, or device p x p doubles receiving C_emp.  A block with
+ * C_emp = 0 gets m = 2.  target > 0.  Errors: PDS_E_M (plan m != p),
+ * PDS_E_ARG, PDS_E_WORKSPACE. */
+pds_status pds_msel_label(pds_plan plan, const float* X, int64_t n, int64_t ldx, double target, int32_t* m_out,
+                          double* C_out, void* ws, size_t ws_bytes, void* stream);
+
+/* The 32 features of a block of n rows computed from its first nsub rows
+ * (2 <= nsub <= min(n, 1024)), written to feats (device, 32 floats):
+ *   0       log mean ||x||^2
+ *   1..8    quantiles of ||x_i||^2 / mean ||x||^2
+ *   9..16   quantiles of log(p max_j x_ij^2 / ||x_i||^2)   (coherence, Sec. III)
+ *   17..24  quantiles of log(p max_j y_ij^2 / ||y_i||^2)   (after H D)
+ *   25      log mean_i p sum_j y_ij^4 / ||y_i||^4
+ *   26      log mean_i p sum_j x_ij^4 / ||x_i||^4
+ *   27      log(U / (mean ||y||^2)^2), U = (nsub^2 ||C_sub||_F^2 - sum_i ||y_i||^4)
+ *           / (nsub (nsub - 1)), C_sub = (1/nsub) sum_i y_i y_i^T
+ *   28      log(||C_sub||_F^2 / (mean ||y||^2)^2)
+ *   29, 30  log n, log p
+ *   31      log(m'/p), m' = the label rule of pds_msel_label evaluated with the
+ *           subset's moments scaled to n rows and ||C_emp||_F^2 predicted as
+ *           (mean ||y||^4 + (n - 1) U) / n
+ * Quantile levels are 0.05 0.15 0.3 0.5 0.7 0.85 0.95 1; level q takes sorted
+ * entry floor(q (nsub - 1)).  A zero row counts as ratio 1 (log 0).
+ * Errors: PDS_E_M (plan m != p), PDS_E_ARG, PDS_E_WORKSPACE. */
+pds_status pds_msel_features(pds_plan plan, const float* X, int64_t n, int64_t ldx, int64_t nsub, double target,
+                             float* feats, void* ws, size_t ws_bytes, void* stream);
+
+/* The selector's network: 32 -> 64 -> 64 -> 1, ReLU hidden layers, inputs
+ * standardized as (f - mu) / sd, output log(gamma).  Parameters are packed
+ * FP32: W1[64][32], b1[64], W2[64][64], b2[64], W3[64], b3 (row-major,
+ * W[out][in]); pds_mlp_param_count() of them. */
+int32_t pds_mlp_param_count(void);
+
+/* Forward pass in FP32 for B >= 1 rows of feats (device, B x 32): pred
+ * (device, B floats) = network output; acts (device, B x 160 floats) keeps
+ * the standardized input and both hidden layers for pds_mlp_backward.
+ * params, mu, sd: device (mu, sd: 32 floats each). */
+pds_status pds_mlp_forward(const float* params, const float* feats, const float* mu, const float* sd, int64_t B,
+                           float* acts, float* pred, void* stream);
+
+/* Gradient of the expectile loss L = (1/B) sum_b |tau - [r_b < 0]| r_b^2,
+ * r_b = target_b - pred_b, with respect to the parameters (device,
+ * pds_mlp_param_count() floats, summed over the batch in a fixed order) and
+ * the loss itself (device, 1 float).  acts and pred come from pds_mlp_forward
+ * with the same params.  ws: device, >= B x 130 floats.  0 < tau < 1. */
+pds_status pds_mlp_backward(const float* params, const float* acts, const float* pred, const float* target, int64_t B,
+                            float tau, float* ws, size_t ws_bytes, float* grad, float* loss, void* stream);
+
+/* One Adam update (Kingma & Ba, ICLR 2015) of every parameter, FP32:
+ * m1 = b1 m1 + (1 - b1) g, m2 = b2 m2 + (1 - b2) g^2,
+ * params -= lr (m1 / (1 - b1^step)) / (sqrt(m2 / (1 - b2^step)) + eps).
+ * step >= 1 counts updates; m1, m2 start at zero.  All device. */
+pds_status pds_mlp_adam(float* params, const float* grad, float* m1, float* m2, int32_t step, float lr, float beta1,
+                        float beta2, float eps, void* stream);
+
+/* BF16 copy of the parameters (round to nearest even), device -> device. */
+pds_status pds_mlp_pack_bf16(const float* params, uint16_t* params_bf16, void* stream);
+
+/* Inference with BF16 parameters: standardized inputs and the first hidden
+ * layer rounded to BF16, FP32 accumulation; gamma[b] = clamp(exp(output),
+ * gamma_min, gamma_max), or gamma_fallback (then clamped) when a feature or
+ * the output is not finite.  feats: device B x 32; gamma: device B floats.
+ * 0 < gamma_min <= gamma_max. */
+pds_status pds_msel_predict(const uint16_t* params_bf16, const float* feats, const float* mu, const float* sd,
+                            int64_t B, float gamma_min, float gamma_max, float gamma_fallback, float* gamma,
+                            void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent data sets, each with its own p, m, K and
+ * seed, compressed in one persistent launch and clustered by T rounds of
+ * sparsified K-means (Sec. VI; Alg. 1) replayed from one captured HIP graph.
+ * Results equal what the single-set calls produce for each set: the same kept
+ * sets (a set's kept sets and D depend on (seed, sample, p, m) only), values
+ * within FP32 rounding, assignments the FP64 argmin.  FP32 data only.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    const float* X;       /* device, n x p row-major, leading dimension ldx >= p; for p >= 256
+                             X and ldx * 4 must be multiples of 16 bytes */
+    int64_t n;            /* samples, >= 0 */
+    int64_t ldx;
+    int32_t p;            /* power of two in [128, 2048] */
+    int32_t m;            /* kept coordinates, 1 <= m <= p */
+    int32_t K;            /* clusters, 1 <= K <= 1024 */
+    int32_t reserved;     /* must be 0 */
+    uint64_t seed;        /* as pds_plan_create's seed */
+    float* vals;          /* device, n x m: compressed values (output) */
+    uint16_t* idx;        /* device, n x m: kept coordinates, ascending (output) */
+    double* centers;      /* device, K x p: initial centers in the preconditioned domain on entry to
+                             pds_batch_kmeans, the centers after T rounds on return */
+    double* centers_alt;  /* device, K x p: scratch */
+    int32_t* assign;      /* device, n: assignments of the last round (output) */
+    double* objective;    /* device, T doubles: J' of each round (output) */
+} pds_batch_desc;
+
+typedef struct pds_batch_s* pds_batch;
+
+/* Creates a batch over count >= 1 descriptors (host array, copied) with T >= 0
+ * K-means rounds.  Host-only.  Errors: PDS_E_ARG (a descriptor's pointers,
+ * sizes or alignment), PDS_E_UNSUPPORTED (p), PDS_E_M (m). */
+pds_status pds_batch_create(pds_batch* out, const pds_batch_desc* descs, int32_t count, int32_t T);
+pds_status pds_batch_destroy(pds_batch b);
+
+/* Device workspace bytes the batch needs (descriptor and work tables,
+ * transposed FP32 centers, per-chunk partial sums).  Host-only. */
+pds_status pds_batch_workspace_size(pds_batch b, size_t* bytes);
+
+/* Binds a workspace (device, >= pds_batch_workspace_size bytes, owned by the
+ * caller and kept alive and unmodified while the batch is used): uploads the
+ * tables on `stream` and captures the T K-means rounds into a graph.
+ * Errors: PDS_E_WORKSPACE, PDS_E_HIP. */
+pds_status pds_batch_bind(pds_batch b, void* ws, size_t ws_bytes, void* stream);
+
+/* Compression of every set (Alg. 1, first loop; as pds_compress with i0 = 0)
+ * in one persistent launch. */
+pds_status pds_batch_compress(pds_batch b, void* stream);
+
+/* Seeds each set's centers with its first K compressed samples, zero-filled
+ * (center k = w_k for k < n, zero beyond).  A simple seeding, not K-means++. */
+pds_status pds_batch_init_centers(pds_batch b, void* stream);
+
+/* T rounds of sparsified K-means on every set (as T calls of pds_kmeans_step
+ * alternating between centers and centers_alt, the last writing centers):
+ * one graph launch.  Needs pds_batch_compress first. */
+pds_status pds_batch_kmeans(pds_batch b, void* stream);
+
+/* Times candidate launch shapes (samples per compression group, samples per
+ * assignment item and per accumulation chunk) on the bound data and keeps the
+ * fastest; re-captures the graph.  Runs the compression and one K-means round
+ * per candidate, so it overwrites vals and idx (with the same values),
+ * centers_alt, assign and objective[0]; call it after pds_batch_compress and
+ * with initial centers in place.  Synchronizes `stream`. */
+pds_status pds_batch_autotune(pds_batch b, void* stream);
+
+/* Text summary: sets, samples, work items, chosen shapes, kernel launches per
+ * pds_batch_kmeans (writes a NUL-terminated line into buf, len bytes). */
+pds_status pds_batch_info(pds_batch b, char* buf, size_t len);
+
 /* Measurement hooks (not part of the method).  pds_profile_enable(1) clears
  * any previous records and starts bracketing every kernel the library launches
  * with a pair of HIP events on the launch stream; pds_profile_enable(0) stops

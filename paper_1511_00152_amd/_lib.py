@@ -30,7 +30,22 @@ EXPORTS = (
     "pds_plan_create", "pds_plan_destroy", "pds_signs", "pds_workspace_size", "pds_covariance_acc_size",
     "pds_compress", "pds_covariance", "pds_kmeans_step", "pds_unmix", "pds_profile_enable", "pds_profile_report",
     "pds_last_error", "pds_version",
+    "pds_row_moments", "pds_frob_diff", "pds_msel_workspace_size", "pds_msel_label", "pds_msel_features",
+    "pds_mlp_param_count", "pds_mlp_forward", "pds_mlp_backward", "pds_mlp_adam", "pds_mlp_pack_bf16",
+    "pds_msel_predict",
+    "pds_batch_create", "pds_batch_destroy", "pds_batch_workspace_size", "pds_batch_bind", "pds_batch_compress",
+    "pds_batch_init_centers", "pds_batch_kmeans", "pds_batch_autotune", "pds_batch_info",
 )
+
+
+class PdsBatchDesc(ctypes.Structure):
+    """pds_batch_desc (include/pds.h)."""
+    _fields_ = [("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("ldx", ctypes.c_int64), ("p", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("K", ctypes.c_int32), ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("vals", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("centers", ctypes.c_void_p),
+                ("centers_alt", ctypes.c_void_p), ("assign", ctypes.c_void_p), ("objective", ctypes.c_void_p)]
+
+PDS_FROB_WS_BYTES = 4096
 
 
 class PdsError(RuntimeError):
@@ -67,6 +82,28 @@ def lib():
     L.pds_unmix.argtypes = [P, P, i32, P, P]
     L.pds_profile_enable.argtypes = [i32]
     L.pds_profile_report.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+    f32 = ctypes.c_float
+    f64 = ctypes.c_double
+    L.pds_row_moments.argtypes = [P, i64, i64, i64, P, P]
+    L.pds_frob_diff.argtypes = [P, P, i64, P, P, sz, P]
+    L.pds_msel_workspace_size.argtypes = [P, i64, ctypes.POINTER(sz)]
+    L.pds_msel_label.argtypes = [P, P, i64, i64, f64, P, P, P, sz, P]
+    L.pds_msel_features.argtypes = [P, P, i64, i64, i64, f64, P, P, sz, P]
+    L.pds_mlp_param_count.argtypes = []
+    L.pds_mlp_forward.argtypes = [P, P, P, P, i64, P, P, P]
+    L.pds_mlp_backward.argtypes = [P, P, P, P, i64, f32, P, sz, P, P, P]
+    L.pds_mlp_adam.argtypes = [P, P, P, P, i32, f32, f32, f32, f32, P]
+    L.pds_mlp_pack_bf16.argtypes = [P, P, P]
+    L.pds_msel_predict.argtypes = [P, P, P, P, i64, f32, f32, f32, P, P]
+    L.pds_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(PdsBatchDesc), i32, i32]
+    L.pds_batch_destroy.argtypes = [P]
+    L.pds_batch_workspace_size.argtypes = [P, ctypes.POINTER(sz)]
+    L.pds_batch_bind.argtypes = [P, P, sz, P]
+    L.pds_batch_compress.argtypes = [P, P]
+    L.pds_batch_init_centers.argtypes = [P, P]
+    L.pds_batch_kmeans.argtypes = [P, P]
+    L.pds_batch_autotune.argtypes = [P, P]
+    L.pds_batch_info.argtypes = [P, ctypes.c_char_p, sz]
     L.pds_last_error.restype = ctypes.c_char_p
     L.pds_version.restype = ctypes.c_char_p
     for name in EXPORTS:

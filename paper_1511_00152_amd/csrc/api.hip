@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/pds.h"
+#include "pds_batch.hpp"
 #include "pds_device.hpp"
 #include "pds_internal.hpp"
 
@@ -21,6 +22,22 @@ struct pds_plan_s {
     int64_t m;
     uint64_t seed;
     int32_t prec;
+};
+
+struct pds_batch_s {
+    std::vector<pds_batch_desc> descs;
+    int T = 0;
+    int pmax = 0;
+    pds::BatchTuning tune{};
+    size_t ws_bytes = 0;
+    // bound state
+    unsigned char* ws = nullptr;
+    std::vector<unsigned char> host_tables;  // staging copy, alive while uploads may be in flight
+    pds::BatchTables tables{};
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int kernels_per_kmeans = 0;
 };
 
 namespace {
@@ -286,6 +303,637 @@ pds_status pds_unmix(pds_plan plan, const double* centers_pre, int32_t K, double
     hipError_t e = pds::launch_unmix(plan->seed, (int)plan->p, centers_pre, K, centers_out,
                                      reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "unmix");
+    return PDS_OK;
+}
+
+// ---- learned m-selector ------------------------------------------------------
+
+pds_status pds_row_moments(const float* X, int64_t n, int64_t p, int64_t ldx, double* out, void* stream)
+{
+    if (n < 0 || p < 1 || p > (1 << 30)) return fail(PDS_E_ARG, "row_moments: n = %lld, p = %lld", (long long)n, (long long)p);
+    if (ldx < p) return fail(PDS_E_ARG, "ldx = %lld < p = %lld", (long long)ldx, (long long)p);
+    if (n == 0) return PDS_OK;
+    if (!X || !out) return fail(PDS_E_ARG, "X and out must be non-NULL");
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e == hipSuccess) e = pds::launch_row_moments(X, n, (int)p, ldx, out, dev, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "row_moments");
+    return PDS_OK;
+}
+
+pds_status pds_frob_diff(const double* A, const double* B, int64_t len, double* out2, void* ws, size_t ws_bytes,
+                         void* stream)
+{
+    if (len < 1) return fail(PDS_E_ARG, "frob_diff: len = %lld < 1", (long long)len);
+    if (!A || !B || !out2) return fail(PDS_E_ARG, "A, B and out2 must be non-NULL");
+    if (!ws || ws_bytes < pds::frob_workspace())
+        return fail(PDS_E_WORKSPACE, "frob_diff needs %zu workspace bytes", pds::frob_workspace());
+    hipError_t e = pds::launch_frob_diff(A, B, len, out2, reinterpret_cast<double*>(ws),
+                                         reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "frob_diff");
+    return PDS_OK;
+}
+
+namespace {
+
+// Workspace of the m-selector calls on n rows of a plan with m = p:
+// idx (n x p u16) | Y (n x p f32) | moments raw, y (n x 3 f64 each) |
+// acc, C (p x p f64 each) | covariance workspace | Frobenius partials | sums
+struct MselLayout {
+    size_t idx, y, mr, my, acc, c, cov, frob, sums, total;
+};
+
+size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+MselLayout msel_layout(int p, int64_t n, const pds::DeviceInfo& dev)
+{
+    MselLayout L;
+    size_t o = 0;
+    L.idx = o;
+    o += up256((size_t)n * p * sizeof(uint16_t));
+    L.y = o;
+    o += up256((size_t)n * p * sizeof(float));
+    L.mr = o;
+    o += up256((size_t)n * 3 * sizeof(double));
+    L.my = o;
+    o += up256((size_t)n * 3 * sizeof(double));
+    L.acc = o;
+    o += up256((size_t)p * p * sizeof(double));
+    L.c = o;
+    o += up256((size_t)p * p * sizeof(double));
+    L.cov = o;
+    o += up256(pds::covariance_workspace(PDS_F32, p, p, n, dev) + pds::compress_workspace(PDS_F32, p, n, dev));
+    L.frob = o;
+    o += up256(pds::frob_workspace());
+    L.sums = o;
+    o += 256;
+    L.total = o;
+    return L;
+}
+
+pds_status msel_check_plan(pds_plan plan)
+{
+    if (pds_status st = check_plan(plan)) return st;
+    if (plan->m != plan->p) return fail(PDS_E_M, "m-selector calls need a plan with m = p (got m = %lld, p = %lld)",
+                                        (long long)plan->m, (long long)plan->p);
+    if (plan->prec != PDS_F32) return fail(PDS_E_ARG, "m-selector calls need a PDS_F32 plan");
+    return PDS_OK;
+}
+
+// y = H D x of rows 0..n-1, their moments and the raw rows' moments, then
+// C = (1/n) sum y y^T into C and ||C||_F^2 into sums[1]
+pds_status msel_exact(pds_plan plan, const float* X, int64_t n, int64_t ldx, unsigned char* w, const MselLayout& L,
+                      double* C, const pds::DeviceInfo& dev, hipStream_t s)
+{
+    const int p = (int)plan->p;
+    uint16_t* idx = reinterpret_cast<uint16_t*>(w + L.idx);
+    float* Y = reinterpret_cast<float*>(w + L.y);
+    double* acc = reinterpret_cast<double*>(w + L.acc);
+    void* cws = w + L.cov;
+    const size_t cws_bytes = L.frob - L.cov;
+    hipError_t e = pds::launch_zero_f64(acc, (int64_t)p * p, dev, s);
+    if (e == hipSuccess) e = pds::launch_sample_indices(plan->seed, p, p, n, 0, idx, dev, s);
+    if (e == hipSuccess) e = pds::launch_compress(PDS_F32, plan->seed, p, p, X, n, ldx, idx, Y, cws, cws_bytes, dev, s);
+    if (e == hipSuccess) e = pds::launch_row_moments(X, n, p, ldx, reinterpret_cast<double*>(w + L.mr), dev, s);
+    if (e == hipSuccess) e = pds::launch_row_moments(Y, n, p, p, reinterpret_cast<double*>(w + L.my), dev, s);
+    if (e == hipSuccess) e = pds::launch_covariance_accumulate(PDS_F32, p, p, Y, idx, n, acc, cws, cws_bytes, dev, s);
+    if (e == hipSuccess) e = pds::launch_covariance_finalize(PDS_F32, p, p, n, acc, C, s);
+    if (e == hipSuccess)
+        e = pds::launch_frob_diff(C, C, (int64_t)p * p, reinterpret_cast<double*>(w + L.sums),
+                                  reinterpret_cast<double*>(w + L.frob), s);
+    if (e != hipSuccess) return hip_fail(e, "m-selector exact covariance");
+    return PDS_OK;
+}
+
+}  // namespace
+
+pds_status pds_msel_workspace_size(pds_plan plan, int64_t n, size_t* bytes)
+{
+    if (pds_status st = msel_check_plan(plan)) return st;
+    if (!bytes) return fail(PDS_E_ARG, "bytes is NULL");
+    if (n < 2) return fail(PDS_E_ARG, "n = %lld < 2", (long long)n);
+    *bytes = msel_layout((int)plan->p, n, query_dev_or_default()).total;
+    return PDS_OK;
+}
+
+pds_status pds_msel_label(pds_plan plan, const float* X, int64_t n, int64_t ldx, double target, int32_t* m_out,
+                          double* C_out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (pds_status st = msel_check_plan(plan)) return st;
+    if (n < 2) return fail(PDS_E_ARG, "n = %lld < 2", (long long)n);
+    if (ldx < plan->p) return fail(PDS_E_ARG, "ldx = %lld < p = %lld", (long long)ldx, (long long)plan->p);
+    if (!X || !m_out) return fail(PDS_E_ARG, "X and m_out must be non-NULL");
+    if (!(target > 0.0) || !isfinite(target)) return fail(PDS_E_ARG, "target must be positive and finite");
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_msel_label");
+    const MselLayout L = msel_layout((int)plan->p, n, dev);
+    if (!ws || ws_bytes < L.total) return fail(PDS_E_WORKSPACE, "msel_label needs %zu workspace bytes", L.total);
+    unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    double* C = C_out ? C_out : reinterpret_cast<double*>(w + L.c);
+    if (pds_status st = msel_exact(plan, X, n, ldx, w, L, C, dev, s)) return st;
+    e = pds::launch_msel_label(reinterpret_cast<double*>(w + L.my), n, (int)plan->p,
+                               reinterpret_cast<double*>(w + L.sums) + 1, target, m_out, s);
+    if (e != hipSuccess) return hip_fail(e, "msel_label");
+    return PDS_OK;
+}
+
+pds_status pds_msel_features(pds_plan plan, const float* X, int64_t n, int64_t ldx, int64_t nsub, double target,
+                             float* feats, void* ws, size_t ws_bytes, void* stream)
+{
+    if (pds_status st = msel_check_plan(plan)) return st;
+    if (nsub < 2 || nsub > 1024 || nsub > n)
+        return fail(PDS_E_ARG, "nsub = %lld: must satisfy 2 <= nsub <= min(n, 1024)", (long long)nsub);
+    if (ldx < plan->p) return fail(PDS_E_ARG, "ldx = %lld < p = %lld", (long long)ldx, (long long)plan->p);
+    if (!X || !feats) return fail(PDS_E_ARG, "X and feats must be non-NULL");
+    if (!(target > 0.0) || !isfinite(target)) return fail(PDS_E_ARG, "target must be positive and finite");
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_msel_features");
+    const MselLayout L = msel_layout((int)plan->p, nsub, dev);
+    if (!ws || ws_bytes < L.total) return fail(PDS_E_WORKSPACE, "msel_features needs %zu workspace bytes", L.total);
+    unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (pds_status st = msel_exact(plan, X, nsub, ldx, w, L, reinterpret_cast<double*>(w + L.c), dev, s)) return st;
+    e = pds::launch_msel_features(reinterpret_cast<double*>(w + L.mr), reinterpret_cast<double*>(w + L.my), (int)nsub,
+                                  n, (int)plan->p, reinterpret_cast<double*>(w + L.sums) + 1, target, feats, s);
+    if (e != hipSuccess) return hip_fail(e, "msel_features");
+    return PDS_OK;
+}
+
+int32_t pds_mlp_param_count(void) { return pds::mlp_param_count(); }
+
+static pds_status mlp_check_B(int64_t B)
+{
+    if (B < 1 || B > (int64_t)1 << 26) return fail(PDS_E_ARG, "B = %lld: must be in [1, 2^26]", (long long)B);
+    return PDS_OK;
+}
+
+pds_status pds_mlp_forward(const float* params, const float* feats, const float* mu, const float* sd, int64_t B,
+                           float* acts, float* pred, void* stream)
+{
+    if (pds_status st = mlp_check_B(B)) return st;
+    if (!params || !feats || !mu || !sd || !acts || !pred)
+        return fail(PDS_E_ARG, "params, feats, mu, sd, acts and pred must be non-NULL");
+    hipError_t e = pds::launch_mlp_forward(params, feats, mu, sd, (int)B, acts, pred,
+                                           reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mlp_forward");
+    return PDS_OK;
+}
+
+pds_status pds_mlp_backward(const float* params, const float* acts, const float* pred, const float* target, int64_t B,
+                            float tau, float* ws, size_t ws_bytes, float* grad, float* loss, void* stream)
+{
+    if (pds_status st = mlp_check_B(B)) return st;
+    if (!params || !acts || !pred || !target || !grad || !loss)
+        return fail(PDS_E_ARG, "params, acts, pred, target, grad and loss must be non-NULL");
+    if (!(tau > 0.0f && tau < 1.0f)) return fail(PDS_E_ARG, "tau must lie in (0, 1)");
+    const size_t need = (size_t)B * 130 * sizeof(float);
+    if (!ws || ws_bytes < need) return fail(PDS_E_WORKSPACE, "mlp_backward needs %zu workspace bytes", need);
+    float* sig = ws;
+    float* lossb = ws + (size_t)B * 129;
+    hipError_t e = pds::launch_mlp_backward(params, acts, pred, target, (int)B, tau, sig, lossb, grad, loss,
+                                            reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mlp_backward");
+    return PDS_OK;
+}
+
+pds_status pds_mlp_adam(float* params, const float* grad, float* m1, float* m2, int32_t step, float lr, float beta1,
+                        float beta2, float eps, void* stream)
+{
+    if (!params || !grad || !m1 || !m2) return fail(PDS_E_ARG, "params, grad, m1 and m2 must be non-NULL");
+    if (step < 1) return fail(PDS_E_ARG, "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+        return fail(PDS_E_ARG, "Adam needs 0 <= beta < 1, eps > 0, lr >= 0");
+    hipError_t e = pds::launch_adam(params, grad, m1, m2, pds::mlp_param_count(), lr, beta1, beta2, eps, step,
+                                    reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mlp_adam");
+    return PDS_OK;
+}
+
+pds_status pds_mlp_pack_bf16(const float* params, uint16_t* params_bf16, void* stream)
+{
+    if (!params || !params_bf16) return fail(PDS_E_ARG, "params and params_bf16 must be non-NULL");
+    hipError_t e = pds::launch_pack_bf16(params, pds::mlp_param_count(), params_bf16,
+                                         reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mlp_pack_bf16");
+    return PDS_OK;
+}
+
+pds_status pds_msel_predict(const uint16_t* params_bf16, const float* feats, const float* mu, const float* sd,
+                            int64_t B, float gamma_min, float gamma_max, float gamma_fallback, float* gamma,
+                            void* stream)
+{
+    if (pds_status st = mlp_check_B(B)) return st;
+    if (!params_bf16 || !feats || !mu || !sd || !gamma)
+        return fail(PDS_E_ARG, "params_bf16, feats, mu, sd and gamma must be non-NULL");
+    if (!(gamma_min > 0.0f && gamma_min <= gamma_max && isfinite(gamma_max) && isfinite(gamma_fallback)))
+        return fail(PDS_E_ARG, "need 0 < gamma_min <= gamma_max and a finite fallback");
+    hipError_t e = pds::launch_mlp_predict_bf16(params_bf16, feats, mu, sd, (int)B, gamma_min, gamma_max,
+                                                gamma_fallback, gamma, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "msel_predict");
+    return PDS_OK;
+}
+
+// ---- batched form --------------------------------------------------------------
+
+namespace {
+
+constexpr int kBatchSpwCand[3] = {16, 32, 64};
+constexpr int kBatchAchunkCand[2] = {256, 1024};
+constexpr int kBatchCchunkCand[2] = {4096, 16384};
+
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Workspace offsets (bytes) of the batch tables; sized for the smallest
+// candidate chunks so that re-tuning never grows the workspace.
+struct BatchOffsets {
+    size_t sets, gp, ap, cp, up, ct, cmax, pobj, psum, pcnt, total;
+};
+
+int accum_kg(int K, int p)
+{
+    int kg = pds::kBatchAccumEntries / p;
+    if (kg < 1) kg = 1;
+    if (kg > K) kg = K;
+    return kg;
+}
+
+BatchOffsets batch_offsets(const pds_batch_s& b)
+{
+    const size_t ns = b.descs.size();
+    size_t ct = 0, pobj = 0, part = 0;
+    for (const auto& d : b.descs) {
+        const int64_t KP = (int64_t)d.K * d.p;
+        ct += (size_t)KP;
+        pobj += (size_t)cdiv(d.n, kBatchAchunkCand[0]);
+        part += (size_t)cdiv(d.n, kBatchCchunkCand[0]) * (size_t)KP;
+    }
+    BatchOffsets o;
+    size_t off = 0;
+    o.sets = off;
+    off += al256(ns * sizeof(pds::BatchSet));
+    o.gp = off;
+    off += al256((ns + 1) * 8);
+    o.ap = off;
+    off += al256((ns + 1) * 8);
+    o.cp = off;
+    off += al256((ns + 1) * 8);
+    o.up = off;
+    off += al256((ns + 1) * 8);
+    o.ct = off;
+    off += al256(ct * 4);
+    o.cmax = off;
+    off += al256(2 * ns * 4);
+    o.pobj = off;
+    off += al256((pobj > 0 ? pobj : 1) * 8);
+    o.psum = off;
+    off += al256((part > 0 ? part : 1) * 4);
+    o.pcnt = off;
+    off += al256((part > 0 ? part : 1) * 4);
+    o.total = off;
+    return o;
+}
+
+// Host image of the tables for a tuning; device pointers relative to ws.
+void batch_build(const pds_batch_s& b, const pds::BatchTuning& tu, unsigned char* ws, std::vector<unsigned char>& img,
+                 pds::BatchTables& t)
+{
+    const BatchOffsets o = batch_offsets(b);
+    const int ns = (int)b.descs.size();
+    img.assign(o.ct, 0);  // sets and prefix tables only
+    pds::BatchSet* sets = reinterpret_cast<pds::BatchSet*>(img.data() + o.sets);
+    int64_t* gp = reinterpret_cast<int64_t*>(img.data() + o.gp);
+    int64_t* ap = reinterpret_cast<int64_t*>(img.data() + o.ap);
+    int64_t* cp = reinterpret_cast<int64_t*>(img.data() + o.cp);
+    int64_t* up = reinterpret_cast<int64_t*>(img.data() + o.up);
+    int64_t g = 0, a = 0, c = 0, u = 0, ct = 0, part = 0;
+    for (int i = 0; i < ns; ++i) {
+        const pds_batch_desc& d = b.descs[i];
+        pds::BatchSet& S = sets[i];
+        S.X = d.X;
+        S.vals = d.vals;
+        S.idx = d.idx;
+        S.c_a = d.centers;
+        S.c_b = d.centers_alt;
+        S.assign = d.assign;
+        S.objective = d.objective;
+        S.n = d.n;
+        S.ldx = d.ldx;
+        S.p = d.p;
+        S.m = d.m;
+        S.K = d.K;
+        int L = 0;
+        while ((1 << L) < d.p) ++L;
+        S.L = L;
+        S.seed = d.seed;
+        const int64_t KP = (int64_t)d.K * d.p;
+        S.aitem0 = a;
+        S.naitems = cdiv(d.n, tu.achunk);
+        S.ct_off = ct;
+        S.part_off = part;
+        S.cchunk = tu.cchunk;
+        S.nacc = cdiv(d.n, tu.cchunk);
+        S.kg = accum_kg(d.K, d.p);
+        S.ngk = (int)cdiv(d.K, S.kg);
+        gp[i] = g;
+        ap[i] = a;
+        cp[i] = c;
+        up[i] = u;
+        g += cdiv(d.n, tu.spw);
+        a += S.naitems;
+        c += S.nacc * S.ngk;
+        u += cdiv(KP, 256);
+        ct += KP;
+        part += S.nacc * KP;
+    }
+    gp[ns] = g;
+    ap[ns] = a;
+    cp[ns] = c;
+    up[ns] = u;
+    t.gprefix = reinterpret_cast<const int64_t*>(ws + o.gp);
+    t.aprefix = reinterpret_cast<const int64_t*>(ws + o.ap);
+    t.cprefix = reinterpret_cast<const int64_t*>(ws + o.cp);
+    t.uprefix = reinterpret_cast<const int64_t*>(ws + o.up);
+    t.ngroups = g;
+    t.naitems = a;
+    t.ncitems = c;
+    t.nuitems = u;
+    t.ct = reinterpret_cast<float*>(ws + o.ct);
+    t.cmax = reinterpret_cast<uint32_t*>(ws + o.cmax);
+    t.pobj = reinterpret_cast<double*>(ws + o.pobj);
+    t.psum = reinterpret_cast<float*>(ws + o.psum);
+    t.pcnt = reinterpret_cast<uint32_t*>(ws + o.pcnt);
+}
+
+const pds::BatchSet* batch_sets(const pds_batch_s& b) { return reinterpret_cast<const pds::BatchSet*>(b.ws); }
+
+void batch_set_grids(pds_batch_s& b, const pds::DeviceInfo& dev)
+{
+    b.tune.compress_grid = (int64_t)dev.cus * pds::batch_compress_occupancy(b.tune.spw, b.pmax);
+    b.tune.assign_grid = (int64_t)dev.cus * 4;
+    b.tune.accum_grid = (int64_t)dev.cus * 2;
+    b.tune.update_grid = (int64_t)dev.cus * 8;
+}
+
+hipError_t batch_upload(pds_batch_s& b, hipStream_t s)
+{
+    batch_build(b, b.tune, b.ws, b.host_tables, b.tables);
+    return hipMemcpyAsync(b.ws, b.host_tables.data(), b.host_tables.size(), hipMemcpyHostToDevice, s);
+}
+
+void batch_drop_graph(pds_batch_s& b)
+{
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+}
+
+// the T rounds (and their prep) on stream s
+hipError_t batch_enqueue_rounds(pds_batch_s& b, hipStream_t s, int T)
+{
+    const int ns = (int)b.descs.size();
+    const pds::BatchSet* sets = batch_sets(b);
+    hipError_t e = pds::launch_batch_round_prep(sets, ns, b.tables.ct, b.tables.cmax, (T & 1) ? 1 : 0, s);
+    for (int r = 0; r < T && e == hipSuccess; ++r)
+        e = pds::launch_batch_round(sets, ns, b.tables, b.tune, (T - 1 - r) & 1, r, s);
+    return e;
+}
+
+hipError_t batch_capture(pds_batch_s& b)
+{
+    batch_drop_graph(b);
+    if (b.T == 0) return hipSuccess;
+    if (!b.cap) {
+        hipError_t e = hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = batch_enqueue_rounds(b, b.cap, b.T);
+    e = hipStreamEndCapture(b.cap, &b.graph);
+    if (le != hipSuccess) return le;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
+    size_t nodes = 0;
+    if (e == hipSuccess) e = hipGraphGetNodes(b.graph, nullptr, &nodes);
+    b.kernels_per_kmeans = (int)nodes;
+    return e;
+}
+
+pds_status check_batch(pds_batch b, bool bound)
+{
+    if (!b) return fail(PDS_E_ARG, "batch is NULL");
+    if (bound && !b->ws) return fail(PDS_E_ARG, "batch has no workspace bound (pds_batch_bind)");
+    return PDS_OK;
+}
+
+}  // namespace
+
+pds_status pds_batch_create(pds_batch* out, const pds_batch_desc* descs, int32_t count, int32_t T)
+{
+    if (!out) return fail(PDS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!descs || count < 1) return fail(PDS_E_ARG, "need count >= 1 descriptors");
+    if (T < 0 || T > 100000) return fail(PDS_E_ARG, "T = %d: must be in [0, 100000]", (int)T);
+    int pmax = 128;
+    for (int i = 0; i < count; ++i) {
+        const pds_batch_desc& d = descs[i];
+        if (d.p < 128 || d.p > 2048 || !is_pow2(d.p))
+            return fail(PDS_E_UNSUPPORTED, "set %d: p = %d must be a power of two in [128, 2048]", i, (int)d.p);
+        if (d.m < 1 || d.m > d.p) return fail(PDS_E_M, "set %d: m = %d must satisfy 1 <= m <= p", i, (int)d.m);
+        if (d.K < 1 || d.K > 1024) return fail(PDS_E_ARG, "set %d: K = %d must be in [1, 1024]", i, (int)d.K);
+        if (d.n < 0 || d.n > ((int64_t)1 << 40)) return fail(PDS_E_ARG, "set %d: n out of range", i);
+        if (d.reserved != 0) return fail(PDS_E_ARG, "set %d: reserved must be 0", i);
+        if (d.ldx < d.p) return fail(PDS_E_ARG, "set %d: ldx < p", i);
+        if (!d.centers || !d.centers_alt || d.centers == d.centers_alt)
+            return fail(PDS_E_ARG, "set %d: centers and centers_alt must be distinct non-NULL buffers", i);
+        if (T > 0 && !d.objective) return fail(PDS_E_ARG, "set %d: objective is NULL", i);
+        if (d.n > 0) {
+            if (!d.X || !d.vals || !d.idx || !d.assign)
+                return fail(PDS_E_ARG, "set %d: X, vals, idx and assign must be non-NULL", i);
+            if (d.p >= 256 && (((uintptr_t)d.X) % 16 != 0 || (d.ldx * 4) % 16 != 0))
+                return fail(PDS_E_ARG, "set %d: rows must be 16-byte aligned for p >= 256", i);
+        }
+        if (d.p > pmax) pmax = d.p;
+    }
+    pds_batch b = new (std::nothrow) pds_batch_s;
+    if (!b) return fail(PDS_E_ARG, "out of host memory");
+    b->descs.assign(descs, descs + count);
+    b->T = T;
+    b->pmax = pmax;
+    b->tune.spw = 64;
+    b->tune.achunk = 1024;
+    b->tune.cchunk = 16384;
+    b->ws_bytes = batch_offsets(*b).total;
+    *out = b;
+    return PDS_OK;
+}
+
+pds_status pds_batch_destroy(pds_batch b)
+{
+    if (!b) return PDS_OK;
+    batch_drop_graph(*b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return PDS_OK;
+}
+
+pds_status pds_batch_workspace_size(pds_batch b, size_t* bytes)
+{
+    if (pds_status st = check_batch(b, false)) return st;
+    if (!bytes) return fail(PDS_E_ARG, "bytes is NULL");
+    *bytes = b->ws_bytes;
+    return PDS_OK;
+}
+
+pds_status pds_batch_bind(pds_batch b, void* ws, size_t ws_bytes, void* stream)
+{
+    if (pds_status st = check_batch(b, false)) return st;
+    if (!ws || ws_bytes < b->ws_bytes)
+        return fail(PDS_E_WORKSPACE, "batch needs %zu workspace bytes, got %zu", b->ws_bytes, ws ? ws_bytes : (size_t)0);
+    if (((uintptr_t)ws) % 256 != 0) return fail(PDS_E_ARG, "workspace must be 256-byte aligned");
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_batch_bind");
+    e = pds::batch_init_attributes();
+    if (e != hipSuccess) return hip_fail(e, "pds_batch_bind");
+    b->ws = reinterpret_cast<unsigned char*>(ws);
+    batch_set_grids(*b, dev);
+    e = batch_upload(*b, reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = batch_capture(*b);
+    if (e != hipSuccess) {
+        b->ws = nullptr;
+        return hip_fail(e, "pds_batch_bind");
+    }
+    return PDS_OK;
+}
+
+pds_status pds_batch_compress(pds_batch b, void* stream)
+{
+    if (pds_status st = check_batch(b, true)) return st;
+    hipError_t e = pds::launch_batch_compress(batch_sets(*b), (int)b->descs.size(), b->tables.gprefix,
+                                              b->tables.ngroups, b->tune.spw, b->pmax, b->tune.compress_grid,
+                                              reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pds_batch_compress");
+    return PDS_OK;
+}
+
+pds_status pds_batch_init_centers(pds_batch b, void* stream)
+{
+    if (pds_status st = check_batch(b, true)) return st;
+    hipError_t e = pds::launch_batch_init(batch_sets(*b), (int)b->descs.size(), b->tables.uprefix, b->tables.nuitems,
+                                          b->tune.update_grid, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pds_batch_init_centers");
+    return PDS_OK;
+}
+
+pds_status pds_batch_kmeans(pds_batch b, void* stream)
+{
+    if (pds_status st = check_batch(b, true)) return st;
+    if (b->T == 0) return PDS_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e;
+    {
+        pds::ProfScope ps_("batch_kmeans_graph", s);
+        e = hipGraphLaunch(b->exec, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "pds_batch_kmeans");
+    return PDS_OK;
+}
+
+pds_status pds_batch_autotune(pds_batch b, void* stream)
+{
+    if (pds_status st = check_batch(b, true)) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_batch_autotune");
+    hipEvent_t t0, t1;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+        return fail(PDS_E_HIP, "pds_batch_autotune: event creation failed");
+    auto timed = [&](auto&& work, float& ms) -> hipError_t {
+        hipError_t r = work();  // warm-up
+        if (r == hipSuccess) r = hipEventRecord(t0, s);
+        for (int rep = 0; rep < 3 && r == hipSuccess; ++rep) r = work();
+        if (r == hipSuccess) r = hipEventRecord(t1, s);
+        if (r == hipSuccess) r = hipEventSynchronize(t1);
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, t0, t1);
+        return r;
+    };
+    const int ns = (int)b->descs.size();
+    // compression: samples per group
+    float best = 1e30f;
+    int best_spw = b->tune.spw;
+    for (int spw : kBatchSpwCand) {
+        if (e != hipSuccess) break;
+        b->tune.spw = spw;
+        batch_set_grids(*b, dev);
+        e = batch_upload(*b, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        float ms = 0.0f;
+        if (e == hipSuccess)
+            e = timed([&]() {
+                return pds::launch_batch_compress(batch_sets(*b), ns, b->tables.gprefix, b->tables.ngroups, spw,
+                                                  b->pmax, b->tune.compress_grid, s);
+            }, ms);
+        if (e == hipSuccess && ms < best) {
+            best = ms;
+            best_spw = spw;
+        }
+    }
+    b->tune.spw = best_spw;
+    // K-means round: assignment item and accumulation chunk lengths
+    best = 1e30f;
+    int best_a = b->tune.achunk, best_c = b->tune.cchunk;
+    for (int ac : kBatchAchunkCand) {
+        for (int cc : kBatchCchunkCand) {
+            if (e != hipSuccess || b->T == 0) break;
+            b->tune.achunk = ac;
+            b->tune.cchunk = cc;
+            batch_set_grids(*b, dev);
+            e = batch_upload(*b, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess) e = pds::launch_batch_round_prep(batch_sets(*b), ns, b->tables.ct, b->tables.cmax, 0, s);
+            float ms = 0.0f;
+            if (e == hipSuccess)
+                e = timed([&]() { return pds::launch_batch_round(batch_sets(*b), ns, b->tables, b->tune, 1, 0, s); }, ms);
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                best_a = ac;
+                best_c = cc;
+            }
+        }
+    }
+    b->tune.achunk = best_a;
+    b->tune.cchunk = best_c;
+    batch_set_grids(*b, dev);
+    if (e == hipSuccess) e = batch_upload(*b, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = batch_capture(*b);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return hip_fail(e, "pds_batch_autotune");
+    return PDS_OK;
+}
+
+pds_status pds_batch_info(pds_batch b, char* buf, size_t len)
+{
+    if (pds_status st = check_batch(b, false)) return st;
+    if (!buf || len == 0) return fail(PDS_E_ARG, "buf is NULL");
+    int64_t n = 0;
+    for (const auto& d : b->descs) n += d.n;
+    snprintf(buf, len,
+             "sets=%d samples=%lld T=%d spw=%d achunk=%d cchunk=%d groups=%lld assign_items=%lld accum_items=%lld "
+             "update_items=%lld compress_grid=%lld graph_kernels=%d ws_bytes=%zu",
+             (int)b->descs.size(), (long long)n, b->T, b->tune.spw, b->tune.achunk, b->tune.cchunk,
+             (long long)b->tables.ngroups, (long long)b->tables.naitems, (long long)b->tables.ncitems,
+             (long long)b->tables.nuitems, (long long)b->tune.compress_grid, b->kernels_per_kmeans, b->ws_bytes);
     return PDS_OK;
 }
 

@@ -16,140 +16,10 @@
 // butterfly stages in a staging buffer (LDS, or a workspace slice for very
 // large p) with barriers between stages.
 #include "pds_device.hpp"
+#include "pds_fast.hpp"
 #include "pds_internal.hpp"
 
 namespace pds {
-
-// ---------------------------------------------------------------------------
-// Bit layouts of the fast path.  Element index bits are split into R register
-// bits and 6 lane bits.  Phase 0 is the load layout (bits [0, LV) and
-// [LV+6, L) in registers, [LV, LV+6) across lanes).  Phase ph >= 1 brings lane
-// bits [LV + (ph-1)R, LV + ph R) into registers (the group), filling any spare
-// register bits with the lowest other bits.
-// ---------------------------------------------------------------------------
-template <int L, int LV>
-struct FastLayout {
-    static constexpr int R = L - 6;
-    static constexpr int kPhases = 1 + (6 + R - 1) / R;
-
-    static constexpr int group_start(int ph) { return LV + (ph - 1) * R; }
-    static constexpr int group_size(int ph)
-    {
-        return (ph == 0) ? R : ((6 - (ph - 1) * R) < R ? (6 - (ph - 1) * R) : R);
-    }
-    static constexpr bool in_group(int ph, int bit)
-    {
-        return ph > 0 && bit >= group_start(ph) && bit < group_start(ph) + group_size(ph);
-    }
-    // element bit carried by register bit k in phase ph
-    static constexpr int reg_bit(int ph, int k)
-    {
-        if (ph == 0) return (k < LV) ? k : k + 6;
-        if (k < group_size(ph)) return group_start(ph) + k;
-        int need = k - group_size(ph);
-        for (int b = 0; b < L; ++b) {
-            if (in_group(ph, b)) continue;
-            if (need == 0) return b;
-            --need;
-        }
-        return -1;
-    }
-    static constexpr bool is_reg_bit(int ph, int bit)
-    {
-        for (int k = 0; k < R; ++k)
-            if (reg_bit(ph, k) == bit) return true;
-        return false;
-    }
-    // element bit carried by lane bit k in phase ph
-    static constexpr int lane_bit(int ph, int k)
-    {
-        int need = k;
-        for (int b = 0; b < L; ++b) {
-            if (is_reg_bit(ph, b)) continue;
-            if (need == 0) return b;
-            --need;
-        }
-        return -1;
-    }
-    static constexpr int reg_part(int ph, int ri)
-    {
-        int e = 0;
-        for (int k = 0; k < R; ++k)
-            if ((ri >> k) & 1) e |= 1 << reg_bit(ph, k);
-        return e;
-    }
-    __device__ static int lane_part(int ph, int lane)
-    {
-        int e = 0;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) e |= ((lane >> k) & 1) << lane_bit(ph, k);
-        return e;
-    }
-};
-
-template <typename T>
-struct VecOf;
-template <>
-struct VecOf<float> {
-    using type = float4;
-    static constexpr int n = 4;
-};
-template <>
-struct VecOf<double> {
-    using type = double2;
-    static constexpr int n = 2;
-};
-
-template <typename T>
-__device__ inline T flip_sign(T x, uint32_t neg);
-template <>
-__device__ inline float flip_sign<float>(float x, uint32_t neg)
-{
-    return __uint_as_float(__float_as_uint(x) ^ (neg << 31));
-}
-template <>
-__device__ inline double flip_sign<double>(double x, uint32_t neg)
-{
-    return __longlong_as_double(__double_as_longlong(x) ^ ((unsigned long long)neg << 63));
-}
-
-template <typename T, int L>
-__device__ inline void load_row(T (&x)[(1 << L) / 64], const T* __restrict__ row, int lane)
-{
-    constexpr int E = (1 << L) / 64;
-    constexpr int V = VecOf<T>::n < E ? VecOf<T>::n : E;
-    using Vec = typename VecOf<T>::type;
-    if constexpr (V == VecOf<T>::n) {
-#pragma unroll
-        for (int j = 0; j < E / V; ++j) {
-            Vec v = *reinterpret_cast<const Vec*>(row + (j * 64 + lane) * V);
-            const T* pv = reinterpret_cast<const T*>(&v);
-#pragma unroll
-            for (int q = 0; q < V; ++q) x[j * V + q] = pv[q];
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < E / V; ++j)
-#pragma unroll
-            for (int q = 0; q < V; ++q) x[j * V + q] = row[(j * 64 + lane) * V + q];
-    }
-}
-
-template <int E, typename T>
-__device__ inline void butterflies(T (&x)[E], int nbits)
-{
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        if (k >= nbits) break;
-#pragma unroll
-        for (int ri = 0; ri < E; ++ri) {
-            if ((ri >> k) & 1) continue;
-            T a = x[ri], b = x[ri | (1 << k)];
-            x[ri] = a + b;
-            x[ri | (1 << k)] = a - b;
-        }
-    }
-}
 
 template <typename T, int L>
 __global__ __launch_bounds__(64) void k_compress_fast(uint64_t seed, int m, const T* __restrict__ X, int64_t n,
@@ -158,7 +28,7 @@ __global__ __launch_bounds__(64) void k_compress_fast(uint64_t seed, int m, cons
 {
     constexpr int P = 1 << L;
     constexpr int E = P / 64;
-    constexpr int LV = (VecOf<T>::n < E) ? (VecOf<T>::n == 4 ? 2 : 1) : (E == 4 ? 2 : (E == 2 ? 1 : 0));
+    constexpr int LV = FastLV<T, L>::value;
     using Lay = FastLayout<L, LV>;
     constexpr int NPH = Lay::kPhases;
     constexpr int PADDED = lds_pad<T>(P - 1) + 1;

@@ -139,7 +139,7 @@ __device__ inline uint32_t uniform_below(WordStream& s, uint32_t range)
 // Padded LDS address of element e of a transform buffer: one extra 32-bit
 // slot every 32 elements spreads strided accesses over the LDS banks.
 template <typename T>
-__device__ constexpr int lds_pad(int e)
+__host__ __device__ constexpr int lds_pad(int e)
 {
     return (sizeof(T) == 4) ? (e + (e >> 5)) : (e + (e >> 4));
 }

@@ -60,4 +60,29 @@ hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const ui
 // ---- unmix ------------------------------------------------------------------
 hipError_t launch_unmix(uint64_t seed, int p, const double* cpre, int K, double* cout, hipStream_t s);
 
+// ---- learned m-selector -----------------------------------------------------
+// per-row (sum x^2, sum x^4, max x^2) in FP64, out is n x 3
+hipError_t launch_row_moments(const float* X, int64_t n, int p, int64_t ldx, double* out, const DeviceInfo& dev,
+                              hipStream_t s);
+// out2 = (sum (A-B)^2, sum B^2); part holds frob_workspace() bytes
+size_t frob_workspace();
+hipError_t launch_frob_diff(const double* A, const double* B, int64_t len, double* out2, double* part, hipStream_t s);
+hipError_t launch_msel_label(const double* mom, int64_t n, int p, const double* F2, double t, int32_t* m_out,
+                             hipStream_t s);
+hipError_t launch_msel_features(const double* mr, const double* my, int s_rows, int64_t n, int p, const double* F2s,
+                                double t, float* feats, hipStream_t s);
+hipError_t launch_zero_f64(double* a, int64_t len, const DeviceInfo& dev, hipStream_t s);
+
+// MLP 32 -> 64 -> 64 -> 1 (packed FP32 parameters, mlp_param_count() of them)
+int mlp_param_count();
+hipError_t launch_mlp_forward(const float* P, const float* feats, const float* mu, const float* sd, int B, float* acts,
+                              float* out, hipStream_t s);
+hipError_t launch_mlp_backward(const float* P, const float* acts, const float* pred, const float* target, int B,
+                               float tau, float* sig, float* lossb, float* grad, float* loss, hipStream_t s);
+hipError_t launch_adam(float* P, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+hipError_t launch_pack_bf16(const float* P, int n, unsigned short* Pb, hipStream_t s);
+hipError_t launch_mlp_predict_bf16(const unsigned short* Pb, const float* feats, const float* mu, const float* sd,
+                                   int B, float gmin, float gmax, float fallback, float* gamma, hipStream_t s);
+
 }  // namespace pds

@@ -1,0 +1,133 @@
+// Exact-m sampling without replacement (Sec. I setup; App. B) into LDS
+// bitmaps, shared by the sampling kernel and the batched compression kernel.
+//
+// Floyd's algorithm (Bentley & Floyd, CACM 1987): for t = p-m .. p-1 draw r
+// uniform on {0..t}; keep r, or keep t when r is already kept.  Draws are
+// Lemire's method on the sample's own Philox word stream (key (seed, 0),
+// counter (block, sample, 0, 0)), so the subset of a sample depends on
+// (seed, sample, p, m) only.  Bitmap word w of column col lives at
+// bitmap[w * stride + col].
+#pragma once
+
+#include "pds_device.hpp"
+
+namespace pds {
+
+__device__ inline int wave_exclusive_scan(int v, int lane)
+{
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    return incl - v;
+}
+
+// Kept set of one sample into a zeroed bitmap column (one lane's work).
+__device__ inline void floyd_bitmap(uint64_t seed, uint64_t sample, int p, int m, uint32_t* bitmap, int stride,
+                                    int col)
+{
+    // Fast path: draw t uses word t - (p - m) of the stream while no draw has
+    // been rejected; the Philox block after the current one is computed before
+    // the current block's set updates, so its arithmetic overlaps the LDS
+    // round trips.  At the first rejection (probability below range / 2^32 per
+    // draw) the lane continues on the exact sequential stream from the next
+    // word.
+    uint64_t blk = 0;
+    u64x4 cur = philox_block(0, sample, 0, 0, seed, 0);
+    int t = p - m;
+    int64_t rejected_word = -1;
+    while (t < p) {
+        const u64x4 nxt = philox_block(blk + 1, sample, 0, 0, seed, 0);
+        uint32_t w[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            w[2 * q] = (uint32_t)cur.w[q];
+            w[2 * q + 1] = (uint32_t)(cur.w[q] >> 32);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (t < p && rejected_word < 0) {
+                const uint32_t range = (uint32_t)(t + 1);
+                const uint64_t prod = (uint64_t)w[q] * range;
+                const uint32_t low = (uint32_t)prod;
+                if (low < range && low < (0u - range) % range) {
+                    rejected_word = (int64_t)(blk * 8 + q);
+                } else {
+                    const uint32_t c = (uint32_t)(prod >> 32);
+                    uint32_t* wc = &bitmap[(c >> 5) * stride + col];
+                    const uint32_t bit = 1u << (c & 31);
+                    const uint32_t old = *wc;
+                    if (old & bit)
+                        bitmap[((uint32_t)t >> 5) * stride + col] |= 1u << (t & 31);
+                    else
+                        *wc = old | bit;
+                    ++t;
+                }
+            }
+        }
+        if (rejected_word >= 0) break;
+        cur = nxt;
+        ++blk;
+    }
+    if (rejected_word >= 0) {
+        WordStream ws;
+        ws.init(seed, sample);
+        ws.seek((uint64_t)rejected_word + 1);
+        // finish the rejected draw: Lemire redraws with the same range
+        {
+            const uint32_t range = (uint32_t)(t + 1);
+            const uint32_t thresh = (0u - range) % range;
+            uint64_t prod;
+            uint32_t low;
+            do {
+                prod = (uint64_t)ws.next() * range;
+                low = (uint32_t)prod;
+            } while (low < thresh);
+            const uint32_t c = (uint32_t)(prod >> 32);
+            uint32_t* wc = &bitmap[(c >> 5) * stride + col];
+            const uint32_t bit = 1u << (c & 31);
+            if (*wc & bit)
+                bitmap[((uint32_t)t >> 5) * stride + col] |= 1u << (t & 31);
+            else
+                *wc |= bit;
+            ++t;
+        }
+        for (; t < p; ++t) {
+            const uint32_t c = uniform_below(ws, (uint32_t)(t + 1));
+            uint32_t* wc = &bitmap[(c >> 5) * stride + col];
+            const uint32_t bit = 1u << (c & 31);
+            if (*wc & bit)
+                bitmap[((uint32_t)t >> 5) * stride + col] |= 1u << (t & 31);
+            else
+                *wc |= bit;
+        }
+    }
+}
+
+// Ascending emission of bitmap column col by the whole wave: each lane takes
+// a contiguous run of bitmap words, a wave prefix sum of their popcounts gives
+// its first output position, and emit(pos, coord) is called for each kept
+// coordinate (lanes write side by side).
+template <class F>
+__device__ inline void emit_sorted(const uint32_t* bitmap, int stride, int col, int words, int lane, F emit)
+{
+    const int wpl = (words + 63) / 64;  // bitmap words per lane
+    const int w0 = lane * wpl;
+    int cnt = 0;
+    for (int q = 0; q < wpl; ++q)
+        if (w0 + q < words) cnt += __popc(bitmap[(w0 + q) * stride + col]);
+    int pos = wave_exclusive_scan(cnt, lane);
+    for (int q = 0; q < wpl; ++q) {
+        if (w0 + q >= words) break;
+        uint32_t bits = bitmap[(w0 + q) * stride + col];
+        while (bits) {
+            const int b = __builtin_ctz(bits);
+            emit(pos++, (w0 + q) * 32 + b);
+            bits &= bits - 1u;
+        }
+    }
+}
+
+}  // namespace pds

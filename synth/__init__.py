@@ -17,6 +17,14 @@ the paper's public datasets are not used):
   spikes, the "few large entries" case that motivates preconditioning):
   p = 1024, K = 10, n = 2^20, FP32.
 
+* ``msel`` -- data blocks for the learned m-selector (not a workload of the
+  paper): p = 1024, n = 8192, spike rank r ~ U{1..50}, lam_k = A / k with
+  amplitude A log-uniform on [50, 5e4], unit noise.  The principal directions
+  mix a random orthonormal basis with r canonical basis vectors, weight alpha ~
+  U[0, 1] on the canonical part, re-orthonormalized: alpha = 1 gives maximally
+  coherent data (the canonical-PC case of Sec. V's Table 1), alpha = 0
+  incoherent data.
+
 Row blocks are drawn from per-block generators (block = 65536 rows) so any
 leading slice of a workload is identical to the same rows of the full one.
 """
@@ -152,3 +160,78 @@ def random_compressed(n, p, m, seed, dtype=np.float32, K=None):
     if K is not None:
         out["centers"] = rng.standard_normal((K, p)) * 0.5
     return out
+
+
+# ---------------------------------------------------------------------------
+# m-selector blocks
+# ---------------------------------------------------------------------------
+MSEL = dict(p=1024, n=8192, rank=(1, 50), amp=(50.0, 5.0e4), target=0.1, nsub=512, gamma_fallback=0.2,
+            data_seed=5)
+
+
+def msel_block_params(seed, b):
+    """Parameters of block b of stream `seed`: rank r, coherence weight alpha, amplitude A."""
+    rng = np.random.default_rng([MSEL["data_seed"], seed, b, 0xE3])
+    lo, hi = MSEL["rank"]
+    r = int(rng.integers(lo, hi + 1))
+    alpha = float(rng.uniform())
+    a0, a1 = MSEL["amp"]
+    A = float(math.exp(rng.uniform(math.log(a0), math.log(a1))))
+    return {"r": r, "alpha": alpha, "amp": A}
+
+
+def msel_basis(seed, b, p, prm):
+    """p x r orthonormal principal directions of block b: the Q factor of
+    (1 - alpha) G / sqrt(p) + alpha E, G standard normal, E r distinct
+    canonical basis vectors (Gaussian columns over sqrt(p) are already close
+    to orthonormal; the QR makes them exactly so)."""
+    rng = np.random.default_rng([MSEL["data_seed"], seed, b, 0xBA5E])
+    r, alpha = prm["r"], prm["alpha"]
+    E = np.zeros((p, r))
+    E[rng.choice(p, size=r, replace=False), np.arange(r)] = 1.0
+    A = (1.0 - alpha) * rng.standard_normal((p, r)) / math.sqrt(p) + alpha * E
+    U, _ = np.linalg.qr(A)
+    return U
+
+
+def msel_block_numpy(seed, b, p=None, n=None):
+    """Block b of stream `seed` as float32 numpy (n x p), and its parameters."""
+    p = MSEL["p"] if p is None else p
+    n = MSEL["n"] if n is None else n
+    prm = msel_block_params(seed, b)
+    prm["r"] = min(prm["r"], p)
+    U = msel_basis(seed, b, p, prm)
+    lam = prm["amp"] / np.arange(1, prm["r"] + 1)
+    rng = np.random.default_rng([MSEL["data_seed"], seed, b, 0xDA7A])
+    X = (rng.standard_normal((n, prm["r"])) * np.sqrt(lam)) @ U.T + rng.standard_normal((n, p))
+    return X.astype(np.float32), prm
+
+
+def msel_blocks_torch(seed, b0, count, p=None, n=None, device="cuda"):
+    """Blocks b0 .. b0+count-1 drawn with torch on `device` (same parameters
+    and construction as msel_block_numpy, torch's generator for every draw).
+    The bases come from one batched QR of 50-column matrices: the first r
+    columns of a Q factor depend only on the first r columns of its input, so
+    block b keeps the first r columns.  Yields (X, params) per block."""
+    import torch
+
+    p = MSEL["p"] if p is None else p
+    n = MSEL["n"] if n is None else n
+    R = min(MSEL["rank"][1], p)
+    prms = [msel_block_params(seed, b) for b in range(b0, b0 + count)]
+    g = torch.Generator(device=device)
+    g.manual_seed((MSEL["data_seed"] * 1000003 + seed) * 1000003 + b0)
+    alpha = torch.tensor([q["alpha"] for q in prms], dtype=torch.float32, device=device).view(-1, 1, 1)
+    rows = torch.rand((count, p), generator=g, device=device).argsort(dim=1)[:, :R]
+    E = torch.zeros((count, p, R), device=device)
+    E.scatter_(1, rows.unsqueeze(1), 1.0)
+    A = (1.0 - alpha) * torch.randn((count, p, R), generator=g, device=device) / math.sqrt(p) + alpha * E
+    Q, _ = torch.linalg.qr(A)
+    for k, prm in enumerate(prms):
+        prm["r"] = min(prm["r"], p)
+        r = prm["r"]
+        sl = torch.as_tensor(np.sqrt(prm["amp"] / np.arange(1, r + 1)), dtype=torch.float32, device=device)
+        Z = torch.randn((n, r), generator=g, device=device)
+        X = torch.randn((n, p), generator=g, device=device)
+        X.addmm_(Z * sl, Q[k, :, :r].T)
+        yield X, prm

@@ -1,0 +1,254 @@
+"""GPU parity of the m-selector entry points against the FP64 oracle
+(oracle/msel.py) on the same seeded inputs.
+
+Bars: row moments and Frobenius sums 1e-12 relative (FP64 sums in another
+order); features 1e-5 absolute (FP32 transform under an FP32 plan); labels
+and the plug-in m of feature 31 equal, except where the oracle's own value of
+the error at the GPU's choice lies within 1e-5 (relative) of the target --
+both sides decide in FP64, but on rows transformed in FP32 and FP64; network
+forward, gradient and Adam 1e-5 normwise; the BF16 parameter copy bit-exact;
+BF16 inference against the oracle's emulation within BF16 rounding.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1511_00152_amd as pds  # noqa: E402
+from paper_1511_00152_amd import msel  # noqa: E402
+import synth  # noqa: E402
+from oracle import msel as om  # noqa: E402
+from oracle import ref  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda:0")
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def nerr(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("n,p,ld", [(1, 1, 1), (5, 3, 3), (77, 1024, 1100), (1000, 257, 257), (4099, 64, 80)])
+def test_row_moments(n, p, ld):
+    log(f"row_moments n={n} p={p} ld={ld}")
+    rng = np.random.default_rng([n, p])
+    Xf = (rng.standard_normal((n, ld)) * rng.uniform(0.1, 10, (n, 1))).astype(np.float32)
+    X = to_dev(Xf)[:, :p]
+    out = msel.row_moments(X)
+    torch.cuda.synchronize()
+    ref_m = om.row_moments(Xf[:, :p])
+    for c in range(3):
+        assert nerr(out.cpu().numpy()[:, c], ref_m[:, c]) < 1e-12
+    assert np.array_equal(out.cpu().numpy()[:, 2], ref_m[:, 2])  # max is exact
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (7, 13), (1024, 1024), (3, 100003)])
+def test_frob_diff(shape):
+    log(f"frob_diff {shape}")
+    rng = np.random.default_rng(shape[1])
+    A = rng.standard_normal(shape)
+    B = A + 1e-3 * rng.standard_normal(shape)
+    out = msel.frob_diff(to_dev(A), to_dev(B)).cpu().numpy()
+    d2, b2 = om.frob_diff(A, B)
+    assert out[0] == pytest.approx(d2, rel=1e-12)
+    assert out[1] == pytest.approx(b2, rel=1e-12)
+    same = msel.frob_diff(to_dev(B), to_dev(B)).cpu().numpy()
+    assert same[0] == 0.0 and same[1] == pytest.approx(b2, rel=1e-12)
+
+
+def _labels_agree(m_gpu, m_orc, Y, t):
+    if m_gpu == m_orc:
+        return True
+    # accepted only at a boundary: the oracle's error at the GPU's m within 1e-5 of t^2
+    lo = min(m_gpu, m_orc)
+    return abs(om.expected_e2(Y, lo) - t * t) <= 1e-5 * t * t and abs(m_gpu - m_orc) == 1
+
+
+MSEL_CASES = [(64, 256, 37, 0.3, 11), (256, 2048, 300, 0.1, 12), (128, 1000, 2, 0.2, 13), (1024, 8192, 512, 0.1, 14)]
+
+
+@pytest.mark.parametrize("p,n,nsub,t,blk", MSEL_CASES)
+def test_msel_label_and_exact_covariance(p, n, nsub, t, blk):
+    log(f"msel_label p={p} n={n} t={t}")
+    Xn, prm = synth.msel_block_numpy(0, blk, p=p, n=n)
+    ctx = msel.MselContext(p=p, n=n, seed=3)
+    C = torch.empty((p, p), dtype=torch.float64, device="cuda")
+    m = int(ctx.label(to_dev(Xn), target=t, C_out=C)[0])
+    Y = om.transform(Xn, ref.signs(3, p))
+    m_orc = om.label_m(Y, t)
+    log(f"  label gpu {m} oracle {m_orc} (r={prm['r']}, amp={prm['amp']:.0f})")
+    assert _labels_agree(m, m_orc, Y, t)
+    Ce = Y.T @ Y / n
+    Cg = C.cpu().numpy()
+    assert np.linalg.norm(Cg - Ce) / np.linalg.norm(Ce) < 1e-5
+    assert np.array_equal(Cg, Cg.T)
+
+
+@pytest.mark.parametrize("p,n,nsub,t,blk", MSEL_CASES)
+def test_msel_features(p, n, nsub, t, blk):
+    log(f"msel_features p={p} n={n} nsub={nsub}")
+    Xn, _ = synth.msel_block_numpy(0, blk, p=p, n=n)
+    Xn[1] = 0.0  # a zero row among the subset
+    ctx = msel.MselContext(p=p, n=n, seed=3)
+    f = ctx.features(to_dev(Xn), nsub=nsub, target=t).cpu().numpy().astype(np.float64)
+    fo = om.features(Xn[:nsub], ref.signs(3, p), n, t)
+    d = np.abs(f - fo)
+    log(f"  max |d| (0..30) {d[:31].max():.2e}; plug-in m gpu {math.exp(f[31]) * p:.1f} oracle "
+        f"{math.exp(fo[31]) * p:.1f}")
+    assert d[:31].max() < 1e-5
+    mg, mo = round(math.exp(f[31]) * p), round(math.exp(fo[31]) * p)
+    assert abs(mg - mo) <= 1
+
+
+def test_msel_label_zero_block_and_argument_errors():
+    ctx = msel.MselContext(p=64, n=100, seed=0)
+    Z = torch.zeros((100, 64), dtype=torch.float32, device="cuda")
+    assert int(ctx.label(Z, target=0.1)[0]) == 2
+    f = ctx.features(Z, nsub=50).cpu().numpy()
+    assert not np.isfinite(f[0])
+    with pytest.raises(pds.PdsError):
+        ctx.features(Z, nsub=1)
+    with pytest.raises(pds.PdsError):
+        ctx.label(Z, target=0.0)
+    import ctypes
+
+    from paper_1511_00152_amd._lib import PDS_E_M, lib
+
+    b = ctypes.c_size_t(0)
+    half = pds.Plan(64, 32, 0, pds.PDS_F32)  # the selector needs m = p
+    assert lib().pds_msel_workspace_size(half.handle, 100, ctypes.byref(b)) == PDS_E_M
+
+
+def _mlp_case(B, seed):
+    rng = np.random.default_rng(seed)
+    P = (rng.standard_normal(om.N_PARAMS) * 0.2).astype(np.float32)
+    F = rng.standard_normal((B, 32)).astype(np.float32) * 3
+    mu = (rng.standard_normal(32) * 0.5).astype(np.float32)
+    sd = (1.0 + rng.random(32)).astype(np.float32)
+    tgt = rng.standard_normal(B).astype(np.float32)
+    return P, F, mu, sd, tgt
+
+
+@pytest.mark.parametrize("B", [1, 3, 37, 1000])
+def test_mlp_forward_backward(B):
+    log(f"mlp forward/backward B={B}")
+    P, F, mu, sd, tgt = _mlp_case(B, B)
+    dP, dF, dmu, dsd, dt = map(to_dev, (P, F, mu, sd, tgt))
+    pred, acts = msel.mlp_forward(dP, dF, dmu, dsd)
+    grad, loss = msel.mlp_backward(dP, acts, pred, dt, 0.85)
+    y, (xn, h1, h2) = om.mlp_forward(P, F, mu, sd)
+    g, L = om.mlp_grad(P, F, mu, sd, tgt, 0.85)
+    a = acts.cpu().numpy()
+    assert nerr(pred.cpu().numpy(), y) < 1e-5
+    assert nerr(a[:, :32], xn) < 1e-6
+    assert nerr(a[:, 32:96], h1) < 1e-5
+    assert nerr(a[:, 96:160], h2) < 1e-5
+    assert np.linalg.norm(grad.cpu().numpy() - g) / np.linalg.norm(g) < 1e-5
+    assert float(loss[0]) == pytest.approx(L, rel=1e-5)
+
+
+def test_mlp_adam_and_pack():
+    P, F, mu, sd, tgt = _mlp_case(64, 5)
+    rng = np.random.default_rng(6)
+    dP = to_dev(P)
+    m1 = torch.zeros_like(dP)
+    m2 = torch.zeros_like(dP)
+    Po, a1, a2 = P.astype(np.float64), np.zeros(om.N_PARAMS), np.zeros(om.N_PARAMS)
+    for step in range(1, 5):
+        g = (rng.standard_normal(om.N_PARAMS) * 10.0 ** rng.uniform(-4, 0, om.N_PARAMS)).astype(np.float32)
+        msel.mlp_adam(dP, to_dev(g), m1, m2, step, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8)
+        Po, a1, a2 = om.adam_step(Po, g.astype(np.float64), a1, a2, step, 1e-2, 0.9, 0.999, 1e-8)
+    assert nerr(dP.cpu().numpy(), Po) < 1e-5
+    pb = msel.mlp_pack_bf16(dP).cpu().numpy().view(np.uint16)
+    expect = om.bf16_round(dP.cpu().numpy()).view(np.uint32) >> 16
+    assert np.array_equal(pb.astype(np.uint32), expect)
+
+
+def test_training_steps_follow_the_oracle():
+    B = 256
+    P, F, mu, sd, tgt = _mlp_case(B, 21)
+    dP, dF, dmu, dsd, dt = map(to_dev, (P, F, mu, sd, tgt))
+    m1 = torch.zeros_like(dP)
+    m2 = torch.zeros_like(dP)
+    Po, a1, a2 = P.astype(np.float64), np.zeros(om.N_PARAMS), np.zeros(om.N_PARAMS)
+    losses = []
+    for step in range(1, 6):
+        pred, acts = msel.mlp_forward(dP, dF, dmu, dsd)
+        grad, loss = msel.mlp_backward(dP, acts, pred, dt, 0.9)
+        msel.mlp_adam(dP, grad, m1, m2, step, lr=1e-3)
+        losses.append(float(loss[0]))
+        g, L = om.mlp_grad(Po, F, mu, sd, tgt, 0.9)
+        Po, a1, a2 = om.adam_step(Po, g, a1, a2, step, 1e-3, 0.9, 0.999, 1e-8)
+        assert losses[-1] == pytest.approx(L, rel=1e-4)
+    assert nerr(dP.cpu().numpy(), Po) < 1e-4
+    assert losses[-1] < losses[0]
+
+
+def test_predict_bf16():
+    B = 2000
+    P, F, mu, sd, _ = _mlp_case(B, 9)
+    P[6336] = -1.5  # output bias: gammas near exp(-1.5)
+    F[7, 3] = np.nan
+    F[8, 0] = np.inf
+    dP = to_dev(P)
+    g = msel.msel_predict(msel.mlp_pack_bf16(dP), to_dev(F), to_dev(mu), to_dev(sd), 1e-30, 1e30, 0.2)
+    g = g.cpu().numpy().astype(np.float64)
+    go, y = om.mlp_predict_bf16(P, F, mu, sd, 1e-30, 1e30, 0.2)
+    assert g[7] == pytest.approx(0.2) and g[8] == pytest.approx(0.2)
+    ok = np.isfinite(F).all(1)
+    d = np.abs(np.log(g[ok]) - np.log(go[ok]))
+    log(f"predict bf16: max |dlog gamma| {d.max():.2e}, 99th pct {np.quantile(d, 0.99):.2e}")
+    assert np.quantile(d, 0.99) < 1e-4
+    assert d.max() < 1e-2
+    # clamping
+    gc = msel.msel_predict(msel.mlp_pack_bf16(dP), to_dev(F), to_dev(mu), to_dev(sd), 0.3, 0.5, 0.9).cpu().numpy()
+    assert gc.min() >= 0.3 - 1e-7 and gc.max() <= 0.5 + 1e-7 and gc[7] == pytest.approx(0.5)
+
+
+@pytest.mark.skipif(not os.path.exists(msel.WEIGHTS), reason="selector weights not trained")
+def test_shipped_selector_on_fresh_blocks():
+    """The committed weights on blocks of a stream used neither for training
+    nor for the held-out evaluation: realized error at the chosen m against
+    the target, and the chosen m against the oracle's label."""
+    sel = msel.MSelector.load()
+    cfg = synth.MSEL
+    p, n, t = cfg["p"], cfg["n"], cfg["target"]
+    ctx = msel.MselContext(p=p, n=n, seed=0)
+    ok = 0
+    ratios = []
+    for b in range(8):
+        Xn, prm = synth.msel_block_numpy(9, b)
+        X = to_dev(Xn)
+        m = sel.choose_m(ctx, X)
+        C = torch.empty((p, p), dtype=torch.float64, device="cuda")
+        m_lab = int(ctx.label(X, target=t, C_out=C)[0])
+        pl = pds.Plan(p, m, 0, pds.PDS_F32)
+        vals, idx = pds.compress(pl, X)
+        Ch = pds.covariance(pl, vals, idx)
+        d = msel.frob_diff(Ch, C).cpu().numpy()
+        err = math.sqrt(d[0] / d[1])
+        log(f"  block {b}: r={prm['r']} amp={prm['amp']:.0f} m={m} label={m_lab} err={err:.4f}")
+        ok += err <= t
+        ratios.append(m / m_lab)
+    assert ok >= 6
+    assert 0.5 < float(np.median(ratios)) < 2.0
