@@ -183,6 +183,99 @@ def cpu_baseline_and_errors(pds, X, p, m, nsamp, variants):
     return base, errs
 
 
+def run_batch(pds, steps, warmup, single_baseline=True):
+    """The batched form on the 256-set workload: one persistent compression
+    launch and T graph-captured K-means rounds per step; per-set single-plan
+    calls timed once for comparison."""
+    import torch
+
+    import synth
+    from paper_1511_00152_amd.batch import Batch
+
+    name = "batch256_f32"
+    w = synth.WORKLOADS[name]
+    T = w["T"]
+    params = synth.batch_params(name)
+    log(f"generating {name}: {len(params)} sets, {sum(q['n'] for q in params)} samples")
+    sets = [dict(X=synth.batch_set_torch(name, i, q), m=q["m"], K=q["K"], seed=q["seed"]) for i, q in enumerate(params)]
+    torch.cuda.synchronize()
+    b = Batch(sets, T=T)
+    b.compress()
+    b.init_centers()
+    t0 = time.perf_counter()
+    b.autotune()
+    t_tune = time.perf_counter() - t0
+    info = b.info()
+    lib = pds.lib()
+
+    def step():
+        b.compress()
+        b.init_centers()
+        b.kmeans()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lib.pds_profile_enable(1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    lib.pds_profile_enable(0)
+    kern = profile_report(lib)
+    ns = sum(q["n"] for q in params)
+    comp_bytes = sum(q["n"] * (4 * q["p"] + 6 * q["m"]) for q in params)
+    round_bytes = sum(q["n"] * (6 * q["m"] + 4) for q in params)
+    t_c = kern["batch_compress"]["avg_ms"] / 1e3
+    t_k = kern["batch_kmeans_graph"]["avg_ms"] / 1e3
+    out = {
+        "workload": f"{name}: {len(params)} sets, n in [1e3, 1e5], p in {{128..2048}}, K in [2, 50], "
+                    f"gamma in [0.02, 0.2], mixture data, T={T}; step = compress + seed + T K-means rounds",
+        "sets": len(params), "samples": ns, "input_gb": sum(q["n"] * q["p"] * 4 for q in params) / 1e9,
+        "T": T, "ms_per_step": wall * 1e3, "samples_per_s": ns / wall,
+        "compress": {"ms": t_c * 1e3, "algorithmic_gb": comp_bytes / 1e9, "achieved_gbs": comp_bytes / t_c / 1e9,
+                     "frac_hbm": comp_bytes / t_c / 1e9 / PEAK_HBM_GBS},
+        "kmeans": {"ms": t_k * 1e3, "ms_per_round": t_k * 1e3 / T, "algorithmic_gb_per_round": round_bytes / 1e9,
+                   "achieved_gbs": T * round_bytes / t_k / 1e9,
+                   "frac_hbm": T * round_bytes / t_k / 1e9 / PEAK_HBM_GBS},
+        "launches_per_step": {"kernels": 2, "graphs": 1, "graph_kernels": int(info["graph_kernels"])},
+        "host_syncs_per_step": 0,
+        "tuning": {k: info[k] for k in ("spw", "cchunk")}, "autotune_s": t_tune,
+    }
+    if single_baseline:
+        # the same work as per-set single-plan calls (eager, one set after another)
+        plans = [pds.Plan(q["p"], q["m"], seed=q["seed"], prec=pds.PDS_F32) for q in params]
+        bufs = []
+        for q, pl, st in zip(params, plans, b.sets):
+            ws = pl.workspace(pds.PDS_OP_KMEANS, q["n"], q["K"], device="cuda")
+            bufs.append((ws, st["centers"].clone(), torch.empty_like(st["centers"])))
+
+        def single():
+            launches = 0
+            for q, pl, st, (ws, ca, cb) in zip(params, plans, b.sets, bufs):
+                pds.compress(pl, st["X"], vals=st["vals"], idx=st["idx"])
+                a, c = ca, cb
+                for r in range(T):
+                    pds.kmeans_step(pl, st["vals"], st["idx"], a, out=c, assign=st["assign"],
+                                    objective=st["objective"][r:r + 1], ws=ws)
+                    a, c = c, a
+                launches += 2 + 2 * T
+            return launches
+
+        single()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        launches = single()
+        torch.cuda.synchronize()
+        t_single = time.perf_counter() - t0
+        out["single_plan_calls"] = {"ms": t_single * 1e3, "kernel_launches": launches,
+                                    "batched_speedup": t_single / wall}
+    b.close()
+    del sets
+    return out
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the FETCH_SIZE /
     WRITE_SIZE counters of a profiled run."""
@@ -206,6 +299,8 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched-form leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -222,6 +317,9 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.batch_only:
+        print(json.dumps({"batch": run_batch(pds, args.steps, args.warmup)}), flush=True)
+        return
     name = "spiked4096_f32"
     w = synth.WORKLOADS[name]
     p = w["p"]
@@ -277,6 +375,11 @@ def main():
         out["errors"] = errs
     else:
         out["cpu_baseline"] = None
+    if not args.no_batch:
+        del X
+        torch.cuda.empty_cache()
+        out["batch"] = run_batch(pds, max(1, min(args.steps, 5)), max(1, min(args.warmup, 2)))
+        log(f"batch: {json.dumps(out['batch'])}")
     print(json.dumps(out), flush=True)
 
 

@@ -541,8 +541,7 @@ pds_status pds_msel_predict(const uint16_t* params_bf16, const float* feats, con
 namespace {
 
 constexpr int kBatchSpwCand[3] = {16, 32, 64};
-constexpr int kBatchAchunkCand[2] = {256, 1024};
-constexpr int kBatchCchunkCand[2] = {4096, 16384};
+constexpr int kBatchCchunkCand[3] = {4096, 16384, 65536};
 
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -551,7 +550,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Workspace offsets (bytes) of the batch tables; sized for the smallest
 // candidate chunks so that re-tuning never grows the workspace.
 struct BatchOffsets {
-    size_t sets, gp, ap, cp, up, ct, cmax, pobj, psum, pcnt, total;
+    size_t sets, gp, ap, cp, up, tp, ct, cmax, pobj, psum, pcnt, vt, it, dist, rlist, rcount, total;
 };
 
 int accum_kg(int K, int p)
@@ -565,11 +564,13 @@ int accum_kg(int K, int p)
 BatchOffsets batch_offsets(const pds_batch_s& b)
 {
     const size_t ns = b.descs.size();
-    size_t ct = 0, pobj = 0, part = 0;
+    size_t ct = 0, pobj = 0, part = 0, tiles = 0, nsamp = 0;
     for (const auto& d : b.descs) {
         const int64_t KP = (int64_t)d.K * d.p;
         ct += (size_t)KP;
-        pobj += (size_t)cdiv(d.n, kBatchAchunkCand[0]);
+        tiles += (size_t)cdiv(d.n, 64) * 64 * (size_t)((d.m + 7) & ~7);
+        pobj += (size_t)cdiv(d.n, kBatchCchunkCand[0]);  // one objective partial per accumulation chunk
+        nsamp += (size_t)d.n;
         part += (size_t)cdiv(d.n, kBatchCchunkCand[0]) * (size_t)KP;
     }
     BatchOffsets o;
@@ -584,6 +585,8 @@ BatchOffsets batch_offsets(const pds_batch_s& b)
     off += al256((ns + 1) * 8);
     o.up = off;
     off += al256((ns + 1) * 8);
+    o.tp = off;
+    off += al256((ns + 1) * 8);
     o.ct = off;
     off += al256(ct * 4);
     o.cmax = off;
@@ -594,6 +597,16 @@ BatchOffsets batch_offsets(const pds_batch_s& b)
     off += al256((part > 0 ? part : 1) * 4);
     o.pcnt = off;
     off += al256((part > 0 ? part : 1) * 4);
+    o.vt = off;
+    off += al256((tiles > 0 ? tiles : 1) * 4);
+    o.it = off;
+    off += al256((tiles > 0 ? tiles : 1) * 2);
+    o.dist = off;
+    off += al256((nsamp > 0 ? nsamp : 1) * 8);
+    o.rlist = off;
+    off += al256((nsamp > 0 ? nsamp : 1) * 8);
+    o.rcount = off;
+    off += 256;
     o.total = off;
     return o;
 }
@@ -610,7 +623,8 @@ void batch_build(const pds_batch_s& b, const pds::BatchTuning& tu, unsigned char
     int64_t* ap = reinterpret_cast<int64_t*>(img.data() + o.ap);
     int64_t* cp = reinterpret_cast<int64_t*>(img.data() + o.cp);
     int64_t* up = reinterpret_cast<int64_t*>(img.data() + o.up);
-    int64_t g = 0, a = 0, c = 0, u = 0, ct = 0, part = 0;
+    int64_t* tp = reinterpret_cast<int64_t*>(img.data() + o.tp);
+    int64_t g = 0, a = 0, c = 0, u = 0, ct = 0, part = 0, tl = 0, telem = 0, dsum = 0, pch = 0;
     for (int i = 0; i < ns; ++i) {
         const pds_batch_desc& d = b.descs[i];
         pds::BatchSet& S = sets[i];
@@ -632,13 +646,22 @@ void batch_build(const pds_batch_s& b, const pds::BatchTuning& tu, unsigned char
         S.seed = d.seed;
         const int64_t KP = (int64_t)d.K * d.p;
         S.aitem0 = a;
-        S.naitems = cdiv(d.n, tu.achunk);
+        S.naitems = cdiv(d.n, pds::kBatchAssignSamples);
         S.ct_off = ct;
         S.part_off = part;
         S.cchunk = tu.cchunk;
         S.nacc = cdiv(d.n, tu.cchunk);
         S.kg = accum_kg(d.K, d.p);
         S.ngk = (int)cdiv(d.K, S.kg);
+        S.ntiles = cdiv(d.n, 64);
+        S.tile_off = telem;
+        S.dist_off = dsum;
+        dsum += d.n;
+        S.pchunk0 = pch;
+        pch += S.nacc;
+        tp[i] = tl;
+        tl += S.ntiles;
+        telem += S.ntiles * 64 * (int64_t)((d.m + 7) & ~7);
         gp[i] = g;
         ap[i] = a;
         cp[i] = c;
@@ -651,6 +674,7 @@ void batch_build(const pds_batch_s& b, const pds::BatchTuning& tu, unsigned char
         part += S.nacc * KP;
     }
     gp[ns] = g;
+    tp[ns] = tl;
     ap[ns] = a;
     cp[ns] = c;
     up[ns] = u;
@@ -667,6 +691,14 @@ void batch_build(const pds_batch_s& b, const pds::BatchTuning& tu, unsigned char
     t.pobj = reinterpret_cast<double*>(ws + o.pobj);
     t.psum = reinterpret_cast<float*>(ws + o.psum);
     t.pcnt = reinterpret_cast<uint32_t*>(ws + o.pcnt);
+    t.tprefix = reinterpret_cast<const int64_t*>(ws + o.tp);
+    t.ntiles = tl;
+    t.vt = reinterpret_cast<float*>(ws + o.vt);
+    t.it = reinterpret_cast<uint16_t*>(ws + o.it);
+    t.dist = reinterpret_cast<double*>(ws + o.dist);
+    t.rlist = reinterpret_cast<int64_t*>(ws + o.rlist);
+    t.rcount = reinterpret_cast<uint32_t*>(ws + o.rcount);
+    t.recheck_grid = (int64_t)b.tune.update_grid;
 }
 
 const pds::BatchSet* batch_sets(const pds_batch_s& b) { return reinterpret_cast<const pds::BatchSet*>(b.ws); }
@@ -674,7 +706,7 @@ const pds::BatchSet* batch_sets(const pds_batch_s& b) { return reinterpret_cast<
 void batch_set_grids(pds_batch_s& b, const pds::DeviceInfo& dev)
 {
     b.tune.compress_grid = (int64_t)dev.cus * pds::batch_compress_occupancy(b.tune.spw, b.pmax);
-    b.tune.assign_grid = (int64_t)dev.cus * 4;
+    b.tune.assign_grid = (int64_t)dev.cus * 2;
     b.tune.accum_grid = (int64_t)dev.cus * 2;
     b.tune.update_grid = (int64_t)dev.cus * 8;
 }
@@ -698,7 +730,8 @@ hipError_t batch_enqueue_rounds(pds_batch_s& b, hipStream_t s, int T)
 {
     const int ns = (int)b.descs.size();
     const pds::BatchSet* sets = batch_sets(b);
-    hipError_t e = pds::launch_batch_round_prep(sets, ns, b.tables.ct, b.tables.cmax, (T & 1) ? 1 : 0, s);
+    hipError_t e = pds::launch_batch_round_prep(sets, ns, b.tables, (T & 1) ? 1 : 0, s);
+    if (e == hipSuccess) e = pds::launch_batch_tile(sets, ns, b.tables, b.tune.update_grid, s);
     for (int r = 0; r < T && e == hipSuccess; ++r)
         e = pds::launch_batch_round(sets, ns, b.tables, b.tune, (T - 1 - r) & 1, r, s);
     return e;
@@ -767,7 +800,6 @@ pds_status pds_batch_create(pds_batch* out, const pds_batch_desc* descs, int32_t
     b->T = T;
     b->pmax = pmax;
     b->tune.spw = 64;
-    b->tune.achunk = 1024;
     b->tune.cchunk = 16384;
     b->ws_bytes = batch_offsets(*b).total;
     *out = b;
@@ -888,29 +920,27 @@ pds_status pds_batch_autotune(pds_batch b, void* stream)
         }
     }
     b->tune.spw = best_spw;
-    // K-means round: assignment item and accumulation chunk lengths
+    // K-means round: accumulation chunk length
     best = 1e30f;
-    int best_a = b->tune.achunk, best_c = b->tune.cchunk;
-    for (int ac : kBatchAchunkCand) {
+    int best_c = b->tune.cchunk;
+    {
         for (int cc : kBatchCchunkCand) {
             if (e != hipSuccess || b->T == 0) break;
-            b->tune.achunk = ac;
             b->tune.cchunk = cc;
             batch_set_grids(*b, dev);
             e = batch_upload(*b, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e == hipSuccess) e = pds::launch_batch_round_prep(batch_sets(*b), ns, b->tables.ct, b->tables.cmax, 0, s);
+            if (e == hipSuccess) e = pds::launch_batch_round_prep(batch_sets(*b), ns, b->tables, 0, s);
+            if (e == hipSuccess) e = pds::launch_batch_tile(batch_sets(*b), ns, b->tables, b->tune.update_grid, s);
             float ms = 0.0f;
             if (e == hipSuccess)
                 e = timed([&]() { return pds::launch_batch_round(batch_sets(*b), ns, b->tables, b->tune, 1, 0, s); }, ms);
             if (e == hipSuccess && ms < best) {
                 best = ms;
-                best_a = ac;
                 best_c = cc;
             }
         }
     }
-    b->tune.achunk = best_a;
     b->tune.cchunk = best_c;
     batch_set_grids(*b, dev);
     if (e == hipSuccess) e = batch_upload(*b, s);
@@ -929,9 +959,9 @@ pds_status pds_batch_info(pds_batch b, char* buf, size_t len)
     int64_t n = 0;
     for (const auto& d : b->descs) n += d.n;
     snprintf(buf, len,
-             "sets=%d samples=%lld T=%d spw=%d achunk=%d cchunk=%d groups=%lld assign_items=%lld accum_items=%lld "
+             "sets=%d samples=%lld T=%d spw=%d cchunk=%d groups=%lld assign_items=%lld accum_items=%lld "
              "update_items=%lld compress_grid=%lld graph_kernels=%d ws_bytes=%zu",
-             (int)b->descs.size(), (long long)n, b->T, b->tune.spw, b->tune.achunk, b->tune.cchunk,
+             (int)b->descs.size(), (long long)n, b->T, b->tune.spw, b->tune.cchunk,
              (long long)b->tables.ngroups, (long long)b->tables.naitems, (long long)b->tables.ncitems,
              (long long)b->tables.nuitems, (long long)b->tune.compress_grid, b->kernels_per_kmeans, b->ws_bytes);
     return PDS_OK;

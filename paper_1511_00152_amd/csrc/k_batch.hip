@@ -11,14 +11,14 @@
 // values together.  Groups are dealt to the persistent workgroups round-robin.
 //
 // K-means round (three launches):
-//   assign  one thread per sample over items of `achunk` samples: FP32
-//           distances to the set's centers (a transposed FP32 copy), FP64
-//           recheck of near ties as in the single-plan kernel, assignment and
-//           per-item objective partial.
+//   assign  one thread per sample, 1024 samples per workgroup: FP32
+//           distances to the set's centers (a transposed FP32 copy staged
+//           through LDS by blocks of coordinates), FP64 recheck of near ties
+//           as in the single-plan kernel, assignment and objective partial.
 //   accum   one workgroup per (set, sample chunk, cluster group): the chunk's
 //           samples whose cluster falls in the group add their kept entries
-//           into LDS sums and counts (one wave per sample), then the group's
-//           K_g x p partial is written out.
+//           into LDS sums and counts (one wave per sample), then the
+//           group's K_g x p partial is written out.
 //   update  one thread per center entry: fixed-order FP64 sum of the chunk
 //           partials, division (zero count keeps the previous value), the
 //           FP32 transposed copy and the largest |center| for the next round;
@@ -117,20 +117,60 @@ __global__ __launch_bounds__(64) void k_batch_compress(const BatchSet* __restric
 // ---------------------------------------------------------------------------
 // K-means
 // ---------------------------------------------------------------------------
-constexpr int kBkThreads = 256;
-constexpr int kBkGroup = 16;
+constexpr int kBkThreads = 256;   // update
+constexpr int kBaThreads = 512;   // assign: one sample per thread
+constexpr int kBaLdsFloats = 32768;  // 128 KB: one assignment workgroup per CU
+constexpr int kBcThreads = 1024;  // accumulate: one sample per thread
 
 __device__ inline const double* round_in(const BatchSet& S, int dir) { return dir ? S.c_a : S.c_b; }
 __device__ inline double* round_out(const BatchSet& S, int dir) { return dir ? S.c_b : S.c_a; }
+
+// Tiles of 64 samples: entries a = 8 c + u of lane (sample) r of tile t sit at
+// ((t mp/8 + c) 64 + r) 8 + u, mp = m rounded up to a multiple of 8, so one
+// thread per sample fetches eight entries with one 16-byte load of
+// coordinates and two of values, and a wave's loads are contiguous.  Entries
+// past m and lanes past n hold coordinate 0, value 0 (never used).
+__device__ inline int64_t tile_base(const BatchSet& S, int64_t t)
+{
+    return S.tile_off + t * (int64_t)((S.m + 7) & ~7) * 64;
+}
+
+__global__ __launch_bounds__(256) void k_batch_tile(const BatchSet* __restrict__ sets, int nsets,
+                                                    const int64_t* __restrict__ tprefix, int64_t ntiles,
+                                                    float* __restrict__ vt, uint16_t* __restrict__ it)
+{
+    for (int64_t g = blockIdx.x; g < ntiles; g += gridDim.x) {
+        const int d = owner(tprefix, nsets, g);
+        const BatchSet& S = sets[d];
+        const int64_t t = g - tprefix[d];
+        const int m = S.m;
+        const int mp = (m + 7) & ~7;
+        const int64_t r0 = t * 64;
+        const float* src_v = S.vals + r0 * (int64_t)m;
+        const uint16_t* src_i = S.idx + r0 * (int64_t)m;
+        float* dv = vt + tile_base(S, t);
+        uint16_t* di = it + tile_base(S, t);
+        const int64_t tot = (int64_t)mp * 64;
+        for (int64_t e = threadIdx.x; e < tot; e += 256) {
+            const int u = (int)(e & 7);
+            const int r = (int)((e >> 3) & 63);
+            const int a = (int)(e >> 9) * 8 + u;
+            const bool ok = r0 + r < S.n && a < m;
+            dv[e] = ok ? src_v[(int64_t)r * m + a] : 0.0f;
+            di[e] = ok ? src_i[(int64_t)r * m + a] : (uint16_t)0;
+        }
+    }
+}
 
 // prep: one workgroup per set; FP32 transposed centers, largest |center|, and
 // (odd round counts) the second center buffer
 __global__ __launch_bounds__(256) void k_batch_prep(const BatchSet* __restrict__ sets, int nsets,
                                                     float* __restrict__ ct, uint32_t* __restrict__ cmax0,
-                                                    int copy_to_b)
+                                                    uint32_t* __restrict__ rcount, int copy_to_b)
 {
     __shared__ uint32_t red[256];
     const int d = blockIdx.x;
+    if (d == 0 && threadIdx.x == 0) *rcount = 0u;
     const BatchSet& S = sets[d];
     const int64_t KP = (int64_t)S.K * S.p;
     float* c = ct + S.ct_off;
@@ -164,101 +204,198 @@ __device__ inline double batch_dist_f64(const float* __restrict__ v, const uint1
     return dd;
 }
 
-__global__ __launch_bounds__(kBkThreads) void k_batch_assign(const BatchSet* __restrict__ sets, int nsets,
-                                                             const int64_t* __restrict__ aprefix, int64_t nitems,
-                                                             int achunk, const float* __restrict__ ct,
-                                                             const uint32_t* __restrict__ cmax_cur,
-                                                             uint32_t* __restrict__ cmax_next, double* __restrict__ pobj,
-                                                             int dir)
+// Assignment of one item (kBaThreads samples, one per thread).  The set's
+// FP32 centers are staged through LDS a window of KW clusters at a time, for
+// all p coordinates (row l holds the window's centers at coordinate l, padded
+// against bank conflicts when it fits); each thread streams its sample's kept
+// entries once per window, so every distance accumulates its terms in
+// ascending coordinate order exactly as the single-plan kernel does.
+template <int KW>
+__device__ inline void batch_assign_item(const BatchSet& S, int set, int64_t j, const float* __restrict__ ct,
+                                         float cmax, const float* __restrict__ vt, const uint16_t* __restrict__ it,
+                                         float* __restrict__ lc, double* __restrict__ dist,
+                                         int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
 {
-    __shared__ double red[kBkThreads / 64];
+    const int K = S.K, p = S.p, m = S.m;
+    const int RS = (p * (KW + 4) <= kBaLdsFloats) ? KW + 4 : KW;
+    const int64_t i = j * kBaThreads + threadIdx.x;
+    const bool live = i < S.n;
+    // this sample's entries in its tile: chunk c (eight entries) at element tb + 512 c
+    const int64_t tl = i >> 6;
+    const int64_t tb = tile_base(S, tl) + (i & 63) * 8;
+    const uint4* ti = reinterpret_cast<const uint4*>(it + tb);  // 8 coordinates per chunk
+    const float4* tv = reinterpret_cast<const float4*>(vt + tb);  // 2 x 4 values per chunk
+    const int nch = (m + 7) >> 3;
+    const float* cT = ct + S.ct_off;
+    float best = INFINITY, second = INFINITY, sv = 0.0f;
+    int bestk = 0;
+    for (int kc = 0; kc < K; kc += KW) {
+        __syncthreads();  // the previous window's reads are done
+        for (int e = threadIdx.x; e < p * KW; e += kBaThreads) {
+            const int r = e / KW, k = e - r * KW;
+            lc[r * RS + k] = (kc + k < K) ? cT[(int64_t)r * K + kc + k] : 0.0f;
+        }
+        __syncthreads();
+        float d[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) d[q] = 0.0f;
+        if (live) {
+            // a ring of four chunks in flight: chunk c + 4 is requested as soon
+            // as chunk c has been used
+            uint4 I[4];
+            float4 A[4], Bv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (r < nch) {
+                    I[r] = ti[(int64_t)r * 64];
+                    A[r] = tv[(int64_t)r * 128];
+                    Bv[r] = tv[(int64_t)r * 128 + 1];
+                }
+            }
+            for (int c0 = 0; c0 < nch; c0 += 4) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = c0 + r;
+                    if (c < nch) {
+                        const uint32_t iw[4] = {I[r].x, I[r].y, I[r].z, I[r].w};
+                        const float xw[8] = {A[r].x, A[r].y, A[r].z, A[r].w, Bv[r].x, Bv[r].y, Bv[r].z, Bv[r].w};
+                        if (c + 4 < nch) {
+                            // a chunk spans 64 lanes x 8 entries: 64 uint4 of coordinates, 128 float4 of values
+                            I[r] = ti[(int64_t)(c + 4) * 64];
+                            A[r] = tv[(int64_t)(c + 4) * 128];
+                            Bv[r] = tv[(int64_t)(c + 4) * 128 + 1];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            if (c * 8 + u < m) {
+                                const int l = (int)((iw[u >> 1] >> ((u & 1) * 16)) & 0xFFFFu);
+                                const float x = xw[u];
+                                if (kc == 0) sv = fmaf(x, x, sv);
+                                const float* cc = lc + l * RS;
+#pragma unroll
+                                for (int q = 0; q < KW; ++q) {
+                                    const float diff = x - cc[q];
+                                    d[q] = fmaf(diff, diff, d[q]);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KW; ++q) {
+            if (kc + q < K) {
+                if (d[q] < best) {
+                    second = best;
+                    best = d[q];
+                    bestk = kc + q;
+                } else if (d[q] < second) {
+                    second = d[q];
+                }
+            }
+        }
+    }
+    if (!live) return;
+    S.assign[i] = bestk;
+    dist[S.dist_off + i] = (double)best;
+    if (K > 1) {
+        // |d32 - d| <= u (8 (sum v^2 + sum mu^2) + 1.01 m d), u = 2^-24, per
+        // candidate; two candidates, factor 2 of slack.  Closer calls are
+        // decided in FP64 by k_batch_recheck.
+        const float u = 5.9604645e-8f;
+        const float mf = (float)m;
+        const float bound = 2.0f * u * (16.0f * (sv + mf * cmax * cmax) + 1.01f * mf * (best + second));
+        if (!(second - best > bound)) {
+            const uint32_t slot = atomicAdd(rcount, 1u);
+            rlist[slot] = ((int64_t)set << 40) | i;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBaThreads) void k_batch_assign(const BatchSet* __restrict__ sets, int nsets,
+                                                             const int64_t* __restrict__ aprefix, int64_t nitems,
+                                                             const float* __restrict__ ct,
+                                                             const float* __restrict__ vtile,
+                                                             const uint16_t* __restrict__ itile,
+                                                             const uint32_t* __restrict__ cmax_cur,
+                                                             uint32_t* __restrict__ cmax_next,
+                                                             double* __restrict__ dist, int64_t* __restrict__ rlist,
+                                                             uint32_t* __restrict__ rcount)
+{
+    extern __shared__ __align__(16) float lc[];  // kBaLdsFloats
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int d = owner(aprefix, nsets, it);
         const BatchSet& S = sets[d];
         const int64_t j = it - aprefix[d];
         if (j == 0 && threadIdx.x == 0) cmax_next[d] = 0u;
-        const double* cin = round_in(S, dir);
-        const float* cT = ct + S.ct_off;
         const float cmax = __uint_as_float(cmax_cur[d]);
-        const int K = S.K, m = S.m;
-        const int64_t i = j * achunk + threadIdx.x;
-        double obj = 0.0;
-        for (int64_t ii = i; ii < S.n && ii < (j + 1) * (int64_t)achunk; ii += kBkThreads) {
-            const float* v = S.vals + ii * (int64_t)m;
-            const uint16_t* ix = S.idx + ii * (int64_t)m;
-            float best = INFINITY, second = INFINITY, sv = 0.0f;
-            int bestk = 0;
-            for (int k0 = 0; k0 < K; k0 += kBkGroup) {
-                float dk[kBkGroup];
-#pragma unroll
-                for (int q = 0; q < kBkGroup; ++q) dk[q] = 0.0f;
-                const int kn = (K - k0) < kBkGroup ? (K - k0) : kBkGroup;
-                for (int a = 0; a < m; ++a) {
-                    const float x = v[a];
-                    const float* c = cT + (int64_t)ix[a] * K + k0;
-                    if (k0 == 0) sv = fmaf(x, x, sv);
-#pragma unroll
-                    for (int q = 0; q < kBkGroup; ++q) {
-                        if (q < kn) {
-                            const float diff = x - c[q];
-                            dk[q] = fmaf(diff, diff, dk[q]);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kBkGroup; ++q) {
-                    if (q < kn) {
-                        if (dk[q] < best) {
-                            second = best;
-                            best = dk[q];
-                            bestk = k0 + q;
-                        } else if (dk[q] < second) {
-                            second = dk[q];
-                        }
-                    }
-                }
-            }
-            double dsel = (double)best;
-            if (K > 1) {
-                // |d32 - d| <= u (8 (sum v^2 + sum mu^2) + 1.01 m d), u = 2^-24,
-                // per candidate; two candidates, factor 2 of slack
-                const float u = 5.9604645e-8f;
-                const float mf = (float)m;
-                const float bound = 2.0f * u * (16.0f * (sv + mf * cmax * cmax) + 1.01f * mf * (best + second));
-                if (!(second - best > bound)) {
-                    double b64 = batch_dist_f64(v, ix, m, cin);
-                    int bk = 0;
-                    for (int k = 1; k < K; ++k) {
-                        const double dk = batch_dist_f64(v, ix, m, cin + (int64_t)k * S.p);
-                        if (dk < b64) {
-                            b64 = dk;
-                            bk = k;
-                        }
-                    }
-                    bestk = bk;
-                    dsel = b64;
-                }
-            }
-            S.assign[ii] = bestk;
-            obj += dsel;
+        // cluster window: the smallest of 8 / 16 / 32 covering K (32 for larger
+        // K) that fits all p coordinates in LDS
+        int kw = S.K <= 8 ? 8 : (S.K <= 16 ? 16 : 32);
+        while (kw > 8 && S.p * kw > kBaLdsFloats) kw >>= 1;
+        switch (kw) {
+            case 8: batch_assign_item<8>(S, d, j, ct, cmax, vtile, itile, lc, dist, rlist, rcount); break;
+            case 16: batch_assign_item<16>(S, d, j, ct, cmax, vtile, itile, lc, dist, rlist, rcount); break;
+            default: batch_assign_item<32>(S, d, j, ct, cmax, vtile, itile, lc, dist, rlist, rcount); break;
         }
-        // fixed-order workgroup sum of the objective
-        for (int off = 32; off > 0; off >>= 1) obj += __shfl_down(obj, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = obj;
-        __syncthreads();
-        if (threadIdx.x == 0) pobj[S.aitem0 + j] = red[0] + red[1] + red[2] + red[3];
-        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(kBkThreads) void k_batch_accum(const BatchSet* __restrict__ sets, int nsets,
+// FP64 decision for the samples the assignment flagged: one wave per sample,
+// lanes over clusters; each lane sums its distance in the oracle's order
+// (ascending kept coordinate, fma), ties go to the lowest k.
+__global__ __launch_bounds__(256) void k_batch_recheck(const BatchSet* __restrict__ sets,
+                                                       const int64_t* __restrict__ rlist,
+                                                       const uint32_t* __restrict__ rcount,
+                                                       double* __restrict__ dist, int dir)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t cnt = *rcount;
+    for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < cnt; e += nw) {
+        const int64_t code = rlist[e];
+        const int d = (int)(code >> 40);
+        const int64_t i = code & (((int64_t)1 << 40) - 1);
+        const BatchSet& S = sets[d];
+        const int m = S.m, p = S.p;
+        const float* v = S.vals + i * (int64_t)m;
+        const uint16_t* ix = S.idx + i * (int64_t)m;
+        const double* cin = round_in(S, dir);
+        double bd = INFINITY;
+        int bk = 0x7fffffff;
+        for (int k = lane; k < S.K; k += 64) {
+            const double dk = batch_dist_f64(v, ix, m, cin + (int64_t)k * p);
+            if (dk < bd) {  // k ascends within a lane, so ties keep the lower k
+                bd = dk;
+                bk = k;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double od = __shfl_xor(bd, off, 64);
+            const int ok = __shfl_xor(bk, off, 64);
+            if (od < bd || (od == bd && ok < bk)) {
+                bd = od;
+                bk = ok;
+            }
+        }
+        if (lane == 0) {
+            S.assign[i] = bk;
+            dist[S.dist_off + i] = bd;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBcThreads) void k_batch_accum(const BatchSet* __restrict__ sets, int nsets,
                                                             const int64_t* __restrict__ cprefix, int64_t nitems,
-                                                            float* __restrict__ psum, uint32_t* __restrict__ pcnt)
+                                                            float* __restrict__ psum, uint32_t* __restrict__ pcnt,
+                                                            const double* __restrict__ dist,
+                                                            double* __restrict__ pobj)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kBcThreads / 64];
     float* sums = reinterpret_cast<float*>(smem);
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int d = owner(cprefix, nsets, it);
         const BatchSet& S = sets[d];
@@ -271,7 +408,7 @@ __global__ __launch_bounds__(kBkThreads) void k_batch_accum(const BatchSet* __re
         const int ent = kg * p;
         uint32_t* cnts = reinterpret_cast<uint32_t*>(sums + ent);
         __syncthreads();  // the previous item's LDS reads are done
-        for (int e = threadIdx.x; e < ent; e += kBkThreads) {
+        for (int e = threadIdx.x; e < ent; e += kBcThreads) {
             sums[e] = 0.0f;
             cnts[e] = 0u;
         }
@@ -279,25 +416,61 @@ __global__ __launch_bounds__(kBkThreads) void k_batch_accum(const BatchSet* __re
         const int64_t s0 = chunk * S.cchunk;
         int64_t s1 = s0 + S.cchunk;
         if (s1 > S.n) s1 = S.n;
-        for (int64_t base = s0 + (int64_t)wv * 64; base < s1; base += kBkThreads) {
+        if (grp == 0) {
+            // the chunk's objective, in a fixed order
+            double o = 0.0;
+            for (int64_t i = s0 + threadIdx.x; i < s1; i += kBcThreads) o += dist[S.dist_off + i];
+            for (int off = 32; off > 0; off >>= 1) o += __shfl_down(o, off, 64);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = o;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int w = 0; w < kBcThreads / 64; ++w) t += red[w];
+                pobj[S.pchunk0 + chunk] = t;
+            }
+        }
+        // 16 lanes per sample, four samples of the wave at a time
+        const int lane = threadIdx.x & 63;
+        const int sub = lane >> 4, sl = lane & 15;
+        for (int64_t base = s0 + (int64_t)(threadIdx.x >> 6) * 64; base < s1; base += kBcThreads) {
             const int64_t mine = base + lane;
             int c = -1;
             if (mine < s1) c = S.assign[mine];
-            const bool in = c >= k0 && c < k0 + kg;
-            uint64_t mask = __ballot(in);
+            uint64_t mask = __ballot(c >= k0 && c < k0 + kg);
             while (mask) {
-                const int b = __builtin_ctzll(mask);
-                mask &= mask - 1ull;
-                const int cb = __shfl(c, b, 64);
-                const int64_t i = base + b;
-                const float* v = S.vals + i * (int64_t)m;
-                const uint16_t* ix = S.idx + i * (int64_t)m;
-                float* sk = sums + (cb - k0) * p;
-                uint32_t* ck = cnts + (cb - k0) * p;
-                for (int a = lane; a < m; a += 64) {
-                    const int l = ix[a];
-                    atomicAdd(&sk[l], v[a]);
-                    atomicAdd(&ck[l], 1u);
+                // the next (up to) four in-group samples, one per quarter-wave
+                int pick = -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int bsel = mask ? __builtin_ctzll(mask) : -1;
+                    if (bsel >= 0) mask &= mask - 1ull;
+                    if (q == sub) pick = bsel;
+                }
+                const int cb = __shfl(c, pick < 0 ? 0 : pick, 64);
+                if (pick >= 0) {
+                    const int64_t i = base + pick;
+                    const float* v = S.vals + i * (int64_t)m;
+                    const uint16_t* ix = S.idx + i * (int64_t)m;
+                    float* sk = sums + (cb - k0) * p;
+                    uint32_t* ck = cnts + (cb - k0) * p;
+                    // four entries per lane per step: the loads are issued before the atomics
+                    for (int a0 = sl; a0 < m; a0 += 64) {
+                        int l[4];
+                        float x[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int a = a0 + 16 * u;
+                            l[u] = (a < m) ? (int)ix[a] : 0;
+                            x[u] = (a < m) ? v[a] : 0.0f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (a0 + 16 * u < m) {
+                                atomicAdd(&sk[l[u]], x[u]);
+                                atomicAdd(&ck[l[u]], 1u);
+                            }
+                        }
+                    }
                 }
             }
         }
@@ -305,7 +478,7 @@ __global__ __launch_bounds__(kBkThreads) void k_batch_accum(const BatchSet* __re
         const int64_t KP = (int64_t)S.K * p;
         float* ps = psum + S.part_off + chunk * KP + (int64_t)k0 * p;
         uint32_t* pc = pcnt + S.part_off + chunk * KP + (int64_t)k0 * p;
-        for (int e = threadIdx.x; e < ent; e += kBkThreads) {
+        for (int e = threadIdx.x; e < ent; e += kBcThreads) {
             ps[e] = sums[e];
             pc[e] = cnts[e];
         }
@@ -316,7 +489,8 @@ __global__ __launch_bounds__(256) void k_batch_update(const BatchSet* __restrict
                                                       const int64_t* __restrict__ uprefix, int64_t nitems,
                                                       const float* __restrict__ psum, const uint32_t* __restrict__ pcnt,
                                                       float* __restrict__ ct, uint32_t* __restrict__ cmax_next,
-                                                      const double* __restrict__ pobj, int dir, int round)
+                                                      const double* __restrict__ pobj, uint32_t* __restrict__ rcount,
+                                                      int dir, int round)
 {
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int d = owner(uprefix, nsets, it);
@@ -326,9 +500,10 @@ __global__ __launch_bounds__(256) void k_batch_update(const BatchSet* __restrict
         const int64_t e = j * 256 + threadIdx.x;
         if (j == 0 && threadIdx.x == 0) {
             double o = 0.0;
-            for (int64_t a = 0; a < S.naitems; ++a) o += pobj[S.aitem0 + a];
+            for (int64_t a = 0; a < S.nacc; ++a) o += pobj[S.pchunk0 + a];
             S.objective[round] = o;
         }
+        if (it == 0 && threadIdx.x == 0) *rcount = 0u;  // for the next round
         if (e >= KP) continue;
         double sum = 0.0;
         uint64_t cnt = 0;
@@ -387,6 +562,9 @@ hipError_t batch_init_attributes()
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_accum),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kBatchAccumLds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_assign),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kBaLdsFloats * 4);
     return e;
 }
 
@@ -427,10 +605,19 @@ hipError_t launch_batch_init(const BatchSet* sets, int nsets, const int64_t* upr
     return hipGetLastError();
 }
 
-hipError_t launch_batch_round_prep(const BatchSet* sets, int nsets, float* ct, uint32_t* cmax0, int copy_to_b,
+hipError_t launch_batch_tile(const BatchSet* sets, int nsets, const BatchTables& t, int64_t grid, hipStream_t s)
+{
+    if (t.ntiles <= 0) return hipSuccess;
+    if (grid > t.ntiles) grid = t.ntiles;
+    hipLaunchKernelGGL(k_batch_tile, dim3((unsigned)grid), dim3(256), 0, s, sets, nsets, t.tprefix, t.ntiles, t.vt,
+                       t.it);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_round_prep(const BatchSet* sets, int nsets, const BatchTables& t, int copy_to_b,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_prep, dim3(nsets), dim3(256), 0, s, sets, nsets, ct, cmax0, copy_to_b);
+    hipLaunchKernelGGL(k_batch_prep, dim3(nsets), dim3(256), 0, s, sets, nsets, t.ct, t.cmax, t.rcount, copy_to_b);
     return hipGetLastError();
 }
 
@@ -441,22 +628,24 @@ hipError_t launch_batch_round(const BatchSet* sets, int nsets, const BatchTables
     uint32_t* cm_next = t.cmax + (size_t)((round + 1) & 1) * nsets;
     if (t.naitems > 0) {
         int64_t grid = t.naitems < tu.assign_grid ? t.naitems : tu.assign_grid;
-        hipLaunchKernelGGL(k_batch_assign, dim3((unsigned)grid), dim3(kBkThreads), 0, s, sets, nsets, t.aprefix,
-                           t.naitems, tu.achunk, t.ct, cm_cur, cm_next, t.pobj, dir);
+        hipLaunchKernelGGL(k_batch_assign, dim3((unsigned)grid), dim3(kBaThreads), (size_t)kBaLdsFloats * 4, s, sets,
+                           nsets, t.aprefix, t.naitems, t.ct, t.vt, t.it, cm_cur, cm_next, t.dist, t.rlist, t.rcount);
+        hipLaunchKernelGGL(k_batch_recheck, dim3((unsigned)t.recheck_grid), dim3(256), 0, s, sets, t.rlist, t.rcount,
+                           t.dist, dir);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (t.ncitems > 0) {
         int64_t grid = t.ncitems < tu.accum_grid ? t.ncitems : tu.accum_grid;
-        hipLaunchKernelGGL(k_batch_accum, dim3((unsigned)grid), dim3(kBkThreads), (size_t)kBatchAccumLds, s, sets,
-                           nsets, t.cprefix, t.ncitems, t.psum, t.pcnt);
+        hipLaunchKernelGGL(k_batch_accum, dim3((unsigned)grid), dim3(kBcThreads), (size_t)kBatchAccumLds, s, sets,
+                           nsets, t.cprefix, t.ncitems, t.psum, t.pcnt, t.dist, t.pobj);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (t.nuitems > 0) {
         int64_t grid = t.nuitems < tu.update_grid ? t.nuitems : tu.update_grid;
         hipLaunchKernelGGL(k_batch_update, dim3((unsigned)grid), dim3(256), 0, s, sets, nsets, t.uprefix, t.nuitems,
-                           t.psum, t.pcnt, t.ct, cm_next, t.pobj, dir, round);
+                           t.psum, t.pcnt, t.ct, cm_next, t.pobj, t.rcount, dir, round);
     }
     return hipGetLastError();
 }

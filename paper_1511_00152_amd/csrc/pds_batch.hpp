@@ -8,6 +8,7 @@
 
 namespace pds {
 
+constexpr int kBatchAssignSamples = 512;           // samples per assignment item (one per thread)
 constexpr int kBatchAccumLds = 65536;               // LDS of one accumulation workgroup
 constexpr int kBatchAccumEntries = kBatchAccumLds / 8;  // FP32 sum + u32 count per entry
 
@@ -28,6 +29,10 @@ struct BatchSet {
     int64_t ct_off;           // first element of the set's transposed FP32 centers
     int64_t nacc, cchunk;     // accumulation chunks and their length (samples)
     int ngk, kg;              // cluster groups, clusters per group
+    int64_t tile_off;         // first element of the set's 64-sample tiles (vt, it)
+    int64_t ntiles;           // ceil(n / 64)
+    int64_t dist_off;         // first element of the set's per-sample distances
+    int64_t pchunk0;          // first objective partial (one per accumulation chunk)
 };
 
 // Device tables in the workspace (pointers) and their sizes.
@@ -42,11 +47,18 @@ struct BatchTables {
     double* pobj;
     float* psum;
     uint32_t* pcnt;
+    const int64_t* tprefix;  // tiles (nsets + 1)
+    int64_t ntiles;
+    float* vt;               // compressed values tiled by 64 samples: [tile][entry][lane]
+    uint16_t* it;            // kept coordinates, same tiling
+    double* dist;            // distance of each sample to its center (FP32 value, FP64 after a recheck)
+    int64_t* rlist;          // samples to recheck in FP64: set << 40 | sample
+    uint32_t* rcount;        // number of entries in rlist
+    int64_t recheck_grid;
 };
 
 struct BatchTuning {
     int spw;     // samples per compression group
-    int achunk;  // samples per assignment item
     int cchunk;  // samples per accumulation chunk
     int64_t compress_grid, assign_grid, accum_grid, update_grid;
 };
@@ -59,8 +71,10 @@ hipError_t launch_batch_compress(const BatchSet* sets, int nsets, const int64_t*
                                  int pmax, int64_t grid, hipStream_t s);
 hipError_t launch_batch_init(const BatchSet* sets, int nsets, const int64_t* uprefix, int64_t nitems, int64_t grid,
                              hipStream_t s);
-hipError_t launch_batch_round_prep(const BatchSet* sets, int nsets, float* ct, uint32_t* cmax0, int copy_to_b,
+hipError_t launch_batch_round_prep(const BatchSet* sets, int nsets, const BatchTables& t, int copy_to_b,
                                    hipStream_t s);
+// row-major compressed data -> 64-sample tiles (once per K-means call)
+hipError_t launch_batch_tile(const BatchSet* sets, int nsets, const BatchTables& t, int64_t grid, hipStream_t s);
 // dir = 1: round reads c_a, writes c_b; dir = 0: reads c_b, writes c_a
 hipError_t launch_batch_round(const BatchSet* sets, int nsets, const BatchTables& t, const BatchTuning& tu, int dir,
                               int round, hipStream_t s);

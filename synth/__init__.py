@@ -17,6 +17,9 @@ the paper's public datasets are not used):
   spikes, the "few large entries" case that motivates preconditioning):
   p = 1024, K = 10, n = 2^20, FP32.
 
+* ``batch256_f32`` -- the batched form's 256 independent sets: n ~ U{1000..100000},
+  p ~ U{128, 256, 512, 1024, 2048}, K ~ U{2..50}, gamma ~ U[0.02, 0.2], each set
+  drawn like ``mixture`` with its own K centers; 20 K-means rounds.
 * ``msel`` -- data blocks for the learned m-selector (not a workload of the
   paper): p = 1024, n = 8192, spike rank r ~ U{1..50}, lam_k = A / k with
   amplitude A log-uniform on [50, 5e4], unit noise.  The principal directions
@@ -42,6 +45,9 @@ WORKLOADS = {
                         spike_scale=20.0, spike_dof=3, dtype="f32", data_seed=1, gamma=0.05, T=20),
     "spiked4096_f32": dict(kind="spiked", n=1 << 20, p=4096, lam=tuple(50.0 / k for k in range(1, 21)),
                            dtype="f32", data_seed=2, gamma=0.1),
+    "batch256_f32": dict(kind="batch", count=256, n=(1000, 100000), p=(128, 256, 512, 1024, 2048), K=(2, 50),
+                         gamma=(0.02, 0.2), center_std=2.0, spike_prob=0.01, spike_scale=20.0, spike_dof=3,
+                         dtype="f32", data_seed=3, T=20),
 }
 
 
@@ -235,3 +241,46 @@ def msel_blocks_torch(seed, b0, count, p=None, n=None, device="cuda"):
         X = torch.randn((n, p), generator=g, device=device)
         X.addmm_(Z * sl, Q[k, :, :r].T)
         yield X, prm
+
+
+# ---------------------------------------------------------------------------
+# batched sets
+# ---------------------------------------------------------------------------
+def batch_params(name="batch256_f32", count=None):
+    """Per-set (n, p, K, gamma, m) of a batched workload, from its data seed."""
+    w = WORKLOADS[name]
+    rng = np.random.default_rng([w["data_seed"], 0xBA7C])
+    out = []
+    for i in range(w["count"] if count is None else count):
+        n = int(rng.integers(w["n"][0], w["n"][1] + 1))
+        p = int(rng.choice(w["p"]))
+        K = int(rng.integers(w["K"][0], w["K"][1] + 1))
+        gamma = float(rng.uniform(w["gamma"][0], w["gamma"][1]))
+        m = max(1, m_from_gamma(gamma, p))
+        out.append(dict(n=n, p=p, K=K, gamma=gamma, m=m, seed=i))
+    return out
+
+
+def batch_set_torch(name, i, prm, device="cuda", n=None):
+    """Set i of a batched workload drawn with torch on `device` (mixture-style:
+    the set's own K centers N(0, 4 I), unit noise, 1% of entries replaced by
+    20 t_3)."""
+    import torch
+
+    w = WORKLOADS[name]
+    n = prm["n"] if n is None else n
+    p, K = prm["p"], prm["K"]
+    rng = np.random.default_rng([w["data_seed"], 0xCE7, i])
+    C = torch.as_tensor(w["center_std"] * rng.standard_normal((K, p)), dtype=torch.float32, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed((w["data_seed"] * 1000003 + 23) * 1000003 + i)
+    lab = torch.randint(0, K, (n,), generator=g, device=device)
+    X = C[lab] + torch.randn((n, p), generator=g, device=device)
+    mask = torch.rand((n, p), generator=g, device=device) < w["spike_prob"]
+    nsp = int(mask.sum())
+    z = torch.randn(nsp, generator=g, device=device)
+    chi = torch.zeros(nsp, device=device)
+    for _ in range(w["spike_dof"]):
+        chi += torch.randn(nsp, generator=g, device=device) ** 2
+    X[mask] = w["spike_scale"] * z / torch.sqrt(chi / w["spike_dof"])
+    return X
