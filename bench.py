@@ -276,6 +276,69 @@ def run_batch(pds, steps, warmup, single_baseline=True):
     return out
 
 
+def run_mixture(pds, steps, warmup):
+    """Sparsified K-means on the mixture workload (n = 2^20, p = 1024, K = 10,
+    m = 51, T = 20): one compression and T kmeans_step calls per step,
+    seeded with the first K compressed samples (zero-filled)."""
+    import torch
+
+    import synth
+
+    name = "mixture_f32"
+    w = synth.WORKLOADS[name]
+    p, K, T = w["p"], w["K"], w["T"]
+    m = synth.m_from_gamma(w["gamma"], p)
+    n = w["n"]
+    log(f"generating {name}: n={n} p={p} m={m} K={K}")
+    X = synth.rows_torch(name, n, device="cuda")
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F32)
+    vals = torch.empty((n, m), dtype=torch.float32, device="cuda")
+    idx = torch.empty((n, m), dtype=torch.int16, device="cuda")
+    ws = plan.workspace(pds.PDS_OP_KMEANS, n, K, device="cuda")
+    ca = torch.zeros((K, p), dtype=torch.float64, device="cuda")
+    cb = torch.empty_like(ca)
+    assign = torch.empty(n, dtype=torch.int32, device="cuda")
+    objs = torch.empty(T, dtype=torch.float64, device="cuda")
+
+    def step():
+        pds.compress(plan, X, vals=vals, idx=idx)
+        ca.zero_()
+        rows = torch.arange(K, device="cuda").unsqueeze(1).expand(K, m)
+        ca[rows, idx[:K].long() & 0xFFFF] = vals[:K].double()
+        a, c = ca, cb
+        for r in range(T):
+            pds.kmeans_step(plan, vals, idx, a, out=c, assign=assign, objective=objs[r:r + 1], ws=ws)
+            a, c = c, a
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lib = pds.lib()
+    lib.pds_profile_enable(1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    lib.pds_profile_enable(0)
+    kern = profile_report(lib)
+    o = objs.cpu().numpy()
+    comp = n * (4 * p + 6 * m)
+    per_round = n * (6 * m + 4)
+    t_c = kern["compress"]["avg_ms"] + kern["sample_indices"]["avg_ms"]
+    t_k = sum(kern[k]["avg_ms"] for k in kern if k.startswith("kmeans")) * 1.0
+    t_k_round = sum(kern[k]["total_ms"] for k in kern if k.startswith("kmeans")) / (steps * T)
+    del X
+    return {
+        "workload": f"{name}: n={n}, p={p}, m={m}, K={K}, T={T}; step = compress + seed + T kmeans_step",
+        "ms_per_step": wall * 1e3, "samples_per_s": n / wall,
+        "compress_ms": t_c, "compress_frac_hbm": comp / (t_c / 1e3) / 1e9 / PEAK_HBM_GBS,
+        "kmeans_step_ms": t_k_round, "kmeans_step_frac_hbm": per_round / (t_k_round / 1e3) / 1e9 / PEAK_HBM_GBS,
+        "kernels_ms": {k: d["avg_ms"] for k, d in kern.items()},
+        "objective_first_last": [float(o[0]), float(o[-1])],
+    }
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the FETCH_SIZE /
     WRITE_SIZE counters of a profiled run."""
@@ -301,6 +364,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-form leg")
+    ap.add_argument("--no-mixture", action="store_true", help="skip the mixture K-means leg")
+    ap.add_argument("--mixture-only", action="store_true", help="run only the mixture K-means leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -319,6 +384,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batch_only:
         print(json.dumps({"batch": run_batch(pds, args.steps, args.warmup)}), flush=True)
+        return
+    if args.mixture_only:
+        print(json.dumps({"mixture": run_mixture(pds, args.steps, args.warmup)}), flush=True)
         return
     name = "spiked4096_f32"
     w = synth.WORKLOADS[name]
@@ -375,9 +443,14 @@ def main():
         out["errors"] = errs
     else:
         out["cpu_baseline"] = None
-    if not args.no_batch:
+    if not args.no_batch or not args.no_mixture:
         del X
         torch.cuda.empty_cache()
+    if not args.no_mixture:
+        out["mixture"] = run_mixture(pds, max(1, min(args.steps, 3)), 1)
+        log(f"mixture: {json.dumps(out['mixture'])}")
+        torch.cuda.empty_cache()
+    if not args.no_batch:
         out["batch"] = run_batch(pds, max(1, min(args.steps, 5)), max(1, min(args.warmup, 2)))
         log(f"batch: {json.dumps(out['batch'])}")
     print(json.dumps(out), flush=True)

@@ -13,12 +13,15 @@
 // registers, then the sample's m entries are added into per-workgroup LDS sums
 // and counts of its cluster.  Each workgroup writes its partial sums once.
 // Pass 2 (k_kmeans_update) adds the partials of all workgroups in a fixed order
-// in FP64 and divides.
+// in FP64 and divides; the objective is a fixed-order sum of per-sample
+// distances (k_kmeans_objective).
 //
 // FP32 plans: distances are FP32.  A sample whose best and second-best
 // distances are closer than a bound on the FP32 rounding error is recomputed in
 // FP64 with the same operation order as an FP64 plan (ascending kept
-// coordinate, fused multiply-add), so the assignment equals the FP64 argmin.
+// coordinate, fused multiply-add), so the assignment equals the FP64 argmin;
+// those samples are collected in a list and decided by k_kmeans_recheck, one
+// wave per sample, and their entries go to FP64 side sums.
 //
 // When K x p is too large for LDS the centers are read from a transposed copy
 // in the workspace and the sums go to FP64 global atomics instead.
@@ -27,7 +30,8 @@
 
 namespace pds {
 
-constexpr int kKmThreads = 256;
+constexpr int kKmThreads = 256;        // GLOBAL assignment path and helper kernels
+constexpr int kKmLdsThreads = 1024;    // LDS path: many waves share one LDS copy of the centers and sums
 constexpr int kKmGroup = 16;  // clusters per register group
 constexpr size_t kKmLdsMax = 150 * 1024;
 
@@ -40,6 +44,7 @@ struct SumType<double> {
     using type = double;
 };
 
+template <int NT>
 __device__ inline double block_sum_f64(double v, double* red)
 {
     const int tid = threadIdx.x;
@@ -48,10 +53,11 @@ __device__ inline double block_sum_f64(double v, double* red)
     __syncthreads();
     double s = 0.0;
     if (tid == 0)
-        for (int w = 0; w < kKmThreads / 64; ++w) s += red[w];
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
     return s;
 }
 
+template <int NT>
 __device__ inline float block_max_f32(float v, float* red)
 {
     const int tid = threadIdx.x;
@@ -59,7 +65,7 @@ __device__ inline float block_max_f32(float v, float* red)
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
     float s = red[0];
-    for (int w = 1; w < kKmThreads / 64; ++w) s = fmaxf(s, red[w]);
+    for (int w = 1; w < NT / 64; ++w) s = fmaxf(s, red[w]);
     __syncthreads();
     return s;
 }
@@ -78,20 +84,25 @@ __device__ inline double dist_f64(const T* __restrict__ v, const uint16_t* __res
 }
 
 // GLOBAL = centers from workspace copy, sums via FP64 global atomics.
-template <typename T, bool GLOBAL>
-__global__ __launch_bounds__(kKmThreads) void k_kmeans_assign(const T* __restrict__ vals,
+// FP32 plans: a sample whose two best distances are closer than the rounding
+// bound is appended to rlist and left to k_kmeans_recheck (its assignment,
+// distance and entries are written there), so no wave here runs the serial
+// FP64 loop on behalf of one lane.
+template <typename T, bool GLOBAL, int NT>
+__global__ __launch_bounds__(NT) void k_kmeans_assign(const T* __restrict__ vals,
                                                               const uint16_t* __restrict__ idx, int64_t n, int m,
                                                               int p, int K, const double* __restrict__ cin,
                                                               const T* __restrict__ cT_global, int64_t per_wg,
                                                               int32_t* __restrict__ assign,
                                                               typename SumType<T>::type* __restrict__ psum,
                                                               uint32_t* __restrict__ pcnt, double* __restrict__ gsum,
-                                                              uint32_t* __restrict__ gcnt, double* __restrict__ pobj)
+                                                              uint32_t* __restrict__ gcnt, double* __restrict__ dist,
+                                                              int64_t* __restrict__ rlist,
+                                                              uint32_t* __restrict__ rcount)
 {
     using S = typename SumType<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red_d[kKmThreads / 64];
-    __shared__ float red_f[kKmThreads / 64];
+    __shared__ float red_f[NT / 64];
     const int tid = threadIdx.x;
     const int64_t KP = (int64_t)K * p;
 
@@ -102,7 +113,7 @@ __global__ __launch_bounds__(kKmThreads) void k_kmeans_assign(const T* __restric
         cT = reinterpret_cast<T*>(smem);
         sums = reinterpret_cast<S*>(smem + ((KP * sizeof(T) + 15) & ~(int64_t)15));
         cnts = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(sums) + ((KP * sizeof(S) + 15) & ~(int64_t)15));
-        for (int64_t e = tid; e < KP; e += kKmThreads) {
+        for (int64_t e = tid; e < KP; e += NT) {
             const int64_t k = e / p, l = e - k * p;
             cT[l * K + k] = (T)cin[e];
             sums[e] = (S)0;
@@ -116,16 +127,15 @@ __global__ __launch_bounds__(kKmThreads) void k_kmeans_assign(const T* __restric
     // largest |center entry| (FP32 rounding bound only)
     float cmax = 0.0f;
     if constexpr (sizeof(T) == 4) {
-        for (int64_t e = tid; e < KP; e += kKmThreads) cmax = fmaxf(cmax, fabsf((float)cT[e]));
-        cmax = block_max_f32(cmax, red_f);
+        for (int64_t e = tid; e < KP; e += NT) cmax = fmaxf(cmax, fabsf((float)cT[e]));
+        cmax = block_max_f32<NT>(cmax, red_f);
     }
 
     const int64_t i0 = (int64_t)blockIdx.x * per_wg;
     int64_t i1 = i0 + per_wg;
     if (i1 > n) i1 = n;
-    double obj = 0.0;
 
-    for (int64_t i = i0 + tid; i < i1; i += kKmThreads) {
+    for (int64_t i = i0 + tid; i < i1; i += NT) {
         const T* v = vals + i * (int64_t)m;
         const uint16_t* ix = idx + i * (int64_t)m;
         T best = (T)INFINITY, second = (T)INFINITY;
@@ -161,32 +171,22 @@ __global__ __launch_bounds__(kKmThreads) void k_kmeans_assign(const T* __restric
                 }
             }
         }
-        double dsel = (double)best;
         if constexpr (sizeof(T) == 4) {
             // |d32 - d| <= u (8 (sum v^2 + sum mu^2) + 1.01 m d), u = 2^-24, per
-            // candidate; two candidates, factor 2 of slack.
+            // candidate; two candidates, factor 2 of slack
             if (K > 1) {
                 const float u = 5.9604645e-8f;
                 const float mf = (float)m;
                 const float bound =
                     2.0f * u * (16.0f * (sv + mf * cmax * cmax) + 1.01f * mf * ((float)best + (float)second));
                 if (!((float)second - (float)best > bound)) {
-                    double b64 = dist_f64<T>(v, ix, m, cin);
-                    int bk = 0;
-                    for (int k = 1; k < K; ++k) {
-                        double dk = dist_f64<T>(v, ix, m, cin + (int64_t)k * p);
-                        if (dk < b64) {
-                            b64 = dk;
-                            bk = k;
-                        }
-                    }
-                    bestk = bk;
-                    dsel = b64;
+                    rlist[atomicAdd(rcount, 1u)] = i;
+                    continue;
                 }
             }
         }
         assign[i] = bestk;
-        obj += dsel;
+        dist[i] = (double)best;
         if constexpr (!GLOBAL) {
             S* sk = sums + (int64_t)bestk * p;
             uint32_t* ck = cnts + (int64_t)bestk * p;
@@ -204,53 +204,302 @@ __global__ __launch_bounds__(kKmThreads) void k_kmeans_assign(const T* __restric
         }
     }
 
-    double tot = block_sum_f64(obj, red_d);
-    if (tid == 0) pobj[blockIdx.x] = tot;
     if constexpr (!GLOBAL) {
         __syncthreads();
         S* ps = psum + (int64_t)blockIdx.x * KP;
         uint32_t* pc = pcnt + (int64_t)blockIdx.x * KP;
-        for (int64_t e = tid; e < KP; e += kKmThreads) {
+        for (int64_t e = tid; e < KP; e += NT) {
             ps[e] = sums[e];
             pc[e] = cnts[e];
         }
     }
 }
 
-template <typename S>
-__global__ __launch_bounds__(256) void k_kmeans_update(const S* __restrict__ psum, const uint32_t* __restrict__ pcnt,
-                                                       int nparts, int64_t KP, const double* __restrict__ cin,
-                                                       double* __restrict__ cout, const double* __restrict__ pobj,
-                                                       int nobj, double* __restrict__ objective)
+// Row sum over the 16 lanes of a DPP row (inclusive shift-add; lane 15 of
+// the row ends with the total).
+__device__ inline float dpp_row_shr(float v, int n)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g == 0) {
+    int r;
+    switch (n) {
+        case 1: r = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true); break;
+        case 2: r = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true); break;
+        case 4: r = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true); break;
+        default: r = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true); break;
+    }
+    return __int_as_float(r);
+}
+
+__device__ inline float dpp_row_total(float v)
+{
+    v += dpp_row_shr(v, 1);
+    v += dpp_row_shr(v, 2);
+    v += dpp_row_shr(v, 4);
+    v += dpp_row_shr(v, 8);
+    return v;  // the row total in lane 15 of the row
+}
+
+// FP32 assignment with coalesced rows: a group of 16 lanes (one DPP row) per
+// sample, lanes over its kept entries, each lane's partial distances to the
+// K <= 32 centers in registers, then a row sum.  The summation order differs
+// from the sequential one, but its rounding error obeys the same bound (every
+// term passes through at most m additions), so the near-tie test and the FP64
+// recheck give the FP64 argmin as before.  Centers are transposed in LDS with
+// rows padded to KP4 = ceil4(K) floats and read as float4.
+__global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
+    const float* __restrict__ vals, const uint16_t* __restrict__ idx, int64_t n, int m, int p, int K,
+    const double* __restrict__ cin, int64_t per_wg, int32_t* __restrict__ assign, float* __restrict__ psum,
+    uint32_t* __restrict__ pcnt, double* __restrict__ dist, int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
+{
+    constexpr int W = 16;
+    constexpr int G = kKmLdsThreads / W;  // groups per workgroup
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float red_f[kKmLdsThreads / 64];
+    const int tid = threadIdx.x;
+    const int KP4 = (K + 3) & ~3;
+    const int nq4 = KP4 >> 2;
+    const int64_t KP = (int64_t)K * p;
+    float* cT = reinterpret_cast<float*>(smem);
+    float* sums = cT + (int64_t)KP4 * p;
+    uint32_t* cnts = reinterpret_cast<uint32_t*>(sums + KP);
+    for (int64_t e = tid; e < (int64_t)KP4 * p; e += kKmLdsThreads) {
+        const int64_t l = e / KP4, k = e - l * KP4;
+        cT[e] = (k < K) ? (float)cin[k * p + l] : 0.0f;
+    }
+    for (int64_t e = tid; e < KP; e += kKmLdsThreads) {
+        sums[e] = 0.0f;
+        cnts[e] = 0u;
+    }
+    __syncthreads();
+    float cmax = 0.0f;
+    for (int64_t e = tid; e < (int64_t)KP4 * p; e += kKmLdsThreads) cmax = fmaxf(cmax, fabsf(cT[e]));
+    cmax = block_max_f32<kKmLdsThreads>(cmax, red_f);
+
+    const int g = tid / W, sl = tid % W;
+    const int64_t i0 = (int64_t)blockIdx.x * per_wg;
+    int64_t i1 = i0 + per_wg;
+    if (i1 > n) i1 = n;
+    for (int64_t i = i0 + g; i < i1; i += G) {
+        const float* v = vals + i * (int64_t)m;
+        const uint16_t* ix = idx + i * (int64_t)m;
+        float d[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) d[q] = 0.0f;
+        float sv = 0.0f;
+        for (int a0 = 0; a0 < m; a0 += 4 * W) {
+            float x[4];
+            int l[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int a = a0 + u * W + sl;
+                x[u] = (a < m) ? v[a] : 0.0f;
+                l[u] = (a < m) ? (int)ix[a] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (l[u] >= 0) {
+                    sv = fmaf(x[u], x[u], sv);
+                    const float4* c4 = reinterpret_cast<const float4*>(cT + l[u] * KP4);
+#pragma unroll
+                    for (int q4 = 0; q4 < 8; ++q4) {
+                        if (q4 < nq4) {
+                            const float4 c = c4[q4];
+                            const float cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const float diff = x[u] - cc[r];
+                                d[4 * q4 + r] = fmaf(diff, diff, d[4 * q4 + r]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        sv = dpp_row_total(sv);
+#pragma unroll
+        for (int q = 0; q < 32; ++q)
+            if (q < K) d[q] = dpp_row_total(d[q]);
+        // lane 15 of the row holds the totals and decides
+        float best = INFINITY, second = INFINITY;
+        int bestk = 0;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            if (q < K) {
+                if (d[q] < best) {
+                    second = best;
+                    best = d[q];
+                    bestk = q;
+                } else if (d[q] < second) {
+                    second = d[q];
+                }
+            }
+        }
+        int flag = 0;
+        if (K > 1) {
+            // |d32 - d| <= u (8 (sum v^2 + sum mu^2) + 1.01 m d), u = 2^-24, per
+            // candidate; two candidates, factor 2 of slack
+            const float u = 5.9604645e-8f;
+            const float mf = (float)m;
+            const float bound = 2.0f * u * (16.0f * (sv + mf * cmax * cmax) + 1.01f * mf * (best + second));
+            flag = !(second - best > bound);
+        }
+        flag = __shfl(flag, W - 1, W);
+        bestk = __shfl(bestk, W - 1, W);
+        if (flag) {
+            if (sl == W - 1) rlist[atomicAdd(rcount, 1u)] = i;
+            continue;
+        }
+        if (sl == W - 1) {
+            assign[i] = bestk;
+            dist[i] = (double)best;
+        }
+        float* sk = sums + (int64_t)bestk * p;
+        uint32_t* ck = cnts + (int64_t)bestk * p;
+        for (int a = sl; a < m; a += W) {
+            const int l = ix[a];
+            atomicAdd(&sk[l], v[a]);
+            atomicAdd(&ck[l], 1u);
+        }
+    }
+    __syncthreads();
+    float* ps = psum + (int64_t)blockIdx.x * KP;
+    uint32_t* pc = pcnt + (int64_t)blockIdx.x * KP;
+    for (int64_t e = tid; e < KP; e += kKmLdsThreads) {
+        ps[e] = sums[e];
+        pc[e] = cnts[e];
+    }
+}
+
+// FP64 decision for the flagged samples: one wave per sample, lanes over
+// clusters, each distance summed in the oracle's order; ties to the lowest k.
+// The sample's entries go to the FP64 side sums (gsum_r, gcnt_r).
+__global__ __launch_bounds__(256) void k_kmeans_recheck(const float* __restrict__ vals,
+                                                        const uint16_t* __restrict__ idx, int m, int p, int K,
+                                                        const double* __restrict__ cin,
+                                                        const int64_t* __restrict__ rlist,
+                                                        const uint32_t* __restrict__ rcount,
+                                                        int32_t* __restrict__ assign, double* __restrict__ dist,
+                                                        double* __restrict__ gsum_r, uint32_t* __restrict__ gcnt_r)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t cnt = *rcount;
+    for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < cnt; e += nw) {
+        const int64_t i = rlist[e];
+        const float* v = vals + i * (int64_t)m;
+        const uint16_t* ix = idx + i * (int64_t)m;
+        double bd = INFINITY;
+        int bk = 0x7fffffff;
+        for (int k = lane; k < K; k += 64) {
+            const double dk = dist_f64<float>(v, ix, m, cin + (int64_t)k * p);
+            if (dk < bd) {  // k ascends within a lane: ties keep the lower k
+                bd = dk;
+                bk = k;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double od = __shfl_xor(bd, off, 64);
+            const int ok = __shfl_xor(bk, off, 64);
+            if (od < bd || (od == bd && ok < bk)) {
+                bd = od;
+                bk = ok;
+            }
+        }
+        if (lane == 0) {
+            assign[i] = bk;
+            dist[i] = bd;
+        }
+        double* sk = gsum_r + (int64_t)bk * p;
+        uint32_t* ck = gcnt_r + (int64_t)bk * p;
+        for (int a = lane; a < m; a += 64) {
+            atomicAdd(&sk[ix[a]], (double)v[a]);
+            atomicAdd(&ck[ix[a]], 1u);
+        }
+    }
+}
+
+// objective partial of each assignment workgroup's range, fixed order
+__global__ __launch_bounds__(kKmThreads) void k_kmeans_objective(const double* __restrict__ dist, int64_t n,
+                                                                 int64_t per_wg, double* __restrict__ pobj)
+{
+    __shared__ double red[kKmThreads / 64];
+    const int64_t i0 = (int64_t)blockIdx.x * per_wg;
+    int64_t i1 = i0 + per_wg;
+    if (i1 > n) i1 = n;
+    double o = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kKmThreads) o += dist[i];
+    const double t = block_sum_f64<kKmThreads>(o, red);
+    if (threadIdx.x == 0) pobj[blockIdx.x] = t;
+}
+
+// Update: a workgroup per 64 center entries; its 16 waves each add every
+// 16th partial for the 64 entries (coalesced), then the 16 wave sums are
+// combined in a fixed order; the first workgroup also sums the objective.
+constexpr int kUpdThreads = 1024;
+
+template <typename S>
+__global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const S* __restrict__ psum,
+                                                               const uint32_t* __restrict__ pcnt, int nparts,
+                                                               int64_t KP, const double* __restrict__ gsum_r,
+                                                               const uint32_t* __restrict__ gcnt_r,
+                                                               const double* __restrict__ cin,
+                                                               double* __restrict__ cout,
+                                                               const double* __restrict__ pobj, int nobj,
+                                                               double* __restrict__ objective)
+{
+    __shared__ double rs[kUpdThreads / 64][64];
+    __shared__ uint64_t rc[kUpdThreads / 64][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         double o = 0.0;
         for (int w = 0; w < nobj; ++w) o += pobj[w];
         *objective = o;
     }
-    if (g >= KP) return;
     double sum = 0.0;
     uint64_t cnt = 0;
-    for (int w = 0; w < nparts; ++w) {
-        sum += (double)psum[(int64_t)w * KP + g];
-        cnt += pcnt[(int64_t)w * KP + g];
+    if (g < KP) {
+        for (int w = wv; w < nparts; w += kUpdThreads / 64) {
+            sum += (double)psum[(int64_t)w * KP + g];
+            cnt += pcnt[(int64_t)w * KP + g];
+        }
     }
-    cout[g] = (cnt > 0) ? sum / (double)cnt : cin[g];
+    rs[wv][lane] = sum;
+    rc[wv][lane] = cnt;
+    __syncthreads();
+    if (wv == 0 && g < KP) {
+        double t = 0.0;
+        uint64_t c = 0;
+        for (int w = 0; w < kUpdThreads / 64; ++w) {
+            t += rs[w][lane];
+            c += rc[w][lane];
+        }
+        t += gsum_r[g];
+        c += gcnt_r[g];
+        cout[g] = (c > 0) ? t / (double)c : cin[g];
+    }
 }
 
+// per call: side sums and counter cleared; for the GLOBAL path also the
+// transposed centers and the global sums
 template <typename T>
-__global__ __launch_bounds__(256) void k_kmeans_prep_global(const double* __restrict__ cin, int K, int p,
-                                                            T* __restrict__ cT, double* __restrict__ gsum,
-                                                            uint32_t* __restrict__ gcnt)
+__global__ __launch_bounds__(256) void k_kmeans_prep(const double* __restrict__ cin, int K, int p, int global,
+                                                     T* __restrict__ cT, double* __restrict__ gsum,
+                                                     uint32_t* __restrict__ gcnt, double* __restrict__ gsum_r,
+                                                     uint32_t* __restrict__ gcnt_r, uint32_t* __restrict__ rcount)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t KP = (int64_t)K * p;
+    if (g == 0) *rcount = 0u;
     if (g >= KP) return;
-    const int64_t k = g / p, l = g - k * p;
-    cT[l * K + k] = (T)cin[g];
-    gsum[g] = 0.0;
-    gcnt[g] = 0u;
+    gsum_r[g] = 0.0;
+    gcnt_r[g] = 0u;
+    if (global) {
+        const int64_t k = g / p, l = g - k * p;
+        cT[l * K + k] = (T)cin[g];
+        gsum[g] = 0.0;
+        gcnt[g] = 0u;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -258,10 +507,12 @@ __global__ __launch_bounds__(256) void k_kmeans_prep_global(const double* __rest
 // ---------------------------------------------------------------------------
 struct KmPlan {
     bool global;
+    int coop;  // FP32 group-per-sample assignment: lanes per sample (0 = not used)
     int nwg;
     int64_t per_wg;
     size_t lds;
     size_t psum_bytes, pcnt_bytes, pobj_bytes, ct_bytes, gsum_bytes, gcnt_bytes;
+    size_t dist_bytes, rlist_bytes, rcount_bytes, gsumr_bytes, gcntr_bytes;
 };
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -275,7 +526,16 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
     const size_t lds = ((KP * te + 15) & ~(size_t)15) + ((KP * se + 15) & ~(size_t)15) + KP * 4;
     k.global = lds > kKmLdsMax;
     k.lds = k.global ? 0 : lds;
-    int64_t want = (n + kKmThreads - 1) / kKmThreads;
+    // FP32, K <= 32, centers (rows padded to 4) + sums + counts in LDS
+    const size_t lds_coop = (size_t)((K + 3) & ~3) * p * 4 + (size_t)KP * 8;
+    k.coop = 0;
+    if (prec != 0 && K <= 32 && lds_coop <= kKmLdsMax) {
+        k.coop = 16;
+        k.global = false;
+        k.lds = lds_coop;
+    }
+    const int nt = k.global ? kKmThreads : kKmLdsThreads;
+    int64_t want = (n + nt - 1) / nt;
     int64_t cap = (int64_t)dev.cus * (k.global ? 8 : 1);
     if (!k.global && lds * 2 <= kKmLdsMax) cap = (int64_t)dev.cus * 2;
     if (want > cap) want = cap;
@@ -288,6 +548,12 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
     k.ct_bytes = k.global ? al256(KP * te) : 0;
     k.gsum_bytes = k.global ? al256(KP * 8) : 0;
     k.gcnt_bytes = k.global ? al256(KP * 4) : 0;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    k.dist_bytes = al256(nn * 8);
+    k.rlist_bytes = (prec == 0) ? 0 : al256(nn * 8);
+    k.rcount_bytes = 256;
+    k.gsumr_bytes = al256(KP * 8);
+    k.gcntr_bytes = al256(KP * 4);
     return k;
 }
 
@@ -295,13 +561,14 @@ size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceIn
 {
     (void)m;
     KmPlan k = km_plan(prec, p, n, K, dev);
-    return k.psum_bytes + k.pcnt_bytes + k.pobj_bytes + k.ct_bytes + k.gsum_bytes + k.gcnt_bytes;
+    return k.psum_bytes + k.pcnt_bytes + k.pobj_bytes + k.ct_bytes + k.gsum_bytes + k.gcnt_bytes + k.dist_bytes +
+           k.rlist_bytes + k.rcount_bytes + k.gsumr_bytes + k.gcntr_bytes;
 }
 
 template <typename T>
 static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const uint16_t* idx, int64_t n, int K,
                             const double* cin, double* cout, int32_t* assign, double* objective, void* ws,
-                            hipStream_t s)
+                            const DeviceInfo& dev, hipStream_t s)
 {
     using S = typename SumType<T>::type;
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
@@ -316,47 +583,83 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
     double* gsum = reinterpret_cast<double*>(w);
     w += k.gsum_bytes;
     uint32_t* gcnt = reinterpret_cast<uint32_t*>(w);
+    w += k.gcnt_bytes;
+    double* dist = reinterpret_cast<double*>(w);
+    w += k.dist_bytes;
+    int64_t* rlist = reinterpret_cast<int64_t*>(w);
+    w += k.rlist_bytes;
+    uint32_t* rcount = reinterpret_cast<uint32_t*>(w);
+    w += k.rcount_bytes;
+    double* gsum_r = reinterpret_cast<double*>(w);
+    w += k.gsumr_bytes;
+    uint32_t* gcnt_r = reinterpret_cast<uint32_t*>(w);
     const int64_t KP = (int64_t)K * p;
-    if (k.global) {
-        {
-        ProfScope ps_("kmeans_prep", s);
-        hipLaunchKernelGGL(k_kmeans_prep_global<T>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, cin, K, p,
-                           cT, gsum, gcnt);
-    }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        {
-        ProfScope ps_("kmeans_assign", s);
-        hipLaunchKernelGGL((k_kmeans_assign<T, true>), dim3(k.nwg), dim3(kKmThreads), 0, s, vals, idx, n, m, p, K,
-                           cin, cT, k.per_wg, assign, psum, pcnt, gsum, gcnt, pobj);
-    }
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        {
-        ProfScope ps_("kmeans_update", s);
-        hipLaunchKernelGGL(k_kmeans_update<double>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, gsum, gcnt, 1,
-                           KP, cin, cout, pobj, k.nwg, objective);
-    }
-        return hipGetLastError();
-    }
-    static bool attr_set[2] = {false, false};
-    if (!attr_set[sizeof(T) == 8]) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kmeans_assign<T, false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kKmLdsMax);
-        attr_set[sizeof(T) == 8] = true;
-    }
     {
-        ProfScope ps_("kmeans_assign", s);
-        hipLaunchKernelGGL((k_kmeans_assign<T, false>), dim3(k.nwg), dim3(kKmThreads), k.lds, s, vals, idx, n, m, p, K,
-                       cin, (const T*)nullptr, k.per_wg, assign, psum, pcnt, (double*)nullptr, (uint32_t*)nullptr,
-                       pobj);
+        ProfScope ps_("kmeans_prep", s);
+        hipLaunchKernelGGL(k_kmeans_prep<T>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, cin, K, p,
+                           k.global ? 1 : 0, cT, gsum, gcnt, gsum_r, gcnt_r, rcount);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (k.global) {
+        ProfScope ps_("kmeans_assign", s);
+        hipLaunchKernelGGL((k_kmeans_assign<T, true, kKmThreads>), dim3(k.nwg), dim3(kKmThreads), 0, s, vals, idx, n,
+                           m, p, K,
+                           cin, cT, k.per_wg, assign, psum, pcnt, gsum, gcnt, dist, rlist, rcount);
+    } else {
+        if constexpr (sizeof(T) == 4) {
+            if (k.coop) {
+                static bool coop_attr = false;
+                if (!coop_attr) {
+                    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kmeans_assign_coop),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kKmLdsMax);
+                    coop_attr = true;
+                }
+                {
+                    ProfScope ps_("kmeans_assign", s);
+                    hipLaunchKernelGGL(k_kmeans_assign_coop, dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s, vals, idx,
+                                       n, m, p, K, cin, k.per_wg, assign, psum, pcnt, dist, rlist, rcount);
+                }
+                goto assigned;
+            }
+        }
+        static bool attr_set[2] = {false, false};
+        if (!attr_set[sizeof(T) == 8]) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kmeans_assign<T, false, kKmLdsThreads>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kKmLdsMax);
+            attr_set[sizeof(T) == 8] = true;
+        }
+        ProfScope ps_("kmeans_assign", s);
+        hipLaunchKernelGGL((k_kmeans_assign<T, false, kKmLdsThreads>), dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s,
+                           vals, idx, n, m, p,
+                           K, cin, (const T*)nullptr, k.per_wg, assign, psum, pcnt, (double*)nullptr,
+                           (uint32_t*)nullptr, dist, rlist, rcount);
+    }
+assigned:
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if constexpr (sizeof(T) == 4) {
+        ProfScope ps_("kmeans_recheck", s);
+        hipLaunchKernelGGL(k_kmeans_recheck, dim3((unsigned)dev.cus * 4), dim3(256), 0, s, vals, idx, m, p, K, cin,
+                           rlist, rcount, assign, dist, gsum_r, gcnt_r);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps_("kmeans_objective", s);
+        hipLaunchKernelGGL(k_kmeans_objective, dim3(k.nwg), dim3(kKmThreads), 0, s, dist, n, k.per_wg, pobj);  // fixed order
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     {
         ProfScope ps_("kmeans_update", s);
-        hipLaunchKernelGGL(k_kmeans_update<S>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, psum, pcnt, k.nwg, KP,
-                       cin, cout, pobj, k.nwg, objective);
+        const unsigned ublocks = (unsigned)((KP + 63) / 64);
+        if (k.global)
+            hipLaunchKernelGGL(k_kmeans_update<double>, dim3(ublocks), dim3(kUpdThreads), 0, s, gsum, gcnt, 1, KP,
+                               gsum_r, gcnt_r, cin, cout, pobj, k.nwg, objective);
+        else
+            hipLaunchKernelGGL(k_kmeans_update<S>, dim3(ublocks), dim3(kUpdThreads), 0, s, psum, pcnt, k.nwg, KP,
+                               gsum_r, gcnt_r, cin, cout, pobj, k.nwg, objective);
     }
     return hipGetLastError();
 }
@@ -369,9 +672,9 @@ hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const ui
     KmPlan k = km_plan(prec, p, n, K, dev);
     if (prec == 0)
         return km_launch<double>(k, p, m, reinterpret_cast<const double*>(vals), idx, n, K, cin, cout, assign,
-                                 objective, ws, s);
+                                 objective, ws, dev, s);
     return km_launch<float>(k, p, m, reinterpret_cast<const float*>(vals), idx, n, K, cin, cout, assign, objective,
-                            ws, s);
+                            ws, dev, s);
 }
 
 // ---------------------------------------------------------------------------
