@@ -18,6 +18,7 @@ from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKS
 
 __all__ = [
     "Plan", "compress", "covariance", "CovarianceAccumulator", "kmeans_step", "unmix", "sparsified_kmeans",
+    "top_eigenvalues",
     "PdsError", "PDS_F64", "PDS_F32", "PDS_SPLIT_BF16", "lib", "EXPORTS",
 ]
 
@@ -159,6 +160,21 @@ def covariance(plan: Plan, vals, idx, acc=None, ws=None, C=None):
     check(lib().pds_covariance(plan.handle, _ptr(vals), _ptr(idx), n, _ptr(acc), 1, n, _ptr(C), _ptr(ws),
                                ws.numel() if ws is not None else 0, _stream()), "pds_covariance")
     return C
+
+
+def top_eigenvalues(C, k: int = 20):
+    """The k largest eigenvalues (descending, FP64) of the symmetric, possibly
+    indefinite covariance estimate C (PCA on the estimate, Sec. V): the
+    device's dense symmetric eigensolver (rocSOLVER through torch.linalg) on
+    the FP64 matrix where it lives.  Eigenvalues are the same in the
+    preconditioned and the original domain (H D is orthogonal)."""
+    import torch
+
+    if C.dim() != 2 or C.shape[0] != C.shape[1]:
+        raise ValueError("C must be square")
+    w = torch.linalg.eigvalsh(C.to(torch.float64))
+    k = min(int(k), C.shape[0])
+    return torch.flip(w, dims=[0])[:k]
 
 
 def kmeans_step(plan: Plan, vals, idx, centers, out=None, assign=None, objective=None, ws=None):

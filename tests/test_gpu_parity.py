@@ -291,3 +291,30 @@ def test_mixture_kmeans_reduced_n_fp32():
         assert np.all(margin[bad] <= 1e-4 * (J_o / n)), (t, bad[:5], margin[bad][:5])
         assert nerr(mu_g.cpu().numpy(), mu_o) <= 1e-5
         assert abs(J_g.item() - J_o) <= 1e-5 * J_o
+
+
+# ------------------------------------------------------------- eigenvalues --
+@pytest.mark.parametrize("p", [16, 257, 1024])
+def test_top_eigenvalues_match_lapack(p):
+    """top_eigenvalues (device solver) against LAPACK on the host, for a
+    symmetric indefinite matrix and for a covariance estimate of the pipeline."""
+    log(f"top_eigenvalues p={p}")
+    rng = np.random.default_rng(p)
+    A = rng.standard_normal((p, p))
+    A = A + A.T
+    ev = pds.top_eigenvalues(to_dev(A), 20).cpu().numpy()
+    ev_o = np.linalg.eigvalsh(A)[::-1][:min(20, p)]
+    assert np.max(np.abs(ev - ev_o)) <= 1e-10 * np.max(np.abs(ev_o))
+
+
+def test_top_eigenvalues_of_the_estimate():
+    p, m, n = 256, 64, 3000
+    X = synth.rows_numpy("small_f64", n)
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F64)
+    vals, idx = pds.compress(plan, to_dev(X))
+    C = pds.covariance(plan, vals, idx)
+    v_o, i_o = ref.compress(X, 0, m)
+    C_o = ref.covariance(p, v_o, i_o)
+    ev = pds.top_eigenvalues(C, 20).cpu().numpy()
+    ev_o = np.linalg.eigvalsh(C_o)[::-1][:20]
+    assert np.max(np.abs(ev - ev_o) / np.abs(ev_o)) < 1e-11
