@@ -97,29 +97,15 @@ struct MfmaLds<true> {
     unsigned short alo[kTR * kBfStride];
     unsigned short bhi[kTC * kBfStride];
     unsigned short blo[kTC * kBfStride];
-    double diag[kTC];  // exact sum of squares per column coordinate (inner tiles)
+    double diag[kTC];  // FP64 sum of squares per column coordinate (inner tiles)
+    __device__ double* diag_ptr() { return diag; }
 };
 template <>
 struct MfmaLds<false> {
     float a[kTR * kF32Stride];
     float b[kTC * kF32Stride];
+    __device__ double* diag_ptr() { return nullptr; }
 };
-
-template <bool SPLIT>
-__device__ inline void scatter_entry(MfmaLds<SPLIT>& L, bool to_b, int coord, int s, float v)
-{
-    if constexpr (SPLIT) {
-        unsigned short h = bf16_bits_rn(v);
-        unsigned short l = bf16_bits_rn(v - bf16_bits_to_float(h));
-        unsigned short* hi = to_b ? L.bhi : L.ahi;
-        unsigned short* lo = to_b ? L.blo : L.alo;
-        hi[coord * kBfStride + s] = h;
-        lo[coord * kBfStride + s] = l;
-    } else {
-        float* d = to_b ? L.b : L.a;
-        d[coord * kF32Stride + s] = v;
-    }
-}
 
 // Tile geometry shared by the host plan and the kernels.
 struct TileGeom {
@@ -152,119 +138,291 @@ __device__ inline void decode_rect_tile(int t, const TileGeom& g, int& a, int& b
     b = r * g.ratio + t;
 }
 
-// Per-thread share of one chunk: thread t serves sample slot s = t / 8 and
-// entries e0 + (t % 8) + 8 k of the row block (k < KA) and of the column block
-// (k < KB).  The host picks KA, KB so that a sample rarely has more entries in
-// a block; the rare extra entries are read and scattered directly.
-struct ChunkOffsets {
-    uint32_t a0, a1, b0, b1;
-    bool ok;  // the sample belongs to this range (else the offsets are not used)
-};
-
-template <int KA, int KB>
-struct ChunkEntries {
-    uint16_t ia[KA], ib[KB];
-    float va[KA], vb[KB];
-    uint32_t valid;  // bit k: row entry k, bit 16 + k: column entry k
-};
-
-// The load address is always a valid row, so no branch guards it.
-__device__ inline ChunkOffsets load_offsets(const uint32_t* __restrict__ off, int nbo, int64_t send, int64_t i,
-                                            int64_t i_safe, int oa0, int oa1, int ob0)
+// ---------------------------------------------------------------------------
+// Chunk packing (matrix-core variants).  Chunk c holds samples 32c .. 32c+31;
+// its n_c m entries are rewritten, in the chunk's own 32 m slots, ordered by
+// column block (tc coordinates), then sample, then coordinate:
+//   P[c][q]  the stored value: bf16 hi | bf16 lo << 16 (split), or the FP32 bits
+//   OA[c][q] LDS byte offset of the entry in a row tile, OB[c][q] in a column
+//            tile: coordinate-in-tile * row bytes + slot * element bytes
+//   BS[c][b] first q of block b, b = 0 .. nbc (BS[c][nbc] = n_c m)
+// A tile's entries of one chunk are then one contiguous run: the tile kernel
+// reads them coalesced, balanced over its threads, and scatters each with one
+// offset extraction, and the bf16 split is done once per entry instead of once
+// per tile.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t split_bits(float v)
 {
-    const uint32_t* r = off + (i < send ? i : i_safe) * (nbo + 1);
-    ChunkOffsets o;
-    o.a0 = r[oa0];
-    o.a1 = r[oa1];
-    o.b0 = r[ob0];
-    o.b1 = r[ob0 + 1];
-    o.ok = i < send;
-    return o;
+    const unsigned short h = bf16_bits_rn(v);
+    const unsigned short l = bf16_bits_rn(v - bf16_bits_to_float(h));
+    return (uint32_t)h | ((uint32_t)l << 16);
 }
 
-// Raw loaded words; the arithmetic on them waits until the scatter so that
-// the loads stay in flight while the matrix cores run.
-template <int KA, int KB>
-__device__ inline ChunkEntries<KA, KB> load_entries(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
-                                                    int m, int64_t send, int64_t i, int64_t i_safe,
-                                                    const ChunkOffsets& o, int sub, bool inner)
+__device__ inline uint32_t block_exclusive_scan256(uint32_t v, uint32_t* wsum)
 {
-    ChunkEntries<KA, KB> c;
-    const int64_t row = (i < send ? i : i_safe) * (int64_t)m;
-    const float* v = vals + row;
-    const uint16_t* ix = idx + row;
-    c.valid = 0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t incl = v;
 #pragma unroll
-    for (int k = 0; k < KA; ++k) {
-        const uint32_t e = o.a0 + sub + 8 * k;
-        const uint32_t se = e < (uint32_t)m ? e : (uint32_t)(m - 1);
-        c.ia[k] = ix[se];
-        c.va[k] = v[se];
-        c.valid |= (uint32_t)(o.ok && e < o.a1) << k;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    return base + incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
+                                                   int64_t n, int m, int tr, int tc, int nbc, int rowbytes, int split,
+                                                   uint32_t* __restrict__ P, uint16_t* __restrict__ OA,
+                                                   uint16_t* __restrict__ OB, uint32_t* __restrict__ BS)
+{
+    extern __shared__ uint32_t pk_sh[];
+    const int nb1 = nbc + 1;
+    uint32_t* off = pk_sh;              // [32][nb1]: first entry of block b in the sample's row
+    uint32_t* seg = pk_sh + 32 * nb1;   // [nbc][32]: chunk position of segment (b, s) minus off[s][b]
+    uint32_t* wsum = seg + 32 * nbc;    // 4 wave totals
+    const int64_t c = blockIdx.x;
+    const int64_t i0 = c * kChunk;
+    const int ns = (int)((n - i0) < kChunk ? (n - i0) : kChunk);
+    const int tid = threadIdx.x;
+    const int eb = split ? 2 : 4;
+    const int sh_c = __builtin_ctz((unsigned)tc);
+
+    // block starts: block b begins at the first entry whose block number
+    // reaches b, which the entry finds by comparing with its predecessor
+    for (int s = 0; s < kChunk; ++s) {
+        if (s >= ns) {
+            for (int b = tid; b < nb1; b += 256) off[s * nb1 + b] = 0;
+            continue;
+        }
+        const uint16_t* row = idx + (i0 + s) * (int64_t)m;
+        for (int e = tid; e < m; e += 256) {
+            const int be = (int)row[e] >> sh_c;
+            const int bp = e > 0 ? ((int)row[e - 1] >> sh_c) : -1;
+            for (int b = bp + 1; b <= be; ++b) off[s * nb1 + b] = (uint32_t)e;
+            if (e == m - 1)
+                for (int b = be + 1; b <= nbc; ++b) off[s * nb1 + b] = (uint32_t)m;
+        }
+    }
+    __syncthreads();
+
+    // exclusive scan of the segment sizes in (block, sample) order
+    const int Q = nbc * kChunk;
+    const int per = (Q + 255) / 256;
+    const int q0 = tid * per;
+    uint32_t run = 0;
+    for (int k = 0; k < per; ++k) {
+        const int q = q0 + k;
+        if (q < Q) {
+            const int b = q >> 5, s = q & 31;
+            run += off[s * nb1 + b + 1] - off[s * nb1 + b];
+        }
+    }
+    uint32_t pos = block_exclusive_scan256(run, wsum);
+    uint32_t* bs = BS + c * nb1;
+    for (int k = 0; k < per; ++k) {
+        const int q = q0 + k;
+        if (q < Q) {
+            const int b = q >> 5, s = q & 31;
+            const uint32_t o0 = off[s * nb1 + b];
+            if (s == 0) bs[b] = pos;
+            seg[q] = pos - o0;  // modular: seg + e is the chunk position of entry e
+            pos += off[s * nb1 + b + 1] - o0;
+        }
+    }
+    if (tid == 0) bs[nbc] = (uint32_t)ns * (uint32_t)m;
+    __syncthreads();
+
+    uint32_t* Pc = P + c * (int64_t)kChunk * m;
+    uint16_t* OAc = OA + c * (int64_t)kChunk * m;
+    uint16_t* OBc = OB + c * (int64_t)kChunk * m;
+    for (int s = 0; s < ns; ++s) {
+        const uint16_t* row = idx + (i0 + s) * (int64_t)m;
+        const float* vrow = vals + (i0 + s) * (int64_t)m;
+        for (int e = tid; e < m; e += 256) {
+            const uint32_t j = row[e];
+            const uint32_t q = seg[((int)j >> sh_c) * kChunk + s] + (uint32_t)e;
+            const float v = vrow[e];
+            Pc[q] = split ? split_bits(v) : __float_as_uint(v);
+            OAc[q] = (uint16_t)((j & (uint32_t)(tr - 1)) * rowbytes + s * eb);
+            OBc[q] = (uint16_t)((j & (uint32_t)(tc - 1)) * rowbytes + s * eb);
+        }
+    }
+}
+
+// A chunk's runs for one tile (workgroup-uniform).
+struct ChunkRun {
+    uint32_t a0, na;  // row-block run: first q and length
+    uint32_t b0, nb;  // column-block run (empty on inner tiles)
+};
+
+// The four run bounds of chunk c are loaded by lanes 0..3 as vector loads, so
+// that their wait falls at the first use (an iteration later), not at the
+// matrix-core block's first LDS wait as a scalar load's would.  Past the range
+// (live false) the lanes read chunk c_safe and the runs are emptied at unpack.
+__device__ inline int chunk_run_col(int ba0, int ba1, int bb, bool inner, int lane)
+{
+    const int sel = lane & 3;
+    return sel == 0 ? ba0 : sel == 1 ? ba1 : bb + (sel == 3 && !inner ? 1 : 0);
+}
+
+__device__ inline uint32_t chunk_run_load(const uint32_t* __restrict__ BS, int nb1, int64_t c, bool live,
+                                          int64_t c_safe, int col)
+{
+    return BS[(live ? c : c_safe) * nb1 + col];
+}
+
+__device__ inline ChunkRun chunk_run_unpack(uint32_t v, bool live)
+{
+    ChunkRun r{0, 0, 0, 0};
+    if (live) {
+        r.a0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+        r.na = (uint32_t)__builtin_amdgcn_readlane((int)v, 1) - r.a0;
+        r.b0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 2);
+        r.nb = (uint32_t)__builtin_amdgcn_readlane((int)v, 3) - r.b0;
+    }
+    return r;
+}
+
+// Register share of one chunk: thread t holds run entries t + 256 k.
+template <int SA, int SB>
+struct ChunkRegs {
+    uint32_t pa[SA], oa[SA], pb[SB], ob[SB];
+};
+
+// Loads for one chunk; lanes past a run's end read entry 0 of the chunk (a
+// valid address) and are masked at the scatter.  Byte offsets inside the chunk
+// are 32-bit (a chunk holds at most 32 * 65536 entries), so the loads take a
+// uniform base and one offset register.
+template <int SA, int SB>
+__device__ inline void load_chunk(ChunkRegs<SA, SB>& R, const uint32_t* __restrict__ P,
+                                  const uint16_t* __restrict__ OA, const uint16_t* __restrict__ OB, int64_t cbase,
+                                  const ChunkRun& r, int tid)
+{
+    const unsigned char* pc = reinterpret_cast<const unsigned char*>(P + cbase);
+    const unsigned char* ac = reinterpret_cast<const unsigned char*>(OA + cbase);
+    const unsigned char* bc = reinterpret_cast<const unsigned char*>(OB + cbase);
+#pragma unroll
+    for (int k = 0; k < SA; ++k) {
+        const uint32_t j = (uint32_t)(tid + 256 * k);
+        const uint32_t q = j < r.na ? r.a0 + j : 0u;
+        R.pa[k] = *reinterpret_cast<const uint32_t*>(pc + q * 4u);
+        R.oa[k] = *reinterpret_cast<const uint16_t*>(ac + q * 2u);
     }
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        const uint32_t e = o.b0 + sub + 8 * k;
-        const uint32_t se = e < (uint32_t)m ? e : (uint32_t)(m - 1);
-        c.ib[k] = ix[se];
-        c.vb[k] = v[se];
-        c.valid |= (uint32_t)(o.ok && !inner && e < o.b1) << (16 + k);
+    for (int k = 0; k < SB; ++k) {
+        const uint32_t j = (uint32_t)(tid + 256 * k);
+        const uint32_t q = j < r.nb ? r.b0 + j : 0u;
+        R.pb[k] = *reinterpret_cast<const uint32_t*>(pc + q * 4u);
+        R.ob[k] = *reinterpret_cast<const uint16_t*>(bc + q * 2u);
     }
-    return c;
+}
+
+template <bool SPLIT, int LO>
+__device__ inline void lds_put(unsigned char* base, uint32_t off, uint32_t pv)
+{
+    if constexpr (SPLIT) {
+        *reinterpret_cast<unsigned short*>(base + off) = (unsigned short)pv;
+        *reinterpret_cast<unsigned short*>(base + off + LO) = (unsigned short)(pv >> 16);
+    } else {
+        *reinterpret_cast<uint32_t*>(base + off) = pv;
+    }
 }
 
 // The split products hi*hi + hi*lo + lo*hi drop lo*lo, which biases every
 // diagonal entry low by the mean of lo^2 (about 2.5e-6 relative); inner tiles
-// therefore also sum the squares v*v of their column block's entries exactly
-// in FP64 and those sums replace the matrix-core diagonal.
+// therefore also sum (hi + lo)^2 of their column block's entries in FP64 and
+// those sums replace the matrix-core diagonal (hi + lo is v to 2^-16
+// relative, with no systematic bias).
 template <bool SPLIT>
-__device__ inline void add_square(MfmaLds<SPLIT>& L, int coord_a, int boff, int tc, float v)
+__device__ inline void add_square(double* diag, uint32_t oa, uint32_t pv, int boff, int tc)
 {
     if constexpr (SPLIT) {
-        const int c = coord_a - boff;
-        if (c >= 0 && c < tc) atomicAdd(&L.diag[c], (double)v * (double)v);
-    }
-}
-
-template <bool SPLIT, int KA, int KB>
-__device__ inline void put_entries(MfmaLds<SPLIT>& L, const ChunkEntries<KA, KB>& c, int s, bool clear, bool inner,
-                                   int a_base, int b_base, int boff, int tc)
-{
-#pragma unroll
-    for (int k = 0; k < KA; ++k) {
-        if ((c.valid >> k) & 1u) {
-            const int coord = (int)c.ia[k] - a_base;
-            scatter_entry<SPLIT>(L, false, coord, s, clear ? 0.0f : c.va[k]);
-            if (inner && !clear) add_square<SPLIT>(L, coord, boff, tc, c.va[k]);
+        const int c = (int)(oa / (uint32_t)(kBfStride * 2)) - boff;
+        if (c >= 0 && c < tc) {
+            const double v = (double)bf16_bits_to_float((unsigned short)pv) +
+                             (double)bf16_bits_to_float((unsigned short)(pv >> 16));
+            atomicAdd(&diag[c], v * v);
         }
     }
-#pragma unroll
-    for (int k = 0; k < KB; ++k)
-        if ((c.valid >> (16 + k)) & 1u) scatter_entry<SPLIT>(L, true, (int)c.ib[k] - b_base, s, clear ? 0.0f : c.vb[k]);
 }
 
-// entries past the register share of a sample (rare): direct loads
 template <bool SPLIT>
-__device__ inline void put_overflow(MfmaLds<SPLIT>& L, const float* __restrict__ vals, const uint16_t* __restrict__ idx,
-                                    int m, int64_t i, const ChunkOffsets& o, int s, int sub, int a_base, int b_base,
-                                    bool inner, int boff, int tc, int ka, int kb, bool clear)
+__device__ inline unsigned char* tile_base(MfmaLds<SPLIT>& L, bool col)
 {
-    if (!o.ok) return;
-    const float* v = vals + i * (int64_t)m;
-    const uint16_t* ix = idx + i * (int64_t)m;
-    for (uint32_t e = o.a0 + 8 * ka + sub; e < o.a1; e += 8) {
-        const int coord = (int)ix[e] - a_base;
-        scatter_entry<SPLIT>(L, false, coord, s, clear ? 0.0f : v[e]);
-        if (inner && !clear) add_square<SPLIT>(L, coord, boff, tc, v[e]);
-    }
-    if (!inner)
-        for (uint32_t e = o.b0 + 8 * kb + sub; e < o.b1; e += 8)
-            scatter_entry<SPLIT>(L, true, (int)ix[e] - b_base, s, clear ? 0.0f : v[e]);
+    if constexpr (SPLIT)
+        return reinterpret_cast<unsigned char*>(col ? L.bhi : L.ahi);
+    else
+        return reinterpret_cast<unsigned char*>(col ? L.b : L.a);
 }
 
-template <bool SPLIT, int KA, int KB>
-__global__ __launch_bounds__(256, 2) void k_gram_mfma(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
-                                                      const uint32_t* __restrict__ off, int m, TileGeom g, int64_t n,
+constexpr int kLoA = kTR * kBfStride * 2;
+constexpr int kLoB = kTC * kBfStride * 2;
+
+// Scatter (or clear) one chunk's register share, then any run entries past it
+// (more than 256 SA or 256 SB in the chunk: a workgroup-uniform branch, direct
+// loads four at a time).
+template <bool SPLIT, int SA, int SB>
+__device__ inline void put_chunk(MfmaLds<SPLIT>& L, const ChunkRegs<SA, SB>& R, const ChunkRun& r, bool clear,
+                                 bool inner, int boff, int tc, const uint32_t* __restrict__ P,
+                                 const uint16_t* __restrict__ OA, const uint16_t* __restrict__ OB, int64_t cbase,
+                                 int tid)
+{
+    unsigned char* ta = tile_base<SPLIT>(L, false);
+    unsigned char* tb = tile_base<SPLIT>(L, true);
+#pragma unroll
+    for (int k = 0; k < SA; ++k)
+        if ((uint32_t)(tid + 256 * k) < r.na) {
+            lds_put<SPLIT, kLoA>(ta, R.oa[k], clear ? 0u : R.pa[k]);
+            if (inner && !clear) add_square<SPLIT>(L.diag_ptr(), R.oa[k], R.pa[k], boff, tc);
+        }
+#pragma unroll
+    for (int k = 0; k < SB; ++k)
+        if ((uint32_t)(tid + 256 * k) < r.nb) lds_put<SPLIT, kLoB>(tb, R.ob[k], clear ? 0u : R.pb[k]);
+    const uint32_t* pc = P + cbase;
+    const uint16_t* ac = OA + cbase;
+    const uint16_t* bc = OB + cbase;
+    if (r.na > 256u * SA) {
+        for (uint32_t j0 = 256u * SA; j0 < r.na; j0 += 1024u) {
+            uint32_t pv[4], ov[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t j = j0 + 256u * u + (uint32_t)tid;
+                const uint32_t q = j < r.na ? r.a0 + j : 0u;
+                ov[u] = ac[q];
+                pv[u] = clear ? 0u : pc[q];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j0 + 256u * u + (uint32_t)tid < r.na) {
+                    lds_put<SPLIT, kLoA>(ta, ov[u], pv[u]);
+                    if (inner && !clear) add_square<SPLIT>(L.diag_ptr(), ov[u], pv[u], boff, tc);
+                }
+        }
+    }
+    if (r.nb > 256u * SB) {
+        for (uint32_t j0 = 256u * SB; j0 < r.nb; j0 += 1024u) {
+            uint32_t pv[4], ov[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t j = j0 + 256u * u + (uint32_t)tid;
+                const uint32_t q = j < r.nb ? r.b0 + j : 0u;
+                ov[u] = bc[q];
+                pv[u] = clear ? 0u : pc[q];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j0 + 256u * u + (uint32_t)tid < r.nb) lds_put<SPLIT, kLoB>(tb, ov[u], pv[u]);
+        }
+    }
+}
+
+template <bool SPLIT, int SA, int SB>
+__global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict__ P, const uint16_t* __restrict__ OA,
+                                                      const uint16_t* __restrict__ OB, const uint32_t* __restrict__ BS, int m, TileGeom g, int64_t n,
                                                       int nsplit, int64_t split_len, float* __restrict__ part,
                                                       double* __restrict__ pdiag)
 {
@@ -278,17 +436,15 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const float* __restrict__ 
     const int tile = (int)(item % g.ntiles);
     int ta, tb;
     decode_rect_tile(tile, g, ta, tb);
-    const int a_base = ta * g.tr, b_base = tb * g.tc;
     const bool inner = tb < (ta + 1) * g.ratio;  // column block inside the row block
-    const int boff = b_base - a_base;            // row of the column block inside the row tile (inner)
-    const int nbo = g.nbc;                       // offsets are per column block
-    const int oa0 = ta * g.ratio, oa1 = (ta + 1) * g.ratio, ob0 = tb;
+    const int boff = tb * g.tc - ta * g.tr;      // row of the column block inside the row tile (inner)
+    const int nb1 = g.nbc + 1;
+    const int ba0 = ta * g.ratio, ba1 = (ta + 1) * g.ratio;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int s = tid >> 3, sub = tid & 7;
 
     {
         uint4* z = reinterpret_cast<uint4*>(smem_raw);
@@ -307,47 +463,57 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const float* __restrict__ 
     const int64_t sbeg = (int64_t)split * split_len;
     int64_t send = sbeg + split_len;
     if (send > n) send = n;
-    const int64_t i_safe = sbeg;
+    const int64_t c0 = sbeg / kChunk, c1 = (send + kChunk - 1) / kChunk;
+    const int64_t cstride = (int64_t)kChunk * m;
 
-    // pipeline: offsets two chunks ahead, entries one chunk ahead
-    ChunkOffsets o_cur = load_offsets(off, nbo, send, sbeg + s, i_safe, oa0, oa1, ob0);
-    ChunkEntries<KA, KB> e_cur = load_entries<KA, KB>(vals, idx, m, send, sbeg + s, i_safe, o_cur, sub, inner);
-    ChunkOffsets o_next = load_offsets(off, nbo, send, sbeg + kChunk + s, i_safe, oa0, oa1, ob0);
-    ChunkEntries<KA, KB> e_prev;
-    e_prev.valid = 0;
-    ChunkOffsets o_prev{0, 0, 0, 0, false};
-    int64_t i_prev = send;
+    // pipeline: runs two chunks ahead, entries one chunk ahead
+    const int rcol = chunk_run_col(ba0, ba1, tb, inner, lane);
+    ChunkRun r_cur = chunk_run_unpack(chunk_run_load(BS, nb1, c0, true, c0, rcol), true);
+    ChunkRegs<SA, SB> R_cur, R_prev;
+#pragma unroll
+    for (int k = 0; k < SA; ++k) R_prev.pa[k] = R_prev.oa[k] = 0;
+#pragma unroll
+    for (int k = 0; k < SB; ++k) R_prev.pb[k] = R_prev.ob[k] = 0;
+    load_chunk<SA, SB>(R_cur, P, OA, OB, c0 * cstride, r_cur, tid);  // c0 < c1: a range is never empty
+    uint32_t v_next = chunk_run_load(BS, nb1, c0 + 1, c0 + 1 < c1, c0, rcol);
+    ChunkRun r_prev{0, 0, 0, 0};
+    int64_t c_prev = c0;
 
     // column operand rows: the column tile, or the row tile at offset boff
     const unsigned short* bh_src = nullptr;
     const unsigned short* bl_src = nullptr;
     const float* bf_src = nullptr;
-    int brow0;
     if constexpr (SPLIT) {
         bh_src = inner ? L.ahi : L.bhi;
         bl_src = inner ? L.alo : L.blo;
     } else {
         bf_src = inner ? L.a : L.b;
     }
-    brow0 = (inner ? boff : 0) + wc * 64;
+    const int brow0 = (inner ? boff : 0) + wc * 64;
 
-    for (int64_t s0 = sbeg; s0 < send; s0 += kChunk) {
-        const int64_t i_cur = s0 + s;
+    for (int64_t c = c0; c < c1; ++c) {
         __syncthreads();
-        // clear the previous chunk's slots, then scatter this chunk (the
-        // writers of a sample slot are one wave, so their LDS writes stay ordered)
-        put_entries<SPLIT, KA, KB>(L, e_prev, s, true, inner, a_base, b_base, boff, g.tc);
-        put_overflow<SPLIT>(L, vals, idx, m, i_prev, o_prev, s, sub, a_base, b_base, inner, boff, g.tc, KA, KB, true);
-        put_entries<SPLIT, KA, KB>(L, e_cur, s, false, inner, a_base, b_base, boff, g.tc);
-        put_overflow<SPLIT>(L, vals, idx, m, i_cur, o_cur, s, sub, a_base, b_base, inner, boff, g.tc, KA, KB, false);
+        // clear the previous chunk's slots, then scatter this chunk; a slot is
+        // cleared and written by different waves, so a barrier orders the two
+        if (c > c0) {
+            put_chunk<SPLIT, SA, SB>(L, R_prev, r_prev, true, inner, boff, g.tc, P, OA, OB, c_prev * cstride, tid);
+            __syncthreads();
+        }
+        put_chunk<SPLIT, SA, SB>(L, R_cur, r_cur, false, inner, boff, g.tc, P, OA, OB, c * cstride, tid);
         __syncthreads();
-        e_prev = e_cur;
-        o_prev = o_cur;
-        i_prev = i_cur;
-        // loads for the next chunks fly while this chunk runs on the matrix cores
-        e_cur = load_entries<KA, KB>(vals, idx, m, send, s0 + kChunk + s, i_safe, o_next, sub, inner);
-        o_cur = o_next;
-        o_next = load_offsets(off, nbo, send, s0 + 2 * kChunk + s, i_safe, oa0, oa1, ob0);
+#pragma unroll
+        for (int k = 0; k < SA; ++k) R_prev.oa[k] = R_cur.oa[k];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) R_prev.ob[k] = R_cur.ob[k];
+        r_prev = r_cur;
+        c_prev = c;
+        // loads for the next chunks fly while this chunk runs on the matrix cores;
+        // the entry loads are unconditional (an empty run past the range reads
+        // this chunk's entry 0), so no value merges after them and nothing
+        // waits for them before the matrix-core block
+        r_cur = chunk_run_unpack(v_next, c + 1 < c1);
+        load_chunk<SA, SB>(R_cur, P, OA, OB, (c + 1 < c1 ? c + 1 : c) * cstride, r_cur, tid);
+        v_next = chunk_run_load(BS, nb1, c + 2, c + 2 < c1, c, rcol);
         // keep the scheduler from sinking those loads (or their address math)
         // into the matrix-core block, where their waits would stall it
         __builtin_amdgcn_sched_barrier(0);
@@ -549,22 +715,34 @@ __global__ __launch_bounds__(256) void k_cov_finalize(const double* __restrict__
 // ---------------------------------------------------------------------------
 struct GramPlan {
     TileGeom geom;
-    int nsplit, ka, kb;
-    int64_t split_len;
-    size_t off_bytes, part_bytes, diag_bytes;
+    int nsplit, sa, sb;
+    int64_t split_len, nchunks;
+    size_t off_bytes;               // FP64 variant: per-sample block offsets
+    size_t pk_bytes, bs_bytes;      // matrix-core variants: packed chunks (P, OA, OB) and block starts
+    size_t part_bytes, diag_bytes;
 };
 
-// Register slots per thread for a block of w coordinates: the kept count of a
-// sample in the block is hypergeometric (m draws, w of p marked); 8 slots per
-// thread-group step, enough for the mean plus four standard deviations.
-static int slots_for(int p, int m, int w)
+static size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Block offsets per sample (FP64 variant): the kept count of a sample in a
+// block of w coordinates is hypergeometric (m draws, w of p marked).
+static double block_count_var(int p, int m, int w)
 {
-    const double mu = (double)m * w / p;
-    const double var = (p > 1) ? (double)m * ((double)w / p) * (1.0 - (double)w / p) * (double)(p - m) / (p - 1) : 0.0;
-    int k = (int)((mu + 4.0 * sqrt(var) + 7.999) / 8.0);
-    k = (k + 1) & ~1;
-    if (k < 2) k = 2;
-    if (k > 8) k = 8;
+    return (p > 1) ? (double)m * ((double)w / p) * (1.0 - (double)w / p) * (double)(p - m) / (p - 1) : 0.0;
+}
+
+// Register slots per thread for a chunk's run in a block of w coordinates:
+// 256 entries per slot, enough for the mean plus four standard deviations of
+// the chunk's count (a sum of kChunk independent hypergeometric counts),
+// rounded up to a power of two, at most 8 (longer runs take the uniform
+// overflow loop).
+static int run_slots(int p, int m, int w)
+{
+    const double mu = (double)kChunk * m * w / p;
+    const double sd = sqrt((double)kChunk * block_count_var(p, m, w));
+    const int need = (int)((mu + 4.0 * sd + 255.999) / 256.0);
+    int k = 1;
+    while (k < need && k < 8) k <<= 1;
     return k;
 }
 
@@ -572,10 +750,11 @@ static GramPlan gram_plan(int prec, int p, int m, int64_t n, const DeviceInfo& d
 {
     GramPlan g;
     g.geom = (prec == 0) ? make_geom(p, kTileF64, kTileF64) : make_geom(p, kTR, kTC);
-    g.ka = slots_for(p, m, g.geom.tr);
-    g.kb = slots_for(p, m, g.geom.tc);
-    if (g.kb > g.ka) g.kb = g.ka;
+    g.sa = run_slots(p, m, g.geom.tr);
+    g.sb = run_slots(p, m, g.geom.tc);
+    if (g.sb > g.sa) g.sb = g.sa;
     const int64_t nchunks = (n + kChunk - 1) / kChunk;
+    g.nchunks = nchunks;
     int64_t ns = (prec == 0) ? 1 : (n + kMaxSamplesPerSplit - 1) / kMaxSamplesPerSplit;
     const int64_t want = ((int64_t)dev.cus * 4 + g.geom.ntiles - 1) / g.geom.ntiles;  // enough workgroups
     if (ns < want) ns = want;
@@ -585,9 +764,17 @@ static GramPlan gram_plan(int prec, int p, int m, int64_t n, const DeviceInfo& d
     g.split_len = chunks_per * kChunk;
     g.nsplit = (int)((n + g.split_len - 1) / g.split_len);
     if (g.nsplit < 1) g.nsplit = 1;
-    g.off_bytes = (((size_t)(n > 0 ? n : 0) * (g.geom.nbc + 1) * 4) + 255) & ~(size_t)255;
+    const size_t nn = (size_t)(n > 0 ? n : 0);
+    if (prec == 0) {
+        g.off_bytes = up256(nn * (g.geom.nbc + 1) * 4);
+        g.pk_bytes = g.bs_bytes = 0;
+    } else {
+        g.off_bytes = 0;
+        g.pk_bytes = 2 * up256(nn * (size_t)m * 4);  // P (4 B per entry), then OA and OB (2 B each)
+        g.bs_bytes = up256((size_t)nchunks * (g.geom.nbc + 1) * 4);
+    }
     const size_t pe = (prec == 0) ? sizeof(double) : sizeof(float);
-    g.part_bytes = (((size_t)g.nsplit * g.geom.ntiles * (size_t)g.geom.tr * g.geom.tc * pe) + 255) & ~(size_t)255;
+    g.part_bytes = up256((size_t)g.nsplit * g.geom.ntiles * (size_t)g.geom.tr * g.geom.tc * pe);
     g.diag_bytes = (prec == 2) ? (size_t)g.nsplit * g.geom.ntiles * (size_t)g.geom.tc * sizeof(double) : 0;
     return g;
 }
@@ -596,47 +783,49 @@ size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo&
 {
     if (n <= 0) return 0;
     GramPlan g = gram_plan(prec, p, m, n, dev);
-    return g.off_bytes + g.part_bytes + g.diag_bytes;
+    return g.off_bytes + g.pk_bytes + g.bs_bytes + g.part_bytes + g.diag_bytes;
 }
 
-template <bool SPLIT, int KA, int KB>
-static void launch_mfma_kernel(const GramPlan& g, int64_t grid, const float* vals, const uint16_t* idx,
-                               const uint32_t* off, int m, int64_t n, float* part, double* pdiag, hipStream_t s)
+template <bool SPLIT, int SA, int SB>
+static void launch_mfma_kernel(const GramPlan& g, int64_t grid, const uint32_t* P, const uint16_t* OA,
+                               const uint16_t* OB, const uint32_t* BS, int m, int64_t n, float* part, double* pdiag, hipStream_t s)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_mfma<SPLIT, KA, KB>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_mfma<SPLIT, SA, SB>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(MfmaLds<SPLIT>));
         attr_set = true;
     }
     {
         ProfScope ps_(SPLIT ? "gram_bf16x3" : "gram_f32", s);
-        hipLaunchKernelGGL((k_gram_mfma<SPLIT, KA, KB>), dim3((unsigned)grid), dim3(256), sizeof(MfmaLds<SPLIT>), s,
-                           vals, idx, off, m, g.geom, n, g.nsplit, g.split_len, part, pdiag);
+        hipLaunchKernelGGL((k_gram_mfma<SPLIT, SA, SB>), dim3((unsigned)grid), dim3(256), sizeof(MfmaLds<SPLIT>), s,
+                           P, OA, OB, BS, m, g.geom, n, g.nsplit, g.split_len, part, pdiag);
     }
 }
 
 template <bool SPLIT>
-static void dispatch_mfma(const GramPlan& g, int64_t grid, const float* vals, const uint16_t* idx,
-                          const uint32_t* off, int m, int64_t n, float* part, double* pdiag, hipStream_t s)
+static void dispatch_mfma(const GramPlan& g, int64_t grid, const uint32_t* P, const uint16_t* OA,
+                          const uint16_t* OB, const uint32_t* BS, int m, int64_t n, float* part, double* pdiag, hipStream_t s)
 {
-#define PDS_GRAM_CASE(A, B)                                                                 \
-    if (g.ka == A && g.kb == B) {                                                           \
-        launch_mfma_kernel<SPLIT, A, B>(g, grid, vals, idx, off, m, n, part, pdiag, s); \
-        return;                                                                             \
+#define PDS_GRAM_CASE(A, B)                                                                   \
+    if (g.sa == A && g.sb == B) {                                                             \
+        launch_mfma_kernel<SPLIT, A, B>(g, grid, P, OA, OB, BS, m, n, part, pdiag, s);           \
+        return;                                                                               \
     }
+    PDS_GRAM_CASE(1, 1)
+    PDS_GRAM_CASE(2, 1)
     PDS_GRAM_CASE(2, 2)
+    PDS_GRAM_CASE(4, 1)
     PDS_GRAM_CASE(4, 2)
     PDS_GRAM_CASE(4, 4)
-    PDS_GRAM_CASE(6, 2)
-    PDS_GRAM_CASE(6, 4)
-    PDS_GRAM_CASE(6, 6)
+    PDS_GRAM_CASE(8, 1)
     PDS_GRAM_CASE(8, 2)
     PDS_GRAM_CASE(8, 4)
-    PDS_GRAM_CASE(8, 6)
     PDS_GRAM_CASE(8, 8)
 #undef PDS_GRAM_CASE
 }
+
+static size_t pack_lds_bytes(int nbc) { return ((size_t)kChunk * (nbc + 1) + (size_t)kChunk * nbc + 4) * 4; }
 
 hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n,
                                         double* acc, void* ws, size_t ws_bytes, const DeviceInfo& dev,
@@ -645,31 +834,51 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
     (void)ws_bytes;
     if (n <= 0) return hipSuccess;
     GramPlan g = gram_plan(prec, p, m, n, dev);
-    uint32_t* off = reinterpret_cast<uint32_t*>(ws);
-    void* part = reinterpret_cast<unsigned char*>(ws) + g.off_bytes;
-    double* pdiag = (prec == 2)
-                        ? reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(ws) + g.off_bytes + g.part_bytes)
-                        : nullptr;
-    {
-        const int64_t threads = n * (int64_t)(g.geom.nbc + 1);
-        ProfScope ps_("block_offsets", s);
-        hipLaunchKernelGGL(k_block_offsets, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, idx, n, m,
-                           g.geom.tc, g.geom.nbc, off);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+    void* part = w + g.off_bytes + g.pk_bytes + g.bs_bytes;
+    double* pdiag = (prec == 2) ? reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(part) + g.part_bytes)
+                                : nullptr;
     const int64_t total = (int64_t)g.geom.ntiles * g.nsplit;
     const int64_t grid = ((total + 7) / 8) * 8;
+    hipError_t e;
     if (prec == 0) {
+        uint32_t* off = reinterpret_cast<uint32_t*>(w);
+        {
+            const int64_t threads = n * (int64_t)(g.geom.nbc + 1);
+            ProfScope ps_("block_offsets", s);
+            hipLaunchKernelGGL(k_block_offsets, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, idx, n, m,
+                               g.geom.tc, g.geom.nbc, off);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
         ProfScope ps_("gram_f64", s);
         hipLaunchKernelGGL(k_gram_f64, dim3((unsigned)grid), dim3(256), 0, s, reinterpret_cast<const double*>(vals),
                            idx, off, m, g.geom, n, g.nsplit, g.split_len, reinterpret_cast<double*>(part));
-    } else if (prec == 2) {
-        dispatch_mfma<true>(g, grid, reinterpret_cast<const float*>(vals), idx, off, m, n,
-                            reinterpret_cast<float*>(part), pdiag, s);
     } else {
-        dispatch_mfma<false>(g, grid, reinterpret_cast<const float*>(vals), idx, off, m, n,
-                             reinterpret_cast<float*>(part), nullptr, s);
+        uint32_t* P = reinterpret_cast<uint32_t*>(w);
+        uint16_t* OA = reinterpret_cast<uint16_t*>(w + g.pk_bytes / 2);
+        uint16_t* OB = reinterpret_cast<uint16_t*>(w + g.pk_bytes / 2 + g.pk_bytes / 4);
+        uint32_t* BS = reinterpret_cast<uint32_t*>(w + g.pk_bytes);
+        const bool split = (prec == 2);
+        const size_t lds = pack_lds_bytes(g.geom.nbc);
+        static bool pack_attr = false;
+        if (!pack_attr) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)pack_lds_bytes(65536 / kTC));
+            pack_attr = true;
+        }
+        {
+            ProfScope ps_("gram_pack", s);
+            hipLaunchKernelGGL(k_gram_pack, dim3((unsigned)g.nchunks), dim3(256), lds, s,
+                               reinterpret_cast<const float*>(vals), idx, n, m, g.geom.tr, g.geom.tc, g.geom.nbc,
+                               split ? kBfStride * 2 : kF32Stride * 4, split ? 1 : 0, P, OA, OB, BS);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (split)
+            dispatch_mfma<true>(g, grid, P, OA, OB, BS, m, n, reinterpret_cast<float*>(part), pdiag, s);
+        else
+            dispatch_mfma<false>(g, grid, P, OA, OB, BS, m, n, reinterpret_cast<float*>(part), nullptr, s);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

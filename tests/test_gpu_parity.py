@@ -126,8 +126,11 @@ def test_compress_empty_is_noop():
 
 
 # ---------------------------------------------------------------- covariance --
+# the last three run many 32-sample chunks per workgroup (the clear-then-write
+# order between chunks), the dense one through the long-run overflow loops
 COV_SHAPES = [(2, 2, 50), (16, 4, 33), (64, 7, 1000), (128, 20, 31), (256, 26, 2000), (512, 64, 4099),
-              (1024, 51, 20000), (4096, 410, 3000), (8192, 200, 100), (256, 256, 300)]
+              (1024, 51, 20000), (4096, 410, 3000), (8192, 200, 100), (256, 256, 300),
+              (256, 26, 40000), (2048, 205, 30000), (1024, 1024, 2000)]
 
 
 @pytest.mark.parametrize("prec", list(PRECS))
