@@ -192,20 +192,25 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     const int sh_c = __builtin_ctz((unsigned)tc);
 
     // block starts: block b begins at the first entry whose block number
-    // reaches b, which the entry finds by comparing with its predecessor
-    for (int s = 0; s < kChunk; ++s) {
-        if (s >= ns) {
-            for (int b = tid; b < nb1; b += 256) off[s * nb1 + b] = 0;
-            continue;
-        }
-        const uint16_t* row = idx + (i0 + s) * (int64_t)m;
-        for (int e = tid; e < m; e += 256) {
-            const int be = (int)row[e] >> sh_c;
-            const int bp = e > 0 ? ((int)row[e - 1] >> sh_c) : -1;
-            for (int b = bp + 1; b <= be; ++b) off[s * nb1 + b] = (uint32_t)e;
-            if (e == m - 1)
-                for (int b = be + 1; b <= nbc; ++b) off[s * nb1 + b] = (uint32_t)m;
-        }
+    // reaches b, which the entry finds by comparing with its predecessor.  The
+    // chunk's index rows are one contiguous range, walked flat (entry f of the
+    // chunk is entry e = f - s m of sample s) so that loads stay in flight.
+    const uint16_t* cidx = idx + i0 * (int64_t)m;
+    const int tot = ns * m;
+    const float inv_m = 1.0f / (float)m;
+    for (int s = ns; s < kChunk; ++s)
+        for (int b = tid; b < nb1; b += 256) off[s * nb1 + b] = 0;
+#pragma unroll 4
+    for (int f = tid; f < tot; f += 256) {
+        int s = (int)((float)f * inv_m);
+        if (s * m > f) --s;
+        if ((s + 1) * m <= f) ++s;
+        const int e = f - s * m;
+        const int be = (int)cidx[f] >> sh_c;
+        const int bp = e > 0 ? ((int)cidx[f - 1] >> sh_c) : -1;
+        for (int b = bp + 1; b <= be; ++b) off[s * nb1 + b] = (uint32_t)e;
+        if (e == m - 1)
+            for (int b = be + 1; b <= nbc; ++b) off[s * nb1 + b] = (uint32_t)m;
     }
     __syncthreads();
 
@@ -239,17 +244,18 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     uint32_t* Pc = P + c * (int64_t)kChunk * m;
     uint16_t* OAc = OA + c * (int64_t)kChunk * m;
     uint16_t* OBc = OB + c * (int64_t)kChunk * m;
-    for (int s = 0; s < ns; ++s) {
-        const uint16_t* row = idx + (i0 + s) * (int64_t)m;
-        const float* vrow = vals + (i0 + s) * (int64_t)m;
-        for (int e = tid; e < m; e += 256) {
-            const uint32_t j = row[e];
-            const uint32_t q = seg[((int)j >> sh_c) * kChunk + s] + (uint32_t)e;
-            const float v = vrow[e];
-            Pc[q] = split ? split_bits(v) : __float_as_uint(v);
-            OAc[q] = (uint16_t)((j & (uint32_t)(tr - 1)) * rowbytes + s * eb);
-            OBc[q] = (uint16_t)((j & (uint32_t)(tc - 1)) * rowbytes + s * eb);
-        }
+    const float* cval = vals + i0 * (int64_t)m;
+#pragma unroll 4
+    for (int f = tid; f < tot; f += 256) {
+        int s = (int)((float)f * inv_m);
+        if (s * m > f) --s;
+        if ((s + 1) * m <= f) ++s;
+        const uint32_t j = cidx[f];
+        const uint32_t q = seg[((int)j >> sh_c) * kChunk + s] + (uint32_t)(f - s * m);
+        const float v = cval[f];
+        Pc[q] = split ? split_bits(v) : __float_as_uint(v);
+        OAc[q] = (uint16_t)((j & (uint32_t)(tr - 1)) * rowbytes + s * eb);
+        OBc[q] = (uint16_t)((j & (uint32_t)(tc - 1)) * rowbytes + s * eb);
     }
 }
 
@@ -517,6 +523,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
         // keep the scheduler from sinking those loads (or their address math)
         // into the matrix-core block, where their waits would stall it
         __builtin_amdgcn_sched_barrier(0);
+        // raised issue priority for the matrix-core block: when both
+        // workgroups of a CU reach it together, one runs ahead and the two
+        // fall back into alternating scatter and matrix-core phases
+        __builtin_amdgcn_s_setprio(1);
         if constexpr (SPLIT) {
 #pragma unroll
             for (int kk = 0; kk < kChunk; kk += 16) {
@@ -567,6 +577,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
                         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
             }
         }
+        __builtin_amdgcn_s_setprio(0);
     }
 
     // write this range's FP32 tile: part[split][tile][i][j], i < tr, j < tc
