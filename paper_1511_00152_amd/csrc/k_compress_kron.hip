@@ -79,27 +79,33 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
     }
     __syncthreads();
 
-    // constant operands: stage-1 B = H[16 kb + 8 h + j][32 cb + i32],
-    // stage-2 A = H[32 rb2 + i32][zrow(rb, kk, h, j)]
-    Parts8 hb1[4][2], ha2[2][2][2];
+    // Constant +-1 operands.  Stage 1's B operand at (kb, cb) holds
+    // H[16 kb + 8 h + j][32 cb + i32], j < 8; the row index splits into
+    // disjoint bits 16 kb + 8 h and j, so the entry is the sign of
+    // popc((16 kb + 8 h) & c) times the sign of popc(j & c): one 8-entry
+    // pattern per lane (hb_base) and one sign per (kb, cb) (hb_neg).  Stage 2's
+    // A operand at (rb2, rb, kk) holds H[32 rb2 + i32][zrow(rb, kk, h, j)]; the
+    // column splits into 32 rb + 16 kk + 4 h and 8 (j / 4) + j % 4 likewise
+    // (ha_base, ha_neg).  A sign flips the sign bits of all eight bf16 values.
+    uint32_t hb_base[4], ha_base[4], hb_neg[8], ha_neg[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        hb_base[k] = hsign_bits(2 * k, i32) | (hsign_bits(2 * k + 1, i32) << 16);
+        ha_base[k] = hsign_bits(i32, zrow(0, 0, 0, 2 * k)) | (hsign_bits(i32, zrow(0, 0, 0, 2 * k + 1)) << 16);
+    }
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                hb1[kb][cb].w[k] = hsign_bits(16 * kb + 8 * h + 2 * k, 32 * cb + i32) |
-                                   (hsign_bits(16 * kb + 8 * h + 2 * k + 1, 32 * cb + i32) << 16);
+            hb_neg[kb * 2 + cb] = (__popc((16 * kb + 8 * h) & (32 * cb + i32)) & 1) ? 0x80008000u : 0u;
 #pragma unroll
     for (int rb2 = 0; rb2 < 2; ++rb2)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    ha2[rb2][rb][kk].w[k] = hsign_bits(32 * rb2 + i32, zrow(rb, kk, h, 2 * k)) |
-                                            (hsign_bits(32 * rb2 + i32, zrow(rb, kk, h, 2 * k + 1)) << 16);
+                ha_neg[(rb2 * 2 + rb) * 2 + kk] =
+                    (__popc((32 * rb2 + i32) & (32 * rb + 16 * kk + 4 * h)) & 1) ? 0x80008000u : 0u;
 
     // this lane's signs: element 64 (32 rb + i32) + 16 kb + 8 h + j
     uint64_t negmask = 0;
@@ -113,9 +119,15 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
                 negmask |= (uint64_t)((negbits[e >> 5] >> (e & 31)) & 1u) << (32 * rb + 8 * kb + j);
             }
 
+    // A lane's whole share of the row (16 x 16 B) is requested at once, so a
+    // sample waits on memory once; the second wave of the SIMD computes
+    // meanwhile.
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < n; i += nwaves) {
-        const float* row = X + i * ldx;
+        // the sign bits are re-read from this register every sample: otherwise
+        // the 64 per-element sign words are hoisted out of the loop and take
+        // 64 registers for the whole kernel
+        asm volatile("" : "+v"(negmask));
         // stage 1: Z = X H
         kf32x16 z[2][2];
 #pragma unroll
@@ -124,12 +136,20 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) z[rb][cb][r] = 0.0f;
+        float4 cur[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            cur[q] = reinterpret_cast<const float4*>(X + i * ldx + 64 * (32 * (q >> 3) + i32) + 16 * ((q >> 1) & 3) +
+                                                     8 * h)[q & 1];
+        // the loads stay here (not sunk to their uses), and each split-and-
+        // multiply block below is scheduled on its own, which bounds the
+        // registers live at once
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-                const float4* src = reinterpret_cast<const float4*>(row + 64 * (32 * rb + i32) + 16 * kb + 8 * h);
-                const float4 u0 = src[0], u1 = src[1];
+                const float4 u0 = cur[rb * 8 + kb * 2], u1 = cur[rb * 8 + kb * 2 + 1];
                 float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -140,11 +160,15 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
                 split3(v, ph, pm, pl);
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
-                    const kbf16x8 hb = as_bf16x8(hb1[kb][cb]);
+                    Parts8 hw;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) hw.w[k] = hb_base[k] ^ hb_neg[kb * 2 + cb];
+                    const kbf16x8 hb = as_bf16x8(hw);
                     z[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ph), hb, z[rb][cb], 0, 0, 0);
                     z[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(pm), hb, z[rb][cb], 0, 0, 0);
                     z[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(pl), hb, z[rb][cb], 0, 0, 0);
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         // stage 2: Y = H Z, K over Z's rows in accumulator order.  Column block
@@ -170,11 +194,15 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
                     split3(v, ph, pm, pl);
 #pragma unroll
                     for (int rb2 = 0; rb2 < 2; ++rb2) {
-                        const kbf16x8 ha = as_bf16x8(ha2[rb2][rb][kk]);
+                        Parts8 aw;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) aw.w[k] = ha_base[k] ^ ha_neg[(rb2 * 2 + rb) * 2 + kk];
+                        const kbf16x8 ha = as_bf16x8(aw);
                         y[rb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha, as_bf16x8(ph), y[rb2], 0, 0, 0);
                         y[rb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha, as_bf16x8(pm), y[rb2], 0, 0, 0);
                         y[rb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha, as_bf16x8(pl), y[rb2], 0, 0, 0);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
             for (int rb2 = 0; rb2 < 2; ++rb2)
