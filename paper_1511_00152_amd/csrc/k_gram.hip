@@ -372,7 +372,8 @@ constexpr int kLoB = kTC * kBfStride * 2;
 // (more than 256 SA or 256 SB in the chunk: a workgroup-uniform branch, direct
 // loads four at a time).
 template <bool SPLIT, int SA, int SB>
-__device__ inline void put_chunk(MfmaLds<SPLIT>& L, const ChunkRegs<SA, SB>& R, const ChunkRun& r, bool clear,
+__device__ inline void put_chunk(MfmaLds<SPLIT>& L, double* diag, const ChunkRegs<SA, SB>& R, const ChunkRun& r,
+                                 bool clear,
                                  bool inner, int boff, int tc, const uint32_t* __restrict__ P,
                                  const uint16_t* __restrict__ OA, const uint16_t* __restrict__ OB, int64_t cbase,
                                  int tid)
@@ -383,7 +384,7 @@ __device__ inline void put_chunk(MfmaLds<SPLIT>& L, const ChunkRegs<SA, SB>& R, 
     for (int k = 0; k < SA; ++k)
         if ((uint32_t)(tid + 256 * k) < r.na) {
             lds_put<SPLIT, kLoA>(ta, R.oa[k], clear ? 0u : R.pa[k]);
-            if (inner && !clear) add_square<SPLIT>(L.diag_ptr(), R.oa[k], R.pa[k], boff, tc);
+            if (inner && !clear) add_square<SPLIT>(diag, R.oa[k], R.pa[k], boff, tc);
         }
 #pragma unroll
     for (int k = 0; k < SB; ++k)
@@ -405,7 +406,7 @@ __device__ inline void put_chunk(MfmaLds<SPLIT>& L, const ChunkRegs<SA, SB>& R, 
             for (int u = 0; u < 4; ++u)
                 if (j0 + 256u * u + (uint32_t)tid < r.na) {
                     lds_put<SPLIT, kLoA>(ta, ov[u], pv[u]);
-                    if (inner && !clear) add_square<SPLIT>(L.diag_ptr(), ov[u], pv[u], boff, tc);
+                    if (inner && !clear) add_square<SPLIT>(diag, ov[u], pv[u], boff, tc);
                 }
         }
     }
@@ -422,6 +423,65 @@ __device__ inline void put_chunk(MfmaLds<SPLIT>& L, const ChunkRegs<SA, SB>& R, 
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (j0 + 256u * u + (uint32_t)tid < r.nb) lds_put<SPLIT, kLoB>(tb, ov[u], pv[u]);
+        }
+    }
+}
+
+// One half of a chunk's K-loop on the matrix cores for a wave's 128 x 64
+// sub-tile (4 x 2 blocks of 32 x 32): K slots 16 half .. 16 half + 15.
+template <bool SPLIT>
+__device__ inline void mfma_step(const MfmaLds<SPLIT>& L, f32x16 (&acc)[4][2], int half, int wr, int brow0,
+                                 bool inner, int lane)
+{
+    if constexpr (SPLIT) {
+        // column operand rows: the column tile, or the row tile at offset boff
+        const unsigned short* bh_src = inner ? L.ahi : L.bhi;
+        const unsigned short* bl_src = inner ? L.alo : L.blo;
+        const int koff = 16 * half + 8 * (lane >> 5);
+        bf16x8 ah[4], al[4], bhv[2], blv[2];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const int row = wr * 128 + rb * 32 + (lane & 31);
+            ah[rb] = *reinterpret_cast<const bf16x8*>(&L.ahi[row * kBfStride + koff]);
+            al[rb] = *reinterpret_cast<const bf16x8*>(&L.alo[row * kBfStride + koff]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int col = brow0 + cb * 32 + (lane & 31);
+            bhv[cb] = *reinterpret_cast<const bf16x8*>(&bh_src[col * kBfStride + koff]);
+            blv[cb] = *reinterpret_cast<const bf16x8*>(&bl_src[col * kBfStride + koff]);
+        }
+        // product-outer order: consecutive MFMAs write different accumulators
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], bhv[cb], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], blv[cb], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rb], bhv[cb], acc[rb][cb], 0, 0, 0);
+    } else {
+        const float* bf_src = inner ? L.a : L.b;
+#pragma unroll 4
+        for (int kk = 16 * half; kk < 16 * half + 16; kk += 2) {
+            const int k = kk + (lane >> 5);
+            float av[4], bv[2];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) av[rb] = L.a[(wr * 128 + rb * 32 + (lane & 31)) * kF32Stride + k];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) bv[cb] = bf_src[(brow0 + cb * 32 + (lane & 31)) * kF32Stride + k];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
         }
     }
 }
@@ -485,16 +545,6 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
     ChunkRun r_prev{0, 0, 0, 0};
     int64_t c_prev = c0;
 
-    // column operand rows: the column tile, or the row tile at offset boff
-    const unsigned short* bh_src = nullptr;
-    const unsigned short* bl_src = nullptr;
-    const float* bf_src = nullptr;
-    if constexpr (SPLIT) {
-        bh_src = inner ? L.ahi : L.bhi;
-        bl_src = inner ? L.alo : L.blo;
-    } else {
-        bf_src = inner ? L.a : L.b;
-    }
     const int brow0 = (inner ? boff : 0) + wc * 64;
 
     for (int64_t c = c0; c < c1; ++c) {
@@ -502,10 +552,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
         // clear the previous chunk's slots, then scatter this chunk; a slot is
         // cleared and written by different waves, so a barrier orders the two
         if (c > c0) {
-            put_chunk<SPLIT, SA, SB>(L, R_prev, r_prev, true, inner, boff, g.tc, P, OA, OB, c_prev * cstride, tid);
+            put_chunk<SPLIT, SA, SB>(L, L.diag_ptr(), R_prev, r_prev, true, inner, boff, g.tc, P, OA, OB, c_prev * cstride, tid);
             __syncthreads();
         }
-        put_chunk<SPLIT, SA, SB>(L, R_cur, r_cur, false, inner, boff, g.tc, P, OA, OB, c * cstride, tid);
+        put_chunk<SPLIT, SA, SB>(L, L.diag_ptr(), R_cur, r_cur, false, inner, boff, g.tc, P, OA, OB, c * cstride, tid);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < SA; ++k) R_prev.oa[k] = R_cur.oa[k];
@@ -527,56 +577,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
         // workgroups of a CU reach it together, one runs ahead and the two
         // fall back into alternating scatter and matrix-core phases
         __builtin_amdgcn_s_setprio(1);
-        if constexpr (SPLIT) {
-#pragma unroll
-            for (int kk = 0; kk < kChunk; kk += 16) {
-                const int koff = kk + 8 * (lane >> 5);
-                bf16x8 ah[4], al[4], bhv[2], blv[2];
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
-                    const int row = wr * 128 + rb * 32 + (lane & 31);
-                    ah[rb] = *reinterpret_cast<const bf16x8*>(&L.ahi[row * kBfStride + koff]);
-                    al[rb] = *reinterpret_cast<const bf16x8*>(&L.alo[row * kBfStride + koff]);
-                }
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    const int col = brow0 + cb * 32 + (lane & 31);
-                    bhv[cb] = *reinterpret_cast<const bf16x8*>(&bh_src[col * kBfStride + koff]);
-                    blv[cb] = *reinterpret_cast<const bf16x8*>(&bl_src[col * kBfStride + koff]);
-                }
-                // product-outer order: consecutive MFMAs write different accumulators
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                    for (int cb = 0; cb < 2; ++cb)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], bhv[cb], acc[rb][cb], 0, 0, 0);
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                    for (int cb = 0; cb < 2; ++cb)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], blv[cb], acc[rb][cb], 0, 0, 0);
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                    for (int cb = 0; cb < 2; ++cb)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rb], bhv[cb], acc[rb][cb], 0, 0, 0);
-            }
-        } else {
-#pragma unroll 4
-            for (int kk = 0; kk < kChunk; kk += 2) {
-                const int k = kk + (lane >> 5);
-                float av[4], bv[2];
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb) av[rb] = L.a[(wr * 128 + rb * 32 + (lane & 31)) * kF32Stride + k];
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb) bv[cb] = bf_src[(brow0 + cb * 32 + (lane & 31)) * kF32Stride + k];
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                    for (int cb = 0; cb < 2; ++cb)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
-            }
-        }
+        mfma_step<SPLIT>(L, acc, 0, wr, brow0, inner, lane);
+        mfma_step<SPLIT>(L, acc, 1, wr, brow0, inner, lane);
         __builtin_amdgcn_s_setprio(0);
     }
 
@@ -820,7 +822,7 @@ static void dispatch_mfma(const GramPlan& g, int64_t grid, const uint32_t* P, co
 {
 #define PDS_GRAM_CASE(A, B)                                                                   \
     if (g.sa == A && g.sb == B) {                                                             \
-        launch_mfma_kernel<SPLIT, A, B>(g, grid, P, OA, OB, BS, m, n, part, pdiag, s);           \
+        launch_mfma_kernel<SPLIT, A, B>(g, grid, P, OA, OB, BS, m, n, part, pdiag, s);                    \
         return;                                                                               \
     }
     PDS_GRAM_CASE(1, 1)

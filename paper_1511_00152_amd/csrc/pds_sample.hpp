@@ -28,17 +28,19 @@ __device__ inline int wave_exclusive_scan(int v, int lane)
 __device__ inline void floyd_bitmap(uint64_t seed, uint64_t sample, int p, int m, uint32_t* bitmap, int stride,
                                     int col)
 {
-    // Fast path: draw t uses word t - (p - m) of the stream while no draw has
-    // been rejected; the Philox block after the current one is computed before
-    // the current block's set updates, so its arithmetic overlaps the LDS
-    // round trips.  At the first rejection (probability below range / 2^32 per
-    // draw) the lane continues on the exact sequential stream from the next
-    // word.
+    // Fast path: draw t uses word t - (p - m) of the stream while no word has
+    // a low product half below the range (the only words Lemire's method can
+    // reject, probability below range / 2^32 per draw).  Each draw is written
+    // without branches: the words of c and of t are read together, and both
+    // are written back (the same value twice when they are one word), so the
+    // Philox block after the current one, computed independently, fills the
+    // LDS round trips.  At the first such word the lane finishes on the exact
+    // sequential stream, starting with that word.
     uint64_t blk = 0;
     u64x4 cur = philox_block(0, sample, 0, 0, seed, 0);
     int t = p - m;
-    int64_t rejected_word = -1;
-    while (t < p) {
+    int64_t stop_word = -1;
+    while (t < p && stop_word < 0) {
         const u64x4 nxt = philox_block(blk + 1, sample, 0, 0, seed, 0);
         uint32_t w[8];
 #pragma unroll
@@ -48,52 +50,34 @@ __device__ inline void floyd_bitmap(uint64_t seed, uint64_t sample, int p, int m
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            if (t < p && rejected_word < 0) {
-                const uint32_t range = (uint32_t)(t + 1);
-                const uint64_t prod = (uint64_t)w[q] * range;
-                const uint32_t low = (uint32_t)prod;
-                if (low < range && low < (0u - range) % range) {
-                    rejected_word = (int64_t)(blk * 8 + q);
-                } else {
-                    const uint32_t c = (uint32_t)(prod >> 32);
-                    uint32_t* wc = &bitmap[(c >> 5) * stride + col];
-                    const uint32_t bit = 1u << (c & 31);
-                    const uint32_t old = *wc;
-                    if (old & bit)
-                        bitmap[((uint32_t)t >> 5) * stride + col] |= 1u << (t & 31);
-                    else
-                        *wc = old | bit;
-                    ++t;
-                }
-            }
+            const bool act = t < p && stop_word < 0;
+            const uint32_t range = (uint32_t)(t + 1);
+            const uint64_t prod = (uint64_t)w[q] * range;
+            const bool st = act && (uint32_t)prod < range;
+            stop_word = st ? (int64_t)(blk * 8 + q) : stop_word;
+            const bool go = act && !st;
+            const uint32_t c = go ? (uint32_t)(prod >> 32) : 0u;
+            const uint32_t tt = go ? (uint32_t)t : 0u;
+            uint32_t* wc = &bitmap[(c >> 5) * stride + col];
+            uint32_t* wt = &bitmap[(tt >> 5) * stride + col];
+            const uint32_t bc = go ? 1u << (c & 31) : 0u;
+            const uint32_t bt = 1u << (tt & 31);
+            const uint32_t oc = *wc, ot = *wt;
+            const bool hit = (oc & bc) != 0u;  // c already kept: keep t instead
+            const bool same = wc == wt;
+            const uint32_t nc = oc | (hit ? (same ? bt : 0u) : bc);
+            const uint32_t nt = same ? nc : (ot | (hit ? bt : 0u));
+            *wc = nc;
+            *wt = nt;
+            t += go ? 1 : 0;
         }
-        if (rejected_word >= 0) break;
         cur = nxt;
         ++blk;
     }
-    if (rejected_word >= 0) {
+    if (stop_word >= 0) {
         WordStream ws;
         ws.init(seed, sample);
-        ws.seek((uint64_t)rejected_word + 1);
-        // finish the rejected draw: Lemire redraws with the same range
-        {
-            const uint32_t range = (uint32_t)(t + 1);
-            const uint32_t thresh = (0u - range) % range;
-            uint64_t prod;
-            uint32_t low;
-            do {
-                prod = (uint64_t)ws.next() * range;
-                low = (uint32_t)prod;
-            } while (low < thresh);
-            const uint32_t c = (uint32_t)(prod >> 32);
-            uint32_t* wc = &bitmap[(c >> 5) * stride + col];
-            const uint32_t bit = 1u << (c & 31);
-            if (*wc & bit)
-                bitmap[((uint32_t)t >> 5) * stride + col] |= 1u << (t & 31);
-            else
-                *wc |= bit;
-            ++t;
-        }
+        ws.seek((uint64_t)stop_word);
         for (; t < p; ++t) {
             const uint32_t c = uniform_below(ws, (uint32_t)(t + 1));
             uint32_t* wc = &bitmap[(c >> 5) * stride + col];
