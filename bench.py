@@ -365,6 +365,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-form leg")
     ap.add_argument("--no-mixture", action="store_true", help="skip the mixture K-means leg")
+    ap.add_argument("--no-eigen", action="store_true", help="skip the eigen-solve timing (outside the step)")
     ap.add_argument("--mixture-only", action="store_true", help="run only the mixture K-means leg")
     args = ap.parse_args()
 
@@ -435,17 +436,18 @@ def main():
     if len(variants) > 1:
         out["split_over_f32"] = res["split"]["value"] / res["f32"]["value"] if "f32" in res and "split" in res else None
     # the eigen-solve (top 20 of C_n, FP64) is timed on its own, outside the step
-    C_head = res[head]["C"]
-    pds.top_eigenvalues(C_head, 20)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    ev_top = pds.top_eigenvalues(C_head, 20)
-    e1.record()
-    torch.cuda.synchronize()
-    out["eigen"] = {"ms": e0.elapsed_time(e1), "what": f"top 20 eigenvalues of the {p}x{p} FP64 estimate (device "
-                    "symmetric eigensolver), not part of the step", "largest": float(ev_top[0])}
+    if not args.no_eigen:
+        C_head = res[head]["C"]
+        pds.top_eigenvalues(C_head, 20)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ev_top = pds.top_eigenvalues(C_head, 20)
+        e1.record()
+        torch.cuda.synchronize()
+        out["eigen"] = {"ms": e0.elapsed_time(e1), "what": f"top 20 eigenvalues of the {p}x{p} FP64 estimate "
+                        "(device symmetric eigensolver), not part of the step", "largest": float(ev_top[0])}
     for v in res.values():
         v.pop("vals", None), v.pop("idx", None), v.pop("C", None)
     if not args.no_cpu_baseline:
