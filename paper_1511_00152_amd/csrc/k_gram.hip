@@ -174,12 +174,17 @@ __device__ inline uint32_t block_exclusive_scan256(uint32_t v, uint32_t* wsum)
     return base + incl - v;
 }
 
+constexpr int kPackStageBytes = 32768;  // chunk index rows staged in LDS up to this size
+
+// STAGE: the chunk's index rows (at most kPackStageBytes, 16-byte aligned
+// source) are copied to LDS with 16-byte loads first; otherwise read in place.
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
                                                    int64_t n, int m, int tr, int tc, int nbc, int rowbytes, int split,
                                                    uint32_t* __restrict__ P, uint16_t* __restrict__ OA,
                                                    uint16_t* __restrict__ OB, uint32_t* __restrict__ BS)
 {
-    extern __shared__ uint32_t pk_sh[];
+    extern __shared__ __align__(16) uint32_t pk_sh[];
     const int nb1 = nbc + 1;
     uint32_t* off = pk_sh;              // [32][nb1]: first entry of block b in the sample's row
     uint32_t* seg = pk_sh + 32 * nb1;   // [nbc][32]: chunk position of segment (b, s) minus off[s][b]
@@ -191,13 +196,25 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     const int eb = split ? 2 : 4;
     const int sh_c = __builtin_ctz((unsigned)tc);
 
+    const int tot = ns * m;
+    const float inv_m = 1.0f / (float)m;
+    const uint16_t* gidx = idx + i0 * (int64_t)m;
+    const uint16_t* cidx = gidx;
+    if constexpr (STAGE) {
+        uint16_t* sidx = reinterpret_cast<uint16_t*>(wsum + 4);  // 16-byte aligned (byte offset 256 nbc + 144)
+        const int nvec = (tot * 2) / 16;
+        const uint4* src = reinterpret_cast<const uint4*>(gidx);
+        uint4* dst = reinterpret_cast<uint4*>(sidx);
+        for (int v = tid; v < nvec; v += 256) dst[v] = src[v];
+        for (int f = nvec * 8 + tid; f < tot; f += 256) sidx[f] = gidx[f];
+        cidx = sidx;
+        __syncthreads();
+    }
+
     // block starts: block b begins at the first entry whose block number
     // reaches b, which the entry finds by comparing with its predecessor.  The
     // chunk's index rows are one contiguous range, walked flat (entry f of the
     // chunk is entry e = f - s m of sample s) so that loads stay in flight.
-    const uint16_t* cidx = idx + i0 * (int64_t)m;
-    const int tot = ns * m;
-    const float inv_m = 1.0f / (float)m;
     for (int s = ns; s < kChunk; ++s)
         for (int b = tid; b < nb1; b += 256) off[s * nb1 + b] = 0;
 #pragma unroll 4
@@ -838,6 +855,8 @@ static void dispatch_mfma(const GramPlan& g, int64_t grid, const uint32_t* P, co
 #undef PDS_GRAM_CASE
 }
 
+constexpr int kLdsMax = 160 * 1024;  // LDS of one workgroup on gfx950
+
 static size_t pack_lds_bytes(int nbc) { return ((size_t)kChunk * (nbc + 1) + (size_t)kChunk * nbc + 4) * 4; }
 
 hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n,
@@ -873,18 +892,29 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
         uint16_t* OB = reinterpret_cast<uint16_t*>(w + g.pk_bytes / 2 + g.pk_bytes / 4);
         uint32_t* BS = reinterpret_cast<uint32_t*>(w + g.pk_bytes);
         const bool split = (prec == 2);
-        const size_t lds = pack_lds_bytes(g.geom.nbc);
+        const bool stage = (size_t)kChunk * m * 2 <= (size_t)kPackStageBytes &&
+                           pack_lds_bytes(g.geom.nbc) + kPackStageBytes <= (size_t)kLdsMax &&
+                           (reinterpret_cast<uintptr_t>(idx) & 15) == 0;
+        const size_t lds = pack_lds_bytes(g.geom.nbc) + (stage ? (size_t)kPackStageBytes : 0);
         static bool pack_attr = false;
         if (!pack_attr) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack),
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<false>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)pack_lds_bytes(65536 / kTC));
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
             pack_attr = true;
         }
         {
             ProfScope ps_("gram_pack", s);
-            hipLaunchKernelGGL(k_gram_pack, dim3((unsigned)g.nchunks), dim3(256), lds, s,
-                               reinterpret_cast<const float*>(vals), idx, n, m, g.geom.tr, g.geom.tc, g.geom.nbc,
-                               split ? kBfStride * 2 : kF32Stride * 4, split ? 1 : 0, P, OA, OB, BS);
+            const int rowbytes = split ? kBfStride * 2 : kF32Stride * 4;
+            if (stage)
+                hipLaunchKernelGGL(k_gram_pack<true>, dim3((unsigned)g.nchunks), dim3(256), lds, s,
+                                   reinterpret_cast<const float*>(vals), idx, n, m, g.geom.tr, g.geom.tc, g.geom.nbc,
+                                   rowbytes, split ? 1 : 0, P, OA, OB, BS);
+            else
+                hipLaunchKernelGGL(k_gram_pack<false>, dim3((unsigned)g.nchunks), dim3(256), lds, s,
+                                   reinterpret_cast<const float*>(vals), idx, n, m, g.geom.tr, g.geom.tc, g.geom.nbc,
+                                   rowbytes, split ? 1 : 0, P, OA, OB, BS);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
