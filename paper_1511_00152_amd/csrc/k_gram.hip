@@ -344,6 +344,7 @@ __device__ inline void load_chunk(ChunkRegs<SA, SB>& R, const uint32_t* __restri
     }
 }
 
+// LO: byte distance from the tile's hi array to its lo array (split variant)
 template <bool SPLIT, int LO>
 __device__ inline void lds_put(unsigned char* base, uint32_t off, uint32_t pv)
 {
