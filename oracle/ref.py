@@ -24,9 +24,11 @@ Functions and the passages they follow (paper = arXiv 1511.00152):
   m = p special case, and against ``oracle_def``.
 * ``kmeans_step`` / ``unmix`` / ``kmeanspp`` -- Sec. VI and Alg. 1; pinned by
   the m = p reduction to Lloyd's algorithm (scikit-learn and a brute-force
-  loop), monotone objective, and ``oracle_def``.  The seeding itself follows
-  Arthur & Vassilvitskii with a reading of the sparse case: parity unpinned
-  beyond "it returns K distinct compressed samples".
+  loop), monotone objective, and ``oracle_def``.  The seeding follows Arthur &
+  Vassilvitskii with the sparsified distance of Sec. VI; it is pinned by its
+  sampling law (first center uniform, the next one with probability D^2 / sum
+  D^2), checked by Monte Carlo over seeds; which stream words it consumes is
+  a reading.
 * ``y_entry`` -- one entry of H D x from the definition (row of H times D x).
 * ``mean_estimate`` -- Thm. "sampleMean"; pinned by enumeration (unbiased).
 """

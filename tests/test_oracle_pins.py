@@ -12,6 +12,7 @@ import math
 import numpy as np
 import pytest
 import scipy.linalg
+import scipy.stats
 
 from oracle import bounds, oracle_def, ref
 
@@ -437,6 +438,39 @@ def test_kmeanspp_picks_distinct_samples():
         assert np.array_equal(C[k], z)
     C2, chosen2 = ref.kmeanspp(0, p, vals, idx, K)
     assert np.array_equal(chosen, chosen2)
+
+
+def test_kmeanspp_seeding_distribution():
+    """K-means++ (Arthur & Vassilvitskii; Alg. 1 init, on compressed samples):
+    the first center is uniform over the n samples; given it, the second is
+    sample j with probability D(j)^2 / sum D^2, D(j) the distance of sample j
+    to the first center over sample j's kept coordinates (Sec. VI's
+    sparsified distance).  Monte Carlo over seeds against those closed forms,
+    with D computed here by a direct loop; chi-square at the 1e-4 level."""
+    p, n, m, K = 16, 5, 6, 2
+    X = np.random.default_rng(21).standard_normal((n, p)) * np.arange(1, n + 1)[:, None]
+    vals, idx = ref.compress(X, 3, m)
+    zf = np.zeros((n, p))
+    for i in range(n):
+        zf[i, idx[i].astype(np.int64)] = vals[i]
+    D2 = np.array([[float(np.sum((vals[j] - zf[c][idx[j].astype(np.int64)]) ** 2)) for j in range(n)]
+                   for c in range(n)])
+    trials = 20000
+    first = np.zeros(n)
+    pair = np.zeros((n, n))
+    for seed in range(trials):
+        _, ch = ref.kmeanspp(seed, p, vals, idx, K)
+        first[ch[0]] += 1
+        pair[ch[0], ch[1]] += 1
+    chi2 = scipy.stats.chisquare(first, np.full(n, trials / n))
+    assert chi2.pvalue > 1e-4, chi2
+    for c in range(n):
+        prob = D2[c] / D2[c].sum()
+        assert pair[c, c] == 0
+        keep = prob > 0
+        exp = prob[keep] * pair[c].sum()
+        chi2 = scipy.stats.chisquare(pair[c][keep], exp)
+        assert chi2.pvalue > 1e-4, (c, chi2)
 
 
 # --------------------------------------------------------- end to end PCA --
