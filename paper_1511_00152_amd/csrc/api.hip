@@ -550,7 +550,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Workspace offsets (bytes) of the batch tables; sized for the smallest
 // candidate chunks so that re-tuning never grows the workspace.
 struct BatchOffsets {
-    size_t sets, gp, ap, cp, up, tp, ct, cmax, pobj, psum, pcnt, vt, it, dist, rlist, rcount, total;
+    size_t sets, gp, ap, cp, up, tp, ct, cmax, vmax, pobj, psum, pcnt, vt, it, dist, rlist, rcount, total;
 };
 
 int accum_kg(int K, int p)
@@ -591,10 +591,12 @@ BatchOffsets batch_offsets(const pds_batch_s& b)
     off += al256(ct * 4);
     o.cmax = off;
     off += al256(2 * ns * 4);
+    o.vmax = off;
+    off += al256(ns * 4);
     o.pobj = off;
     off += al256((pobj > 0 ? pobj : 1) * 8);
     o.psum = off;
-    off += al256((part > 0 ? part : 1) * 4);
+    off += al256((part > 0 ? part : 1) * 8);
     o.pcnt = off;
     off += al256((part > 0 ? part : 1) * 4);
     o.vt = off;
@@ -689,7 +691,8 @@ void batch_build(const pds_batch_s& b, const pds::BatchTuning& tu, unsigned char
     t.ct = reinterpret_cast<float*>(ws + o.ct);
     t.cmax = reinterpret_cast<uint32_t*>(ws + o.cmax);
     t.pobj = reinterpret_cast<double*>(ws + o.pobj);
-    t.psum = reinterpret_cast<float*>(ws + o.psum);
+    t.psum = reinterpret_cast<int64_t*>(ws + o.psum);
+    t.vmax = reinterpret_cast<uint32_t*>(ws + o.vmax);
     t.pcnt = reinterpret_cast<uint32_t*>(ws + o.pcnt);
     t.tprefix = reinterpret_cast<const int64_t*>(ws + o.tp);
     t.ntiles = tl;

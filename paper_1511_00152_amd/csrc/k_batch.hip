@@ -137,8 +137,10 @@ __device__ inline int64_t tile_base(const BatchSet& S, int64_t t)
 
 __global__ __launch_bounds__(256) void k_batch_tile(const BatchSet* __restrict__ sets, int nsets,
                                                     const int64_t* __restrict__ tprefix, int64_t ntiles,
-                                                    float* __restrict__ vt, uint16_t* __restrict__ it)
+                                                    float* __restrict__ vt, uint16_t* __restrict__ it,
+                                                    uint32_t* __restrict__ vmax)
 {
+    __shared__ uint32_t red[256];
     for (int64_t g = blockIdx.x; g < ntiles; g += gridDim.x) {
         const int d = owner(tprefix, nsets, g);
         const BatchSet& S = sets[d];
@@ -151,26 +153,52 @@ __global__ __launch_bounds__(256) void k_batch_tile(const BatchSet* __restrict__
         float* dv = vt + tile_base(S, t);
         uint16_t* di = it + tile_base(S, t);
         const int64_t tot = (int64_t)mp * 64;
+        uint32_t mx = 0u;  // largest |value| (float bits compare as integers for non-negative floats)
         for (int64_t e = threadIdx.x; e < tot; e += 256) {
             const int u = (int)(e & 7);
             const int r = (int)((e >> 3) & 63);
             const int a = (int)(e >> 9) * 8 + u;
             const bool ok = r0 + r < S.n && a < m;
-            dv[e] = ok ? src_v[(int64_t)r * m + a] : 0.0f;
+            const float v = ok ? src_v[(int64_t)r * m + a] : 0.0f;
+            dv[e] = v;
             di[e] = ok ? src_i[(int64_t)r * m + a] : (uint16_t)0;
+            mx = max(mx, __float_as_uint(fabsf(v)));
         }
+        red[threadIdx.x] = mx;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) atomicMax(&vmax[d], red[0]);
+        __syncthreads();
     }
+}
+
+// Fixed-point scale of a set's sums: a chunk sums at most cchunk values of
+// magnitude below 2^ev (frexp of the set's largest |value|), so with F =
+// 62 - ev - ceil(log2 cchunk) every chunk sum times 2^F stays below 2^62 and
+// each value is rounded once, to 2^-F absolute (the sums themselves are then
+// exact integers, independent of the order of the additions).
+__device__ inline int batch_fx_exp(uint32_t vmax_bits, int64_t cchunk)
+{
+    int ev = 0;
+    (void)frexpf(__uint_as_float(vmax_bits), &ev);
+    const int cb = cchunk > 1 ? 64 - __clzll((unsigned long long)(cchunk - 1)) : 0;
+    return 62 - ev - cb;
 }
 
 // prep: one workgroup per set; FP32 transposed centers, largest |center|, and
 // (odd round counts) the second center buffer
 __global__ __launch_bounds__(256) void k_batch_prep(const BatchSet* __restrict__ sets, int nsets,
                                                     float* __restrict__ ct, uint32_t* __restrict__ cmax0,
-                                                    uint32_t* __restrict__ rcount, int copy_to_b)
+                                                    uint32_t* __restrict__ rcount, uint32_t* __restrict__ vmax,
+                                                    int copy_to_b)
 {
     __shared__ uint32_t red[256];
     const int d = blockIdx.x;
     if (d == 0 && threadIdx.x == 0) *rcount = 0u;
+    if (threadIdx.x == 0) vmax[d] = 0u;  // the tiling that follows takes the set's largest |value|
     const BatchSet& S = sets[d];
     const int64_t KP = (int64_t)S.K * S.p;
     float* c = ct + S.ct_off;
@@ -389,13 +417,16 @@ __global__ __launch_bounds__(256) void k_batch_recheck(const BatchSet* __restric
 
 __global__ __launch_bounds__(kBcThreads) void k_batch_accum(const BatchSet* __restrict__ sets, int nsets,
                                                             const int64_t* __restrict__ cprefix, int64_t nitems,
-                                                            float* __restrict__ psum, uint32_t* __restrict__ pcnt,
+                                                            int64_t* __restrict__ psum, uint32_t* __restrict__ pcnt,
+                                                            const uint32_t* __restrict__ vmax,
                                                             const double* __restrict__ dist,
                                                             double* __restrict__ pobj)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kBcThreads / 64];
-    float* sums = reinterpret_cast<float*>(smem);
+    // 64-bit fixed-point sums: integer LDS atomics run at full rate, the FP32
+    // ones do not
+    unsigned long long* sums = reinterpret_cast<unsigned long long*>(smem);
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int d = owner(cprefix, nsets, it);
         const BatchSet& S = sets[d];
@@ -407,9 +438,10 @@ __global__ __launch_bounds__(kBcThreads) void k_batch_accum(const BatchSet* __re
         const int p = S.p, m = S.m;
         const int ent = kg * p;
         uint32_t* cnts = reinterpret_cast<uint32_t*>(sums + ent);
+        const int fx = batch_fx_exp(vmax[d], S.cchunk);
         __syncthreads();  // the previous item's LDS reads are done
         for (int e = threadIdx.x; e < ent; e += kBcThreads) {
-            sums[e] = 0.0f;
+            sums[e] = 0ull;
             cnts[e] = 0u;
         }
         __syncthreads();
@@ -451,7 +483,7 @@ __global__ __launch_bounds__(kBcThreads) void k_batch_accum(const BatchSet* __re
                     const int64_t i = base + pick;
                     const float* v = S.vals + i * (int64_t)m;
                     const uint16_t* ix = S.idx + i * (int64_t)m;
-                    float* sk = sums + (cb - k0) * p;
+                    unsigned long long* sk = sums + (cb - k0) * p;
                     uint32_t* ck = cnts + (cb - k0) * p;
                     // four entries per lane per step: the loads are issued before the atomics
                     for (int a0 = sl; a0 < m; a0 += 64) {
@@ -466,7 +498,8 @@ __global__ __launch_bounds__(kBcThreads) void k_batch_accum(const BatchSet* __re
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             if (a0 + 16 * u < m) {
-                                atomicAdd(&sk[l[u]], x[u]);
+                                const long long q = __double2ll_rn(ldexp((double)x[u], fx));
+                                atomicAdd(&sk[l[u]], (unsigned long long)q);
                                 atomicAdd(&ck[l[u]], 1u);
                             }
                         }
@@ -476,10 +509,10 @@ __global__ __launch_bounds__(kBcThreads) void k_batch_accum(const BatchSet* __re
         }
         __syncthreads();
         const int64_t KP = (int64_t)S.K * p;
-        float* ps = psum + S.part_off + chunk * KP + (int64_t)k0 * p;
+        int64_t* ps = psum + S.part_off + chunk * KP + (int64_t)k0 * p;
         uint32_t* pc = pcnt + S.part_off + chunk * KP + (int64_t)k0 * p;
         for (int e = threadIdx.x; e < ent; e += kBcThreads) {
-            ps[e] = sums[e];
+            ps[e] = (int64_t)sums[e];
             pc[e] = cnts[e];
         }
     }
@@ -487,7 +520,8 @@ __global__ __launch_bounds__(kBcThreads) void k_batch_accum(const BatchSet* __re
 
 __global__ __launch_bounds__(256) void k_batch_update(const BatchSet* __restrict__ sets, int nsets,
                                                       const int64_t* __restrict__ uprefix, int64_t nitems,
-                                                      const float* __restrict__ psum, const uint32_t* __restrict__ pcnt,
+                                                      const int64_t* __restrict__ psum, const uint32_t* __restrict__ pcnt,
+                                                      const uint32_t* __restrict__ vmax,
                                                       float* __restrict__ ct, uint32_t* __restrict__ cmax_next,
                                                       const double* __restrict__ pobj, uint32_t* __restrict__ rcount,
                                                       int dir, int round)
@@ -511,6 +545,7 @@ __global__ __launch_bounds__(256) void k_batch_update(const BatchSet* __restrict
             sum += (double)psum[S.part_off + c * KP + e];
             cnt += pcnt[S.part_off + c * KP + e];
         }
+        sum = ldexp(sum, -batch_fx_exp(vmax[d], S.cchunk));
         const double* cin = round_in(S, dir);
         const double nv = (cnt > 0) ? sum / (double)cnt : cin[e];
         round_out(S, dir)[e] = nv;
@@ -610,14 +645,15 @@ hipError_t launch_batch_tile(const BatchSet* sets, int nsets, const BatchTables&
     if (t.ntiles <= 0) return hipSuccess;
     if (grid > t.ntiles) grid = t.ntiles;
     hipLaunchKernelGGL(k_batch_tile, dim3((unsigned)grid), dim3(256), 0, s, sets, nsets, t.tprefix, t.ntiles, t.vt,
-                       t.it);
+                       t.it, t.vmax);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_round_prep(const BatchSet* sets, int nsets, const BatchTables& t, int copy_to_b,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_prep, dim3(nsets), dim3(256), 0, s, sets, nsets, t.ct, t.cmax, t.rcount, copy_to_b);
+    hipLaunchKernelGGL(k_batch_prep, dim3(nsets), dim3(256), 0, s, sets, nsets, t.ct, t.cmax, t.rcount, t.vmax,
+                       copy_to_b);
     return hipGetLastError();
 }
 
@@ -638,14 +674,14 @@ hipError_t launch_batch_round(const BatchSet* sets, int nsets, const BatchTables
     if (t.ncitems > 0) {
         int64_t grid = t.ncitems < tu.accum_grid ? t.ncitems : tu.accum_grid;
         hipLaunchKernelGGL(k_batch_accum, dim3((unsigned)grid), dim3(kBcThreads), (size_t)kBatchAccumLds, s, sets,
-                           nsets, t.cprefix, t.ncitems, t.psum, t.pcnt, t.dist, t.pobj);
+                           nsets, t.cprefix, t.ncitems, t.psum, t.pcnt, t.vmax, t.dist, t.pobj);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (t.nuitems > 0) {
         int64_t grid = t.nuitems < tu.update_grid ? t.nuitems : tu.update_grid;
         hipLaunchKernelGGL(k_batch_update, dim3((unsigned)grid), dim3(256), 0, s, sets, nsets, t.uprefix, t.nuitems,
-                           t.psum, t.pcnt, t.ct, cm_next, t.pobj, t.rcount, dir, round);
+                           t.psum, t.pcnt, t.vmax, t.ct, cm_next, t.pobj, t.rcount, dir, round);
     }
     return hipGetLastError();
 }

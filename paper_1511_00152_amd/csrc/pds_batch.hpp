@@ -10,7 +10,7 @@ namespace pds {
 
 constexpr int kBatchAssignSamples = 512;           // samples per assignment item (one per thread)
 constexpr int kBatchAccumLds = 65536;               // LDS of one accumulation workgroup
-constexpr int kBatchAccumEntries = kBatchAccumLds / 8;  // FP32 sum + u32 count per entry
+constexpr int kBatchAccumEntries = kBatchAccumLds / 12;  // 64-bit fixed-point sum + u32 count per entry
 
 // One data set as the kernels see it (device copy).
 struct BatchSet {
@@ -45,8 +45,9 @@ struct BatchTables {
     float* ct;
     uint32_t* cmax;  // 2 x nsets (float bits)
     double* pobj;
-    float* psum;
+    int64_t* psum;           // fixed-point partial sums (scale 2^F of the set, see batch_fx_exp)
     uint32_t* pcnt;
+    uint32_t* vmax;          // nsets: largest |compressed value| of the set (float bits), per K-means call
     const int64_t* tprefix;  // tiles (nsets + 1)
     int64_t ntiles;
     float* vt;               // compressed values tiled by 64 samples: [tile][entry][lane]
