@@ -245,10 +245,54 @@ __device__ inline float dpp_row_total(float v)
 // term passes through at most m additions), so the near-tie test and the FP64
 // recheck give the FP64 argmin as before.  Centers are transposed in LDS with
 // rows padded to KP4 = ceil4(K) floats and read as float4.
+// Fixed-point scale of a workgroup's sums: at most per_wg values of magnitude
+// below 2^ev (frexp of the largest |value|) go into one sum, so with F = 62 -
+// ev - ceil(log2 per_wg) every sum times 2^F stays below 2^62; each value is
+// rounded once, to 2^-F absolute, and the sums are exact integers, the same in
+// any order of addition.
+__device__ inline int km_fx_exp(uint32_t vmax_bits, int64_t per_wg)
+{
+    int ev = 0;
+    (void)frexpf(__uint_as_float(vmax_bits), &ev);
+    const int cb = per_wg > 1 ? 64 - __clzll((unsigned long long)(per_wg - 1)) : 0;
+    return 62 - ev - cb;
+}
+
+// largest |value| of the compressed data (float bits; the target is cleared by
+// the prep kernel)
+__global__ __launch_bounds__(256) void k_kmeans_absmax(const float* __restrict__ vals, int64_t count,
+                                                       uint32_t* __restrict__ vmax)
+{
+    __shared__ uint32_t red[256];
+    uint32_t mx = 0u;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // 16-byte loads over the aligned part (the sign bit is masked off the
+    // float bits, which then order like the magnitudes)
+    const int64_t head = (int64_t)((16 - (reinterpret_cast<uintptr_t>(vals) & 15)) & 15) / 4;
+    const int64_t h = head < count ? head : count;
+    const int64_t nv = (count - h) / 4;
+    const uint4* v4 = reinterpret_cast<const uint4*>(vals + h);
+    for (int64_t e = t0; e < nv; e += stride) {
+        const uint4 q = v4[e];
+        mx = max(mx, max(max(q.x & 0x7fffffffu, q.y & 0x7fffffffu), max(q.z & 0x7fffffffu, q.w & 0x7fffffffu)));
+    }
+    for (int64_t e = t0; e < h; e += stride) mx = max(mx, __float_as_uint(fabsf(vals[e])));
+    for (int64_t e = h + nv * 4 + t0; e < count; e += stride) mx = max(mx, __float_as_uint(fabsf(vals[e])));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(vmax, red[0]);
+}
+
 __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     const float* __restrict__ vals, const uint16_t* __restrict__ idx, int64_t n, int m, int p, int K,
-    const double* __restrict__ cin, int64_t per_wg, int32_t* __restrict__ assign, float* __restrict__ psum,
-    uint32_t* __restrict__ pcnt, double* __restrict__ dist, int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
+    const double* __restrict__ cin, int64_t per_wg, int32_t* __restrict__ assign, int64_t* __restrict__ psum,
+    uint32_t* __restrict__ pcnt, const uint32_t* __restrict__ vmax, double* __restrict__ dist,
+    int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
 {
     constexpr int W = 16;
     constexpr int G = kKmLdsThreads / W;  // groups per workgroup
@@ -258,17 +302,19 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     const int KP4 = (K + 3) & ~3;
     const int nq4 = KP4 >> 2;
     const int64_t KP = (int64_t)K * p;
+    // centers transposed (rows padded to 4), 64-bit fixed-point sums and
+    // 16-bit counts two to a word: integer LDS atomics run at full rate, the
+    // FP32 ones do not; at most 65535 samples per workgroup
     float* cT = reinterpret_cast<float*>(smem);
-    float* sums = cT + (int64_t)KP4 * p;
-    uint32_t* cnts = reinterpret_cast<uint32_t*>(sums + KP);
+    unsigned long long* sums = reinterpret_cast<unsigned long long*>(cT + (int64_t)KP4 * p);
+    uint32_t* cnt2 = reinterpret_cast<uint32_t*>(sums + KP);
+    const int fx = km_fx_exp(*vmax, per_wg);
     for (int64_t e = tid; e < (int64_t)KP4 * p; e += kKmLdsThreads) {
         const int64_t l = e / KP4, k = e - l * KP4;
         cT[e] = (k < K) ? (float)cin[k * p + l] : 0.0f;
     }
-    for (int64_t e = tid; e < KP; e += kKmLdsThreads) {
-        sums[e] = 0.0f;
-        cnts[e] = 0u;
-    }
+    for (int64_t e = tid; e < KP; e += kKmLdsThreads) sums[e] = 0ull;
+    for (int64_t e = tid; e < (KP + 1) / 2; e += kKmLdsThreads) cnt2[e] = 0u;
     __syncthreads();
     float cmax = 0.0f;
     for (int64_t e = tid; e < (int64_t)KP4 * p; e += kKmLdsThreads) cmax = fmaxf(cmax, fabsf(cT[e]));
@@ -352,20 +398,19 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
             assign[i] = bestk;
             dist[i] = (double)best;
         }
-        float* sk = sums + (int64_t)bestk * p;
-        uint32_t* ck = cnts + (int64_t)bestk * p;
+        const int64_t kb = (int64_t)bestk * p;
         for (int a = sl; a < m; a += W) {
-            const int l = ix[a];
-            atomicAdd(&sk[l], v[a]);
-            atomicAdd(&ck[l], 1u);
+            const int64_t e = kb + ix[a];
+            atomicAdd(&sums[e], (unsigned long long)__double2ll_rn(ldexp((double)v[a], fx)));
+            atomicAdd(&cnt2[e >> 1], 1u << (16 * (int)(e & 1)));
         }
     }
     __syncthreads();
-    float* ps = psum + (int64_t)blockIdx.x * KP;
+    int64_t* ps = psum + (int64_t)blockIdx.x * KP;
     uint32_t* pc = pcnt + (int64_t)blockIdx.x * KP;
     for (int64_t e = tid; e < KP; e += kKmLdsThreads) {
-        ps[e] = sums[e];
-        pc[e] = cnts[e];
+        ps[e] = (int64_t)sums[e];
+        pc[e] = (cnt2[e >> 1] >> (16 * (int)(e & 1))) & 0xffffu;
     }
 }
 
@@ -445,7 +490,8 @@ __global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const S* __restri
                                                                const double* __restrict__ cin,
                                                                double* __restrict__ cout,
                                                                const double* __restrict__ pobj, int nobj,
-                                                               double* __restrict__ objective)
+                                                               double* __restrict__ objective,
+                                                               const uint32_t* __restrict__ vmax, int64_t per_wg)
 {
     __shared__ double rs[kUpdThreads / 64][64];
     __shared__ uint64_t rc[kUpdThreads / 64][64];
@@ -474,6 +520,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const S* __restri
             t += rs[w][lane];
             c += rc[w][lane];
         }
+        if (vmax) t = ldexp(t, -km_fx_exp(*vmax, per_wg));  // fixed-point partials
         t += gsum_r[g];
         c += gcnt_r[g];
         cout[g] = (c > 0) ? t / (double)c : cin[g];
@@ -486,11 +533,15 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_kmeans_prep(const double* __restrict__ cin, int K, int p, int global,
                                                      T* __restrict__ cT, double* __restrict__ gsum,
                                                      uint32_t* __restrict__ gcnt, double* __restrict__ gsum_r,
-                                                     uint32_t* __restrict__ gcnt_r, uint32_t* __restrict__ rcount)
+                                                     uint32_t* __restrict__ gcnt_r, uint32_t* __restrict__ rcount,
+                                                     uint32_t* __restrict__ vmax)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t KP = (int64_t)K * p;
-    if (g == 0) *rcount = 0u;
+    if (g == 0) {
+        *rcount = 0u;
+        *vmax = 0u;
+    }
     if (g >= KP) return;
     gsum_r[g] = 0.0;
     gcnt_r[g] = 0u;
@@ -512,7 +563,7 @@ struct KmPlan {
     int64_t per_wg;
     size_t lds;
     size_t psum_bytes, pcnt_bytes, pobj_bytes, ct_bytes, gsum_bytes, gcnt_bytes;
-    size_t dist_bytes, rlist_bytes, rcount_bytes, gsumr_bytes, gcntr_bytes;
+    size_t dist_bytes, rlist_bytes, rcount_bytes, gsumr_bytes, gcntr_bytes, vmax_bytes;
 };
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -526,8 +577,9 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
     const size_t lds = ((KP * te + 15) & ~(size_t)15) + ((KP * se + 15) & ~(size_t)15) + KP * 4;
     k.global = lds > kKmLdsMax;
     k.lds = k.global ? 0 : lds;
-    // FP32, K <= 32, centers (rows padded to 4) + sums + counts in LDS
-    const size_t lds_coop = (size_t)((K + 3) & ~3) * p * 4 + (size_t)KP * 8;
+    // FP32, K <= 32: centers (rows padded to 4), 64-bit fixed-point sums and
+    // 16-bit counts in LDS
+    const size_t lds_coop = (size_t)((K + 3) & ~3) * p * 4 + (size_t)KP * 8 + (size_t)((KP + 1) / 2) * 4;
     k.coop = 0;
     if (prec != 0 && K <= 32 && lds_coop <= kKmLdsMax) {
         k.coop = 16;
@@ -540,9 +592,10 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
     if (!k.global && lds * 2 <= kKmLdsMax) cap = (int64_t)dev.cus * 2;
     if (want > cap) want = cap;
     if (want < 1) want = 1;
+    if (k.coop && (n + want - 1) / want > 65535) want = (n + 65534) / 65535;  // 16-bit counts
     k.nwg = (int)want;
     k.per_wg = (n + k.nwg - 1) / k.nwg;
-    k.psum_bytes = k.global ? 0 : al256((size_t)k.nwg * KP * se);
+    k.psum_bytes = k.global ? 0 : al256((size_t)k.nwg * KP * (k.coop ? 8 : se));
     k.pcnt_bytes = k.global ? 0 : al256((size_t)k.nwg * KP * 4);
     k.pobj_bytes = al256((size_t)k.nwg * 8);
     k.ct_bytes = k.global ? al256(KP * te) : 0;
@@ -554,6 +607,7 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
     k.rcount_bytes = 256;
     k.gsumr_bytes = al256(KP * 8);
     k.gcntr_bytes = al256(KP * 4);
+    k.vmax_bytes = 256;
     return k;
 }
 
@@ -562,7 +616,7 @@ size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceIn
     (void)m;
     KmPlan k = km_plan(prec, p, n, K, dev);
     return k.psum_bytes + k.pcnt_bytes + k.pobj_bytes + k.ct_bytes + k.gsum_bytes + k.gcnt_bytes + k.dist_bytes +
-           k.rlist_bytes + k.rcount_bytes + k.gsumr_bytes + k.gcntr_bytes;
+           k.rlist_bytes + k.rcount_bytes + k.gsumr_bytes + k.gcntr_bytes + k.vmax_bytes;
 }
 
 template <typename T>
@@ -593,11 +647,13 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
     double* gsum_r = reinterpret_cast<double*>(w);
     w += k.gsumr_bytes;
     uint32_t* gcnt_r = reinterpret_cast<uint32_t*>(w);
+    w += k.gcntr_bytes;
+    uint32_t* vmax = reinterpret_cast<uint32_t*>(w);
     const int64_t KP = (int64_t)K * p;
     {
         ProfScope ps_("kmeans_prep", s);
         hipLaunchKernelGGL(k_kmeans_prep<T>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, cin, K, p,
-                           k.global ? 1 : 0, cT, gsum, gcnt, gsum_r, gcnt_r, rcount);
+                           k.global ? 1 : 0, cT, gsum, gcnt, gsum_r, gcnt_r, rcount, vmax);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -616,9 +672,18 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
                     coop_attr = true;
                 }
                 {
+                    ProfScope ps_("kmeans_absmax", s);
+                    const int64_t cnt = n * (int64_t)m;
+                    int64_t blocks = (cnt + 255) / 256;
+                    if (blocks > (int64_t)dev.cus * 16) blocks = (int64_t)dev.cus * 16;
+                    hipLaunchKernelGGL(k_kmeans_absmax, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s,
+                                       reinterpret_cast<const float*>(vals), cnt, vmax);
+                }
+                {
                     ProfScope ps_("kmeans_assign", s);
                     hipLaunchKernelGGL(k_kmeans_assign_coop, dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s, vals, idx,
-                                       n, m, p, K, cin, k.per_wg, assign, psum, pcnt, dist, rlist, rcount);
+                                       n, m, p, K, cin, k.per_wg, assign, reinterpret_cast<int64_t*>(psum), pcnt,
+                                       vmax, dist, rlist, rcount);
                 }
                 goto assigned;
             }
@@ -656,10 +721,16 @@ assigned:
         const unsigned ublocks = (unsigned)((KP + 63) / 64);
         if (k.global)
             hipLaunchKernelGGL(k_kmeans_update<double>, dim3(ublocks), dim3(kUpdThreads), 0, s, gsum, gcnt, 1, KP,
-                               gsum_r, gcnt_r, cin, cout, pobj, k.nwg, objective);
+                               gsum_r, gcnt_r, cin, cout, pobj, k.nwg, objective, (const uint32_t*)nullptr,
+                               (int64_t)0);
+        else if (sizeof(T) == 4 && k.coop)
+            hipLaunchKernelGGL(k_kmeans_update<int64_t>, dim3(ublocks), dim3(kUpdThreads), 0, s,
+                               reinterpret_cast<const int64_t*>(psum), pcnt, k.nwg, KP, gsum_r, gcnt_r, cin, cout, pobj,
+                               k.nwg, objective, (const uint32_t*)vmax, k.per_wg);
         else
             hipLaunchKernelGGL(k_kmeans_update<S>, dim3(ublocks), dim3(kUpdThreads), 0, s, psum, pcnt, k.nwg, KP,
-                               gsum_r, gcnt_r, cin, cout, pobj, k.nwg, objective);
+                               gsum_r, gcnt_r, cin, cout, pobj, k.nwg, objective, (const uint32_t*)nullptr,
+                               (int64_t)0);
     }
     return hipGetLastError();
 }
