@@ -19,7 +19,11 @@
 
 namespace pds {
 
-constexpr int kSampleLdsBytes = 34816;  // 64 samples x 128 words x stride 65 at p = 4096
+// Bitmap budget per 64-lane workgroup: 32 samples (stride 33) at p = 4096, so
+// that nine workgroups share a CU and the cooperative emission's latencies are
+// covered by the other waves (64 samples per wave, four waves per CU, leave
+// them exposed: 2.6 against 1.9 ms at n = 2^20, p = 4096, m = 410).
+constexpr int kSampleLdsBytes = 16896;
 
 __global__ __launch_bounds__(64) void k_sample_indices(uint64_t seed, int p, int m, int64_t n, uint64_t i0,
                                                        int spw, int words, uint16_t* __restrict__ idx)

@@ -26,8 +26,14 @@ struct u64x4 {
 __host__ __device__ inline void mul_hi_lo(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    lo = a * b;
-    hi = __umul64hi(a, b);
+    // four 32 x 32 -> 64 partial products with the carries folded into the
+    // multiply-adds (none of the sums can exceed 2^64 - 1)
+    const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32), bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+    const uint64_t p0 = (uint64_t)al * bl;
+    const uint64_t p1 = (uint64_t)al * bh + (p0 >> 32);
+    const uint64_t p2 = (uint64_t)ah * bl + (uint32_t)p1;
+    hi = (uint64_t)ah * bh + (p1 >> 32) + (p2 >> 32);
+    lo = (p2 << 32) | (uint32_t)p0;
 #else
     unsigned __int128 p = (unsigned __int128)a * b;
     lo = (uint64_t)p;

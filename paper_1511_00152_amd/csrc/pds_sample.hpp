@@ -13,15 +13,20 @@
 
 namespace pds {
 
-__device__ inline int wave_exclusive_scan(int v, int lane)
+// Exclusive prefix sum over the 64 lanes of a wave, on data-parallel
+// primitives (no LDS round trips): shifts by 1, 2, 4, 8 within each row of
+// 16 lanes, then each row's total broadcast to the rows above it.  Lanes whose
+// source lies outside the pattern add zero.  All 64 lanes must be active.
+__device__ inline int wave_exclusive_scan(int v)
 {
-    int incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int t = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += t;
-    }
-    return incl - v;
+    int x = v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return x - v;
 }
 
 // Kept set of one sample into a zeroed bitmap column (one lane's work).
@@ -93,7 +98,7 @@ __device__ inline void floyd_bitmap(uint64_t seed, uint64_t sample, int p, int m
 // Ascending emission of bitmap column col by the whole wave: each lane takes
 // a contiguous run of bitmap words, a wave prefix sum of their popcounts gives
 // its first output position, and emit(pos, coord) is called for each kept
-// coordinate (lanes write side by side).
+// coordinate (lanes write side by side).  Called by all 64 lanes.
 template <class F>
 __device__ inline void emit_sorted(const uint32_t* bitmap, int stride, int col, int words, int lane, F emit)
 {
@@ -102,7 +107,7 @@ __device__ inline void emit_sorted(const uint32_t* bitmap, int stride, int col, 
     int cnt = 0;
     for (int q = 0; q < wpl; ++q)
         if (w0 + q < words) cnt += __popc(bitmap[(w0 + q) * stride + col]);
-    int pos = wave_exclusive_scan(cnt, lane);
+    int pos = wave_exclusive_scan(cnt);
     for (int q = 0; q < wpl; ++q) {
         if (w0 + q >= words) break;
         uint32_t bits = bitmap[(w0 + q) * stride + col];
