@@ -128,7 +128,7 @@ pds_status pds_compress(pds_plan plan, const void* X, int64_t n, int64_t ldx, ui
  *          the original domain; eigenvectors map back by (H D)^T).
  * n may be 0 (finalize only).  ws: device, >= pds_workspace_size(COVARIANCE, n);
  * for FP32 and split plans it holds the batch's kept entries re-packed by
- * 32-sample chunk and 128-coordinate block (8 bytes per kept entry) and FP32
+ * 32-sample chunk and 128-coordinate block (6 bytes per kept entry) and FP32
  * partial tiles per sample range, so it grows linearly with n: large inputs
  * can be streamed in batches into the same acc.
  * Errors: PDS_E_M (m < 2: the rescaling divides by m - 1), PDS_E_ARG (null

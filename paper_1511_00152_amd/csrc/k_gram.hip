@@ -143,8 +143,9 @@ __device__ inline void decode_rect_tile(int t, const TileGeom& g, int& a, int& b
 // its n_c m entries are rewritten, in the chunk's own 32 m slots, ordered by
 // column block (tc coordinates), then sample, then coordinate:
 //   P[c][q]  the stored value: bf16 hi | bf16 lo << 16 (split), or the FP32 bits
-//   OA[c][q] LDS byte offset of the entry in a row tile, OB[c][q] in a column
-//            tile: coordinate-in-tile * row bytes + slot * element bytes
+//   OA[c][q] LDS byte offset of the entry in a row tile: coordinate-in-tile
+//            * row bytes + slot * element bytes.  Its offset in a column tile
+//            (tc rows) is OA mod (tc * row bytes), taken by the tile kernel.
 //   BS[c][b] first q of block b, b = 0 .. nbc (BS[c][nbc] = n_c m)
 // A tile's entries of one chunk are then one contiguous run: the tile kernel
 // reads them coalesced, balanced over its threads, and scatters each with one
@@ -182,7 +183,7 @@ template <bool STAGE>
 __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
                                                    int64_t n, int m, int tr, int tc, int nbc, int rowbytes, int split,
                                                    uint32_t* __restrict__ P, uint16_t* __restrict__ OA,
-                                                   uint16_t* __restrict__ OB, uint32_t* __restrict__ BS)
+                                                   uint32_t* __restrict__ BS)
 {
     extern __shared__ __align__(16) uint32_t pk_sh[];
     const int nb1 = nbc + 1;
@@ -260,7 +261,6 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
 
     uint32_t* Pc = P + c * (int64_t)kChunk * m;
     uint16_t* OAc = OA + c * (int64_t)kChunk * m;
-    uint16_t* OBc = OB + c * (int64_t)kChunk * m;
     const float* cval = vals + i0 * (int64_t)m;
 #pragma unroll 4
     for (int f = tid; f < tot; f += 256) {
@@ -272,7 +272,6 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
         const float v = cval[f];
         Pc[q] = split ? split_bits(v) : __float_as_uint(v);
         OAc[q] = (uint16_t)((j & (uint32_t)(tr - 1)) * rowbytes + s * eb);
-        OBc[q] = (uint16_t)((j & (uint32_t)(tc - 1)) * rowbytes + s * eb);
     }
 }
 
@@ -310,6 +309,15 @@ __device__ inline ChunkRun chunk_run_unpack(uint32_t v, bool live)
     return r;
 }
 
+// An entry's column-tile offset from its row-tile offset: OA mod tcb, where
+// tcb (tc rows) is a multiple of a row and OA < 2 tcb (unsigned wrap-around
+// makes the difference the larger operand when OA < tcb).
+__device__ inline uint32_t col_offset(uint32_t oa, uint32_t tcb)
+{
+    const uint32_t d = oa - tcb;
+    return d < oa ? d : oa;
+}
+
 // Register share of one chunk: thread t holds run entries t + 256 k.
 template <int SA, int SB>
 struct ChunkRegs {
@@ -322,12 +330,10 @@ struct ChunkRegs {
 // uniform base and one offset register.
 template <int SA, int SB>
 __device__ inline void load_chunk(ChunkRegs<SA, SB>& R, const uint32_t* __restrict__ P,
-                                  const uint16_t* __restrict__ OA, const uint16_t* __restrict__ OB, int64_t cbase,
-                                  const ChunkRun& r, int tid)
+                                  const uint16_t* __restrict__ OA, int64_t cbase, const ChunkRun& r, int tid)
 {
     const unsigned char* pc = reinterpret_cast<const unsigned char*>(P + cbase);
     const unsigned char* ac = reinterpret_cast<const unsigned char*>(OA + cbase);
-    const unsigned char* bc = reinterpret_cast<const unsigned char*>(OB + cbase);
 #pragma unroll
     for (int k = 0; k < SA; ++k) {
         const uint32_t j = (uint32_t)(tid + 256 * k);
@@ -340,7 +346,7 @@ __device__ inline void load_chunk(ChunkRegs<SA, SB>& R, const uint32_t* __restri
         const uint32_t j = (uint32_t)(tid + 256 * k);
         const uint32_t q = j < r.nb ? r.b0 + j : 0u;
         R.pb[k] = *reinterpret_cast<const uint32_t*>(pc + q * 4u);
-        R.ob[k] = *reinterpret_cast<const uint16_t*>(bc + q * 2u);
+        R.ob[k] = *reinterpret_cast<const uint16_t*>(ac + q * 2u);  // row-tile offset: folded at the scatter
     }
 }
 
@@ -393,8 +399,7 @@ template <bool SPLIT, int SA, int SB>
 __device__ inline void put_chunk(MfmaLds<SPLIT>& L, double* diag, const ChunkRegs<SA, SB>& R, const ChunkRun& r,
                                  bool clear,
                                  bool inner, int boff, int tc, const uint32_t* __restrict__ P,
-                                 const uint16_t* __restrict__ OA, const uint16_t* __restrict__ OB, int64_t cbase,
-                                 int tid)
+                                 const uint16_t* __restrict__ OA, int64_t cbase, uint32_t tcb, int tid)
 {
     unsigned char* ta = tile_base<SPLIT>(L, false);
     unsigned char* tb = tile_base<SPLIT>(L, true);
@@ -406,10 +411,9 @@ __device__ inline void put_chunk(MfmaLds<SPLIT>& L, double* diag, const ChunkReg
         }
 #pragma unroll
     for (int k = 0; k < SB; ++k)
-        if ((uint32_t)(tid + 256 * k) < r.nb) lds_put<SPLIT, kLoB>(tb, R.ob[k], clear ? 0u : R.pb[k]);
+        if ((uint32_t)(tid + 256 * k) < r.nb) lds_put<SPLIT, kLoB>(tb, col_offset(R.ob[k], tcb), clear ? 0u : R.pb[k]);
     const uint32_t* pc = P + cbase;
     const uint16_t* ac = OA + cbase;
-    const uint16_t* bc = OB + cbase;
     if (r.na > 256u * SA) {
         for (uint32_t j0 = 256u * SA; j0 < r.na; j0 += 1024u) {
             uint32_t pv[4], ov[4];
@@ -435,7 +439,7 @@ __device__ inline void put_chunk(MfmaLds<SPLIT>& L, double* diag, const ChunkReg
             for (int u = 0; u < 4; ++u) {
                 const uint32_t j = j0 + 256u * u + (uint32_t)tid;
                 const uint32_t q = j < r.nb ? r.b0 + j : 0u;
-                ov[u] = bc[q];
+                ov[u] = col_offset(ac[q], tcb);
                 pv[u] = clear ? 0u : pc[q];
             }
 #pragma unroll
@@ -506,7 +510,7 @@ __device__ inline void mfma_step(const MfmaLds<SPLIT>& L, f32x16 (&acc)[4][2], i
 
 template <bool SPLIT, int SA, int SB>
 __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict__ P, const uint16_t* __restrict__ OA,
-                                                      const uint16_t* __restrict__ OB, const uint32_t* __restrict__ BS, int m, TileGeom g, int64_t n,
+                                                      const uint32_t* __restrict__ BS, int m, TileGeom g, int64_t n,
                                                       int nsplit, int64_t split_len, float* __restrict__ part,
                                                       double* __restrict__ pdiag)
 {
@@ -558,7 +562,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
     for (int k = 0; k < SA; ++k) R_prev.pa[k] = R_prev.oa[k] = 0;
 #pragma unroll
     for (int k = 0; k < SB; ++k) R_prev.pb[k] = R_prev.ob[k] = 0;
-    load_chunk<SA, SB>(R_cur, P, OA, OB, c0 * cstride, r_cur, tid);  // c0 < c1: a range is never empty
+    const uint32_t tcb = (uint32_t)g.tc * (SPLIT ? kBfStride * 2 : kF32Stride * 4);
+    load_chunk<SA, SB>(R_cur, P, OA, c0 * cstride, r_cur, tid);  // c0 < c1: a range is never empty
     uint32_t v_next = chunk_run_load(BS, nb1, c0 + 1, c0 + 1 < c1, c0, rcol);
     ChunkRun r_prev{0, 0, 0, 0};
     int64_t c_prev = c0;
@@ -570,10 +575,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
         // clear the previous chunk's slots, then scatter this chunk; a slot is
         // cleared and written by different waves, so a barrier orders the two
         if (c > c0) {
-            put_chunk<SPLIT, SA, SB>(L, L.diag_ptr(), R_prev, r_prev, true, inner, boff, g.tc, P, OA, OB, c_prev * cstride, tid);
+            put_chunk<SPLIT, SA, SB>(L, L.diag_ptr(), R_prev, r_prev, true, inner, boff, g.tc, P, OA, c_prev * cstride, tcb, tid);
             __syncthreads();
         }
-        put_chunk<SPLIT, SA, SB>(L, L.diag_ptr(), R_cur, r_cur, false, inner, boff, g.tc, P, OA, OB, c * cstride, tid);
+        put_chunk<SPLIT, SA, SB>(L, L.diag_ptr(), R_cur, r_cur, false, inner, boff, g.tc, P, OA, c * cstride, tcb, tid);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < SA; ++k) R_prev.oa[k] = R_cur.oa[k];
@@ -586,7 +591,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
         // this chunk's entry 0), so no value merges after them and nothing
         // waits for them before the matrix-core block
         r_cur = chunk_run_unpack(v_next, c + 1 < c1);
-        load_chunk<SA, SB>(R_cur, P, OA, OB, (c + 1 < c1 ? c + 1 : c) * cstride, r_cur, tid);
+        load_chunk<SA, SB>(R_cur, P, OA, (c + 1 < c1 ? c + 1 : c) * cstride, r_cur, tid);
         v_next = chunk_run_load(BS, nb1, c + 2, c + 2 < c1, c, rcol);
         // keep the scheduler from sinking those loads (or their address math)
         // into the matrix-core block, where their waits would stall it
@@ -749,7 +754,7 @@ struct GramPlan {
     int nsplit, sa, sb;
     int64_t split_len, nchunks;
     size_t off_bytes;               // FP64 variant: per-sample block offsets
-    size_t pk_bytes, bs_bytes;      // matrix-core variants: packed chunks (P, OA, OB) and block starts
+    size_t pk_bytes, bs_bytes;      // matrix-core variants: packed chunks (P, then OA) and block starts
     size_t part_bytes, diag_bytes;
 };
 
@@ -801,7 +806,7 @@ static GramPlan gram_plan(int prec, int p, int m, int64_t n, const DeviceInfo& d
         g.pk_bytes = g.bs_bytes = 0;
     } else {
         g.off_bytes = 0;
-        g.pk_bytes = 2 * up256(nn * (size_t)m * 4);  // P (4 B per entry), then OA and OB (2 B each)
+        g.pk_bytes = up256(nn * (size_t)m * 4) + up256(nn * (size_t)m * 2);  // P (4 B per entry), then OA (2 B)
         g.bs_bytes = up256((size_t)nchunks * (g.geom.nbc + 1) * 4);
     }
     const size_t pe = (prec == 0) ? sizeof(double) : sizeof(float);
@@ -819,7 +824,7 @@ size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo&
 
 template <bool SPLIT, int SA, int SB>
 static void launch_mfma_kernel(const GramPlan& g, int64_t grid, const uint32_t* P, const uint16_t* OA,
-                               const uint16_t* OB, const uint32_t* BS, int m, int64_t n, float* part, double* pdiag, hipStream_t s)
+                               const uint32_t* BS, int m, int64_t n, float* part, double* pdiag, hipStream_t s)
 {
     static bool attr_set = false;
     if (!attr_set) {
@@ -830,17 +835,17 @@ static void launch_mfma_kernel(const GramPlan& g, int64_t grid, const uint32_t* 
     {
         ProfScope ps_(SPLIT ? "gram_bf16x3" : "gram_f32", s);
         hipLaunchKernelGGL((k_gram_mfma<SPLIT, SA, SB>), dim3((unsigned)grid), dim3(256), sizeof(MfmaLds<SPLIT>), s,
-                           P, OA, OB, BS, m, g.geom, n, g.nsplit, g.split_len, part, pdiag);
+                           P, OA, BS, m, g.geom, n, g.nsplit, g.split_len, part, pdiag);
     }
 }
 
 template <bool SPLIT>
 static void dispatch_mfma(const GramPlan& g, int64_t grid, const uint32_t* P, const uint16_t* OA,
-                          const uint16_t* OB, const uint32_t* BS, int m, int64_t n, float* part, double* pdiag, hipStream_t s)
+                          const uint32_t* BS, int m, int64_t n, float* part, double* pdiag, hipStream_t s)
 {
 #define PDS_GRAM_CASE(A, B)                                                                   \
     if (g.sa == A && g.sb == B) {                                                             \
-        launch_mfma_kernel<SPLIT, A, B>(g, grid, P, OA, OB, BS, m, n, part, pdiag, s);                    \
+        launch_mfma_kernel<SPLIT, A, B>(g, grid, P, OA, BS, m, n, part, pdiag, s);                    \
         return;                                                                               \
     }
     PDS_GRAM_CASE(1, 1)
@@ -889,8 +894,7 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
                            idx, off, m, g.geom, n, g.nsplit, g.split_len, reinterpret_cast<double*>(part));
     } else {
         uint32_t* P = reinterpret_cast<uint32_t*>(w);
-        uint16_t* OA = reinterpret_cast<uint16_t*>(w + g.pk_bytes / 2);
-        uint16_t* OB = reinterpret_cast<uint16_t*>(w + g.pk_bytes / 2 + g.pk_bytes / 4);
+        uint16_t* OA = reinterpret_cast<uint16_t*>(w + up256((size_t)n * (size_t)m * 4));
         uint32_t* BS = reinterpret_cast<uint32_t*>(w + g.pk_bytes);
         const bool split = (prec == 2);
         const bool stage = (size_t)kChunk * m * 2 <= (size_t)kPackStageBytes &&
@@ -911,18 +915,18 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
             if (stage)
                 hipLaunchKernelGGL(k_gram_pack<true>, dim3((unsigned)g.nchunks), dim3(256), lds, s,
                                    reinterpret_cast<const float*>(vals), idx, n, m, g.geom.tr, g.geom.tc, g.geom.nbc,
-                                   rowbytes, split ? 1 : 0, P, OA, OB, BS);
+                                   rowbytes, split ? 1 : 0, P, OA, BS);
             else
                 hipLaunchKernelGGL(k_gram_pack<false>, dim3((unsigned)g.nchunks), dim3(256), lds, s,
                                    reinterpret_cast<const float*>(vals), idx, n, m, g.geom.tr, g.geom.tc, g.geom.nbc,
-                                   rowbytes, split ? 1 : 0, P, OA, OB, BS);
+                                   rowbytes, split ? 1 : 0, P, OA, BS);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (split)
-            dispatch_mfma<true>(g, grid, P, OA, OB, BS, m, n, reinterpret_cast<float*>(part), pdiag, s);
+            dispatch_mfma<true>(g, grid, P, OA, BS, m, n, reinterpret_cast<float*>(part), pdiag, s);
         else
-            dispatch_mfma<false>(g, grid, P, OA, OB, BS, m, n, reinterpret_cast<float*>(part), nullptr, s);
+            dispatch_mfma<false>(g, grid, P, OA, BS, m, n, reinterpret_cast<float*>(part), nullptr, s);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
