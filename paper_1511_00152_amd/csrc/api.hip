@@ -561,6 +561,20 @@ int accum_kg(int K, int p)
     return kg;
 }
 
+// Samples per accumulation chunk of a set: the tuned length, halved while an
+// item (a chunk and a cluster group) would hold more than kAccItemEntries kept
+// entries on average (large m with few cluster groups), so that no single item
+// keeps its workgroup busy long after the others have finished.
+constexpr double kAccItemEntries = 262144.0;
+
+int accum_chunk(int64_t m, int K, int p, int tuned)
+{
+    const double per = (double)m * (double)accum_kg(K, p) / (double)K;  // entries per sample and item
+    int c = tuned;
+    while (c > 256 && (double)c * per > kAccItemEntries) c >>= 1;
+    return c;
+}
+
 BatchOffsets batch_offsets(const pds_batch_s& b)
 {
     const size_t ns = b.descs.size();
@@ -569,9 +583,11 @@ BatchOffsets batch_offsets(const pds_batch_s& b)
         const int64_t KP = (int64_t)d.K * d.p;
         ct += (size_t)KP;
         tiles += (size_t)cdiv(d.n, 64) * 64 * (size_t)((d.m + 7) & ~7);
-        pobj += (size_t)cdiv(d.n, kBatchCchunkCand[0]);  // one objective partial per accumulation chunk
+        // the smallest candidate gives the most chunks (accum_chunk grows with it)
+        const int64_t cmin = accum_chunk(d.m, d.K, d.p, kBatchCchunkCand[0]);
+        pobj += (size_t)cdiv(d.n, cmin);  // one objective partial per accumulation chunk
         nsamp += (size_t)d.n;
-        part += (size_t)cdiv(d.n, kBatchCchunkCand[0]) * (size_t)KP;
+        part += (size_t)cdiv(d.n, cmin) * (size_t)KP;
     }
     BatchOffsets o;
     size_t off = 0;
@@ -651,8 +667,8 @@ void batch_build(const pds_batch_s& b, const pds::BatchTuning& tu, unsigned char
         S.naitems = cdiv(d.n, pds::kBatchAssignSamples);
         S.ct_off = ct;
         S.part_off = part;
-        S.cchunk = tu.cchunk;
-        S.nacc = cdiv(d.n, tu.cchunk);
+        S.cchunk = accum_chunk(d.m, d.K, d.p, tu.cchunk);
+        S.nacc = cdiv(d.n, S.cchunk);
         S.kg = accum_kg(d.K, d.p);
         S.ngk = (int)cdiv(d.K, S.kg);
         S.ntiles = cdiv(d.n, 64);

@@ -197,7 +197,11 @@ __global__ __launch_bounds__(256) void k_batch_prep(const BatchSet* __restrict__
 {
     __shared__ uint32_t red[256];
     const int d = blockIdx.x;
-    if (d == 0 && threadIdx.x == 0) *rcount = 0u;
+    if (d == 0 && threadIdx.x == 0) {
+        rcount[0] = 0u;
+        rcount[1] = 0u;  // the first round's queues
+        rcount[2] = 0u;
+    }
     if (threadIdx.x == 0) vmax[d] = 0u;  // the tiling that follows takes the set's largest |value|
     const BatchSet& S = sets[d];
     const int64_t KP = (int64_t)S.K * S.p;
@@ -341,6 +345,22 @@ __device__ inline void batch_assign_item(const BatchSet& S, int set, int64_t j, 
     }
 }
 
+// Work queues of the persistent assignment and accumulation launches: the
+// workgroup takes the next item from a counter (items differ in cost by two
+// orders of magnitude across sets, so a fixed round-robin leaves CUs idle).
+// Counter words: rcount[0] recheck list length, rcount[1] assignment queue,
+// rcount[2] accumulation queue; prep clears both, then each queue is cleared
+// by a launch that runs after its last use and before its next (the
+// assignment clears the accumulation queue, the update the assignment
+// queue).
+__device__ inline int64_t next_item(uint32_t* queue, int64_t* shared_item)
+{
+    __syncthreads();  // every thread has read the previous item
+    if (threadIdx.x == 0) *shared_item = (int64_t)atomicAdd(queue, 1u);
+    __syncthreads();
+    return *shared_item;
+}
+
 __global__ __launch_bounds__(kBaThreads) void k_batch_assign(const BatchSet* __restrict__ sets, int nsets,
                                                              const int64_t* __restrict__ aprefix, int64_t nitems,
                                                              const float* __restrict__ ct,
@@ -352,7 +372,9 @@ __global__ __launch_bounds__(kBaThreads) void k_batch_assign(const BatchSet* __r
                                                              uint32_t* __restrict__ rcount)
 {
     extern __shared__ __align__(16) float lc[];  // kBaLdsFloats
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    __shared__ int64_t item;
+    if (blockIdx.x == 0 && threadIdx.x == 0) rcount[2] = 0u;  // the accumulation queue, for the launch after
+    for (int64_t it = next_item(rcount + 1, &item); it < nitems; it = next_item(rcount + 1, &item)) {
         const int d = owner(aprefix, nsets, it);
         const BatchSet& S = sets[d];
         const int64_t j = it - aprefix[d];
@@ -415,19 +437,24 @@ __global__ __launch_bounds__(256) void k_batch_recheck(const BatchSet* __restric
     }
 }
 
+constexpr int kAccSeg = 4096;  // samples listed at a time by k_batch_accum
+
 __global__ __launch_bounds__(kBcThreads) void k_batch_accum(const BatchSet* __restrict__ sets, int nsets,
                                                             const int64_t* __restrict__ cprefix, int64_t nitems,
                                                             int64_t* __restrict__ psum, uint32_t* __restrict__ pcnt,
                                                             const uint32_t* __restrict__ vmax,
                                                             const double* __restrict__ dist,
-                                                            double* __restrict__ pobj)
+                                                            double* __restrict__ pobj, uint32_t* __restrict__ qcount)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kBcThreads / 64];
     // 64-bit fixed-point sums: integer LDS atomics run at full rate, the FP32
     // ones do not
     unsigned long long* sums = reinterpret_cast<unsigned long long*>(smem);
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    uint16_t* list = reinterpret_cast<uint16_t*>(smem + kBatchAccumLds);  // kAccSeg sample offsets
+    __shared__ uint32_t lcount[1];
+    __shared__ int64_t item;
+    for (int64_t it = next_item(qcount + 2, &item); it < nitems; it = next_item(qcount + 2, &item)) {
         const int d = owner(cprefix, nsets, it);
         const BatchSet& S = sets[d];
         const int64_t j = it - cprefix[d];
@@ -461,51 +488,38 @@ __global__ __launch_bounds__(kBcThreads) void k_batch_accum(const BatchSet* __re
                 pobj[S.pchunk0 + chunk] = t;
             }
         }
-        // 16 lanes per sample, four samples of the wave at a time
-        const int lane = threadIdx.x & 63;
-        const int sub = lane >> 4, sl = lane & 15;
-        for (int64_t base = s0 + (int64_t)(threadIdx.x >> 6) * 64; base < s1; base += kBcThreads) {
-            const int64_t mine = base + lane;
-            int c = -1;
-            if (mine < s1) c = S.assign[mine];
-            uint64_t mask = __ballot(c >= k0 && c < k0 + kg);
-            while (mask) {
-                // the next (up to) four in-group samples, one per quarter-wave
-                int pick = -1;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int bsel = mask ? __builtin_ctzll(mask) : -1;
-                    if (bsel >= 0) mask &= mask - 1ull;
-                    if (q == sub) pick = bsel;
-                }
-                const int cb = __shfl(c, pick < 0 ? 0 : pick, 64);
-                if (pick >= 0) {
-                    const int64_t i = base + pick;
-                    const float* v = S.vals + i * (int64_t)m;
-                    const uint16_t* ix = S.idx + i * (int64_t)m;
-                    unsigned long long* sk = sums + (cb - k0) * p;
-                    uint32_t* ck = cnts + (cb - k0) * p;
-                    // four entries per lane per step: the loads are issued before the atomics
-                    for (int a0 = sl; a0 < m; a0 += 64) {
-                        int l[4];
-                        float x[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int a = a0 + 16 * u;
-                            l[u] = (a < m) ? (int)ix[a] : 0;
-                            x[u] = (a < m) ? v[a] : 0.0f;
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            if (a0 + 16 * u < m) {
-                                const long long q = __double2ll_rn(ldexp((double)x[u], fx));
-                                atomicAdd(&sk[l[u]], (unsigned long long)q);
-                                atomicAdd(&ck[l[u]], 1u);
-                            }
-                        }
-                    }
-                }
+        // The chunk's samples of this cluster group are listed (LDS slot
+        // counter, any order), kAccSeg at a time; then the threads walk the
+        // listed samples' entries as one flat range (consecutive threads on
+        // consecutive entries of a sample: coalesced, and many loads in
+        // flight per thread), adding each to its cluster's sums and counts.
+        // Integer additions: the order does not change the result.
+        for (int64_t g0 = s0; g0 < s1; g0 += kAccSeg) {
+            if (threadIdx.x == 0) *lcount = 0u;
+            __syncthreads();
+            for (int64_t i = g0 + threadIdx.x; i < s1 && i < g0 + kAccSeg; i += kBcThreads) {
+                const int c = S.assign[i];
+                if (c >= k0 && c < k0 + kg) list[atomicAdd(lcount, 1u)] = (uint16_t)(i - g0);
             }
+            __syncthreads();
+            const int cnt = (int)*lcount;
+            const int tot = cnt * m;
+            const float inv_m = 1.0f / (float)m;
+#pragma unroll 4
+            for (int f = threadIdx.x; f < tot; f += kBcThreads) {
+                int r = (int)((float)f * inv_m);
+                while (r * m > f) --r;
+                while ((r + 1) * m <= f) ++r;
+                const int64_t i = g0 + list[r];
+                const int64_t e = i * (int64_t)m + (f - r * m);
+                const int cb = S.assign[i] - k0;
+                const int l = (int)S.idx[e];
+                const float x = S.vals[e];
+                const long long q = __double2ll_rn(ldexp((double)x, fx));
+                atomicAdd(&sums[cb * p + l], (unsigned long long)q);
+                atomicAdd(&cnts[cb * p + l], 1u);
+            }
+            __syncthreads();  // the list is rebuilt for the next segment
         }
         __syncthreads();
         const int64_t KP = (int64_t)S.K * p;
@@ -537,7 +551,10 @@ __global__ __launch_bounds__(256) void k_batch_update(const BatchSet* __restrict
             for (int64_t a = 0; a < S.nacc; ++a) o += pobj[S.pchunk0 + a];
             S.objective[round] = o;
         }
-        if (it == 0 && threadIdx.x == 0) *rcount = 0u;  // for the next round
+        if (it == 0 && threadIdx.x == 0) {
+            rcount[0] = 0u;  // for the next round: the recheck list and the assignment queue
+            rcount[1] = 0u;
+        }
         if (e >= KP) continue;
         double sum = 0.0;
         uint64_t cnt = 0;
@@ -596,7 +613,7 @@ hipError_t batch_init_attributes()
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_accum),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, kBatchAccumLds);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kBatchAccumLds + kAccSeg * 2);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_assign),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kBaLdsFloats * 4);
@@ -673,8 +690,8 @@ hipError_t launch_batch_round(const BatchSet* sets, int nsets, const BatchTables
     if (e != hipSuccess) return e;
     if (t.ncitems > 0) {
         int64_t grid = t.ncitems < tu.accum_grid ? t.ncitems : tu.accum_grid;
-        hipLaunchKernelGGL(k_batch_accum, dim3((unsigned)grid), dim3(kBcThreads), (size_t)kBatchAccumLds, s, sets,
-                           nsets, t.cprefix, t.ncitems, t.psum, t.pcnt, t.vmax, t.dist, t.pobj);
+        hipLaunchKernelGGL(k_batch_accum, dim3((unsigned)grid), dim3(kBcThreads), (size_t)(kBatchAccumLds + kAccSeg * 2), s, sets,
+                           nsets, t.cprefix, t.ncitems, t.psum, t.pcnt, t.vmax, t.dist, t.pobj, t.rcount);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
