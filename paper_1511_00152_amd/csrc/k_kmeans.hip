@@ -288,6 +288,110 @@ __global__ __launch_bounds__(256) void k_kmeans_absmax(const float* __restrict__
     if (threadIdx.x == 0) atomicMax(vmax, red[0]);
 }
 
+// One sample of the cooperative assignment (its group of W lanes): distances
+// from the entries the lanes hold (x, l: four per lane, entries u W + sl, -1
+// past m; further entries are loaded here when m > 4 W), the decision, and the
+// entries' sums and counts.
+template <int W, int NQ4>
+__device__ inline void coop_sample(int64_t i, const float (&x0)[4], const int (&l0)[4],
+                                   const float* __restrict__ vals, const uint16_t* __restrict__ idx, int m, int p,
+                                   int K, int KP4, const float* cT, unsigned long long* sums, uint32_t* cnt2,
+                                   int fx, float cmax, int sl, int32_t* __restrict__ assign,
+                                   double* __restrict__ dist, int64_t* __restrict__ rlist,
+                                   uint32_t* __restrict__ rcount)
+{
+    constexpr int NQ = 4 * NQ4;  // clusters padded to a multiple of four
+    const float* v = vals + i * (int64_t)m;
+    const uint16_t* ix = idx + i * (int64_t)m;
+    float d[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) d[q] = 0.0f;
+    float sv = 0.0f;
+    for (int a0 = 0; a0 < m; a0 += 4 * W) {
+        float x[4];
+        int l[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (a0 == 0) {
+                x[u] = x0[u];
+                l[u] = l0[u];
+            } else {
+                const int a = a0 + u * W + sl;
+                x[u] = (a < m) ? v[a] : 0.0f;
+                l[u] = (a < m) ? (int)ix[a] : -1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (l[u] >= 0) {
+                sv = fmaf(x[u], x[u], sv);
+                const float4* c4 = reinterpret_cast<const float4*>(cT + l[u] * KP4);
+#pragma unroll
+                for (int q4 = 0; q4 < NQ4; ++q4) {
+                    const float4 c = c4[q4];
+                    const float cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float diff = x[u] - cc[r];
+                        d[4 * q4 + r] = fmaf(diff, diff, d[4 * q4 + r]);
+                    }
+                }
+            }
+        }
+    }
+    sv = dpp_row_total(sv);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) d[q] = dpp_row_total(d[q]);
+    // lane W - 1 of the row holds the totals and decides; padding clusters
+    // (q >= K) take no part
+    float best = INFINITY, second = INFINITY;
+    int bestk = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const float dq = q < K ? d[q] : INFINITY;
+        const bool nb = dq < best;
+        second = nb ? best : fminf(second, dq);
+        bestk = nb ? q : bestk;
+        best = nb ? dq : best;
+    }
+    int flag = 0;
+    if (K > 1) {
+        // |d32 - d| <= u (8 (sum v^2 + sum mu^2) + 1.01 m d), u = 2^-24, per
+        // candidate; two candidates, factor 2 of slack
+        const float u = 5.9604645e-8f;
+        const float mf = (float)m;
+        const float bound = 2.0f * u * (16.0f * (sv + mf * cmax * cmax) + 1.01f * mf * (best + second));
+        flag = !(second - best > bound);
+    }
+    flag = __shfl(flag, W - 1, W);
+    bestk = __shfl(bestk, W - 1, W);
+    if (flag) {
+        if (sl == W - 1) rlist[atomicAdd(rcount, 1u)] = i;
+        return;
+    }
+    if (sl == W - 1) {
+        assign[i] = bestk;
+        dist[i] = (double)best;
+    }
+    const int64_t kb = (int64_t)bestk * p;
+    // the first 4 W entries from registers, any others from memory
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (l0[u] >= 0) {
+            const int64_t e = kb + l0[u];
+            atomicAdd(&sums[e], (unsigned long long)__double2ll_rn(ldexp((double)x0[u], fx)));
+            atomicAdd(&cnt2[e >> 1], 1u << (16 * (int)(e & 1)));
+        }
+    }
+    for (int a = 4 * W + sl; a < m; a += W) {
+        const int64_t e = kb + ix[a];
+        atomicAdd(&sums[e], (unsigned long long)__double2ll_rn(ldexp((double)v[a], fx)));
+        atomicAdd(&cnt2[e >> 1], 1u << (16 * (int)(e & 1)));
+    }
+}
+
+
+template <int NQ4>
 __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     const float* __restrict__ vals, const uint16_t* __restrict__ idx, int64_t n, int m, int p, int K,
     const double* __restrict__ cin, int64_t per_wg, int32_t* __restrict__ assign, int64_t* __restrict__ psum,
@@ -300,7 +404,6 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     __shared__ float red_f[kKmLdsThreads / 64];
     const int tid = threadIdx.x;
     const int KP4 = (K + 3) & ~3;
-    const int nq4 = KP4 >> 2;
     const int64_t KP = (int64_t)K * p;
     // centers transposed (rows padded to 4), 64-bit fixed-point sums and
     // 16-bit counts two to a word: integer LDS atomics run at full rate, the
@@ -324,86 +427,35 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     const int64_t i0 = (int64_t)blockIdx.x * per_wg;
     int64_t i1 = i0 + per_wg;
     if (i1 > n) i1 = n;
-    for (int64_t i = i0 + g; i < i1; i += G) {
+    // the first 4 W entries of the samples two and one steps ahead are in
+    // flight while a sample is processed
+    auto load_first = [&](int64_t i, float (&x)[4], int (&l)[4]) {
         const float* v = vals + i * (int64_t)m;
         const uint16_t* ix = idx + i * (int64_t)m;
-        float d[32];
 #pragma unroll
-        for (int q = 0; q < 32; ++q) d[q] = 0.0f;
-        float sv = 0.0f;
-        for (int a0 = 0; a0 < m; a0 += 4 * W) {
-            float x[4];
-            int l[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int a = a0 + u * W + sl;
-                x[u] = (a < m) ? v[a] : 0.0f;
-                l[u] = (a < m) ? (int)ix[a] : -1;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (l[u] >= 0) {
-                    sv = fmaf(x[u], x[u], sv);
-                    const float4* c4 = reinterpret_cast<const float4*>(cT + l[u] * KP4);
-#pragma unroll
-                    for (int q4 = 0; q4 < 8; ++q4) {
-                        if (q4 < nq4) {
-                            const float4 c = c4[q4];
-                            const float cc[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const float diff = x[u] - cc[r];
-                                d[4 * q4 + r] = fmaf(diff, diff, d[4 * q4 + r]);
-                            }
-                        }
-                    }
-                }
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int a = u * W + sl;
+            x[u] = (a < m) ? v[a] : 0.0f;
+            l[u] = (a < m) ? (int)ix[a] : -1;
         }
-        sv = dpp_row_total(sv);
+    };
+    float xa[4], xb[4];
+    int la[4], lb[4];
+    if (i0 + g < i1) load_first(i0 + g, xa, la);
+    if (i0 + g + G < i1) load_first(i0 + g + G, xb, lb);
+    for (int64_t i = i0 + g; i < i1; i += G) {
+        float x[4];
+        int l[4];
 #pragma unroll
-        for (int q = 0; q < 32; ++q)
-            if (q < K) d[q] = dpp_row_total(d[q]);
-        // lane 15 of the row holds the totals and decides
-        float best = INFINITY, second = INFINITY;
-        int bestk = 0;
-#pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            if (q < K) {
-                if (d[q] < best) {
-                    second = best;
-                    best = d[q];
-                    bestk = q;
-                } else if (d[q] < second) {
-                    second = d[q];
-                }
-            }
+        for (int u = 0; u < 4; ++u) {
+            x[u] = xa[u];
+            l[u] = la[u];
+            xa[u] = xb[u];
+            la[u] = lb[u];
         }
-        int flag = 0;
-        if (K > 1) {
-            // |d32 - d| <= u (8 (sum v^2 + sum mu^2) + 1.01 m d), u = 2^-24, per
-            // candidate; two candidates, factor 2 of slack
-            const float u = 5.9604645e-8f;
-            const float mf = (float)m;
-            const float bound = 2.0f * u * (16.0f * (sv + mf * cmax * cmax) + 1.01f * mf * (best + second));
-            flag = !(second - best > bound);
-        }
-        flag = __shfl(flag, W - 1, W);
-        bestk = __shfl(bestk, W - 1, W);
-        if (flag) {
-            if (sl == W - 1) rlist[atomicAdd(rcount, 1u)] = i;
-            continue;
-        }
-        if (sl == W - 1) {
-            assign[i] = bestk;
-            dist[i] = (double)best;
-        }
-        const int64_t kb = (int64_t)bestk * p;
-        for (int a = sl; a < m; a += W) {
-            const int64_t e = kb + ix[a];
-            atomicAdd(&sums[e], (unsigned long long)__double2ll_rn(ldexp((double)v[a], fx)));
-            atomicAdd(&cnt2[e >> 1], 1u << (16 * (int)(e & 1)));
-        }
+        if (i + 2 * G < i1) load_first(i + 2 * G, xb, lb);
+        coop_sample<W, NQ4>(i, x, l, vals, idx, m, p, K, KP4, cT, sums, cnt2, fx, cmax, sl, assign, dist, rlist,
+                            rcount);
     }
     __syncthreads();
     int64_t* ps = psum + (int64_t)blockIdx.x * KP;
@@ -667,8 +719,16 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
             if (k.coop) {
                 static bool coop_attr = false;
                 if (!coop_attr) {
-                    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kmeans_assign_coop),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kKmLdsMax);
+                    const void* fns[8] = {reinterpret_cast<const void*>(&k_kmeans_assign_coop<1>),
+                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<2>),
+                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<3>),
+                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<4>),
+                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<5>),
+                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<6>),
+                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<7>),
+                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<8>)};
+                    for (const void* f : fns)
+                        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kKmLdsMax);
                     coop_attr = true;
                 }
                 {
@@ -681,9 +741,24 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
                 }
                 {
                     ProfScope ps_("kmeans_assign", s);
-                    hipLaunchKernelGGL(k_kmeans_assign_coop, dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s, vals, idx,
-                                       n, m, p, K, cin, k.per_wg, assign, reinterpret_cast<int64_t*>(psum), pcnt,
-                                       vmax, dist, rlist, rcount);
+                    // K <= 32 here: one instance per number of four-cluster groups
+#define PDS_KM_COOP(Q)                                                                                        \
+    case Q:                                                                                                   \
+        hipLaunchKernelGGL(k_kmeans_assign_coop<Q>, dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s, vals, idx, n, m, \
+                           p, K, cin, k.per_wg, assign, reinterpret_cast<int64_t*>(psum), pcnt, vmax, dist,     \
+                           rlist, rcount);                                                                    \
+        break;
+                    switch ((K + 3) / 4) {
+                        PDS_KM_COOP(1)
+                        PDS_KM_COOP(2)
+                        PDS_KM_COOP(3)
+                        PDS_KM_COOP(4)
+                        PDS_KM_COOP(5)
+                        PDS_KM_COOP(6)
+                        PDS_KM_COOP(7)
+                        default: PDS_KM_COOP(8)
+                    }
+#undef PDS_KM_COOP
                 }
                 goto assigned;
             }
