@@ -726,7 +726,11 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const PT* __restrict__ part
     int ta, tb;
     decode_rect_tile(tile, g, ta, tb);
     double sum = 0.0;
-    for (int s = 0; s < nsplit; ++s) sum += (double)part[((int64_t)s * g.ntiles + tile) * per_tile + e];
+    // the loads of eight ranges are issued together; the sum keeps range order
+    const PT* pe = part + (int64_t)tile * per_tile + e;
+    const int64_t rstride = (int64_t)g.ntiles * per_tile;
+#pragma unroll 8
+    for (int s = 0; s < nsplit; ++s) sum += (double)pe[(int64_t)s * rstride];
     const int boff = tb * g.tc - ta * g.tr;
     if (pdiag && tb < (ta + 1) * g.ratio && i == j + boff)
         for (int s = 0; s < nsplit; ++s) sum += pdiag[((int64_t)s * g.ntiles + tile) * g.tc + j];
