@@ -558,6 +558,8 @@ __global__ __launch_bounds__(256) void k_batch_update(const BatchSet* __restrict
         if (e >= KP) continue;
         double sum = 0.0;
         uint64_t cnt = 0;
+        // eight chunks' loads in flight; the sum keeps chunk order
+#pragma unroll 8
         for (int64_t c = 0; c < S.nacc; ++c) {
             sum += (double)psum[S.part_off + c * KP + e];
             cnt += pcnt[S.part_off + c * KP + e];
