@@ -238,13 +238,6 @@ __device__ inline float dpp_row_total(float v)
     return v;  // the row total in lane 15 of the row
 }
 
-// FP32 assignment with coalesced rows: a group of 16 lanes (one DPP row) per
-// sample, lanes over its kept entries, each lane's partial distances to the
-// K <= 32 centers in registers, then a row sum.  The summation order differs
-// from the sequential one, but its rounding error obeys the same bound (every
-// term passes through at most m additions), so the near-tie test and the FP64
-// recheck give the FP64 argmin as before.  Centers are transposed in LDS with
-// rows padded to KP4 = ceil4(K) floats and read as float4.
 // Fixed-point scale of a workgroup's sums: at most per_wg values of magnitude
 // below 2^ev (frexp of the largest |value|) go into one sum, so with F = 62 -
 // ev - ceil(log2 per_wg) every sum times 2^F stays below 2^62; each value is
@@ -256,36 +249,6 @@ __device__ inline int km_fx_exp(uint32_t vmax_bits, int64_t per_wg)
     (void)frexpf(__uint_as_float(vmax_bits), &ev);
     const int cb = per_wg > 1 ? 64 - __clzll((unsigned long long)(per_wg - 1)) : 0;
     return 62 - ev - cb;
-}
-
-// largest |value| of the compressed data (float bits; the target is cleared by
-// the prep kernel)
-__global__ __launch_bounds__(256) void k_kmeans_absmax(const float* __restrict__ vals, int64_t count,
-                                                       uint32_t* __restrict__ vmax)
-{
-    __shared__ uint32_t red[256];
-    uint32_t mx = 0u;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    const int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    // 16-byte loads over the aligned part (the sign bit is masked off the
-    // float bits, which then order like the magnitudes)
-    const int64_t head = (int64_t)((16 - (reinterpret_cast<uintptr_t>(vals) & 15)) & 15) / 4;
-    const int64_t h = head < count ? head : count;
-    const int64_t nv = (count - h) / 4;
-    const uint4* v4 = reinterpret_cast<const uint4*>(vals + h);
-    for (int64_t e = t0; e < nv; e += stride) {
-        const uint4 q = v4[e];
-        mx = max(mx, max(max(q.x & 0x7fffffffu, q.y & 0x7fffffffu), max(q.z & 0x7fffffffu, q.w & 0x7fffffffu)));
-    }
-    for (int64_t e = t0; e < h; e += stride) mx = max(mx, __float_as_uint(fabsf(vals[e])));
-    for (int64_t e = h + nv * 4 + t0; e < count; e += stride) mx = max(mx, __float_as_uint(fabsf(vals[e])));
-    red[threadIdx.x] = mx;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(vmax, red[0]);
 }
 
 // One sample of the cooperative assignment (its group of W lanes): distances
@@ -391,11 +354,19 @@ __device__ inline void coop_sample(int64_t i, const float (&x0)[4], const int (&
 }
 
 
+// FP32 assignment with coalesced rows: a group of 16 lanes (one DPP row) per
+// sample, lanes over its kept entries, each lane's partial distances to the
+// K <= 32 centers in registers, then a row sum.  The summation order differs
+// from the sequential one, but its rounding error obeys the same bound (every
+// term passes through at most m additions), so the near-tie test and the FP64
+// recheck give the FP64 argmin as before.  Centers are transposed in LDS with
+// rows padded to KP4 = ceil4(K) floats and read as float4.  Each workgroup
+// takes its own fixed-point scale from its samples' largest |value|.
 template <int NQ4>
 __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     const float* __restrict__ vals, const uint16_t* __restrict__ idx, int64_t n, int m, int p, int K,
     const double* __restrict__ cin, int64_t per_wg, int32_t* __restrict__ assign, int64_t* __restrict__ psum,
-    uint32_t* __restrict__ pcnt, const uint32_t* __restrict__ vmax, double* __restrict__ dist,
+    uint32_t* __restrict__ pcnt, uint32_t* __restrict__ wvmax, double* __restrict__ dist,
     int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
 {
     constexpr int W = 16;
@@ -411,7 +382,18 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     float* cT = reinterpret_cast<float*>(smem);
     unsigned long long* sums = reinterpret_cast<unsigned long long*>(cT + (int64_t)KP4 * p);
     uint32_t* cnt2 = reinterpret_cast<uint32_t*>(sums + KP);
-    const int fx = km_fx_exp(*vmax, per_wg);
+    const int64_t i0 = (int64_t)blockIdx.x * per_wg;
+    int64_t i1 = i0 + per_wg;
+    if (i1 > n) i1 = n;
+    // the fixed-point scale of this workgroup's sums: the largest |value| of
+    // its own samples (kept in wvmax for the update)
+    float vm = 0.0f;
+    {
+        const float* vb = vals + i0 * (int64_t)m;
+        const int64_t cnt = (i1 > i0 ? i1 - i0 : 0) * (int64_t)m;
+#pragma unroll 4
+        for (int64_t e = tid; e < cnt; e += kKmLdsThreads) vm = fmaxf(vm, fabsf(vb[e]));
+    }
     for (int64_t e = tid; e < (int64_t)KP4 * p; e += kKmLdsThreads) {
         const int64_t l = e / KP4, k = e - l * KP4;
         cT[e] = (k < K) ? (float)cin[k * p + l] : 0.0f;
@@ -422,11 +404,11 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     float cmax = 0.0f;
     for (int64_t e = tid; e < (int64_t)KP4 * p; e += kKmLdsThreads) cmax = fmaxf(cmax, fabsf(cT[e]));
     cmax = block_max_f32<kKmLdsThreads>(cmax, red_f);
+    vm = block_max_f32<kKmLdsThreads>(vm, red_f);
+    if (tid == 0) wvmax[blockIdx.x] = __float_as_uint(vm);
+    const int fx = km_fx_exp(__float_as_uint(vm), per_wg);
 
     const int g = tid / W, sl = tid % W;
-    const int64_t i0 = (int64_t)blockIdx.x * per_wg;
-    int64_t i1 = i0 + per_wg;
-    if (i1 > n) i1 = n;
     // the first 4 W entries of the samples two and one steps ahead are in
     // flight while a sample is processed
     auto load_first = [&](int64_t i, float (&x)[4], int (&l)[4]) {
@@ -558,7 +540,9 @@ __global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const S* __restri
     uint64_t cnt = 0;
     if (g < KP) {
         for (int w = wv; w < nparts; w += kUpdThreads / 64) {
-            sum += (double)psum[(int64_t)w * KP + g];
+            const double pv = (double)psum[(int64_t)w * KP + g];
+            // fixed-point partials carry their workgroup's scale
+            sum += vmax ? ldexp(pv, -km_fx_exp(vmax[w], per_wg)) : pv;
             cnt += pcnt[(int64_t)w * KP + g];
         }
     }
@@ -572,7 +556,6 @@ __global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const S* __restri
             t += rs[w][lane];
             c += rc[w][lane];
         }
-        if (vmax) t = ldexp(t, -km_fx_exp(*vmax, per_wg));  // fixed-point partials
         t += gsum_r[g];
         c += gcnt_r[g];
         cout[g] = (c > 0) ? t / (double)c : cin[g];
@@ -659,7 +642,7 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
     k.rcount_bytes = 256;
     k.gsumr_bytes = al256(KP * 8);
     k.gcntr_bytes = al256(KP * 4);
-    k.vmax_bytes = 256;
+    k.vmax_bytes = al256((size_t)k.nwg * 4);  // per-workgroup largest |value| (fixed-point scale)
     return k;
 }
 
@@ -730,14 +713,6 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
                     for (const void* f : fns)
                         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kKmLdsMax);
                     coop_attr = true;
-                }
-                {
-                    ProfScope ps_("kmeans_absmax", s);
-                    const int64_t cnt = n * (int64_t)m;
-                    int64_t blocks = (cnt + 255) / 256;
-                    if (blocks > (int64_t)dev.cus * 16) blocks = (int64_t)dev.cus * 16;
-                    hipLaunchKernelGGL(k_kmeans_absmax, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s,
-                                       reinterpret_cast<const float*>(vals), cnt, vmax);
                 }
                 {
                     ProfScope ps_("kmeans_assign", s);
