@@ -238,8 +238,11 @@ __device__ inline double batch_dist_f64(const float* __restrict__ v, const uint1
 
 // Assignment of one item (kBaThreads samples, one per thread).  The set's
 // FP32 centers are staged through LDS a window of KW clusters at a time, for
-// all p coordinates (row l holds the window's centers at coordinate l, padded
-// against bank conflicts when it fits); each thread streams its sample's kept
+// all p coordinates (row l holds the window's centers at coordinate l, its
+// 16-byte quads permuted by an XOR with bits of l that the row's own bank
+// offset does not use, so the lanes' reads at random rows spread over all
+// eight 4-bank groups; unpadded, so the permutation works at every p, where a
+// padded row no longer fits from p = 1024); each thread streams its sample's kept
 // entries once per window, so every distance accumulates its terms in
 // ascending coordinate order exactly as the single-plan kernel does.
 template <int KW>
@@ -249,7 +252,8 @@ __device__ inline void batch_assign_item(const BatchSet& S, int set, int64_t j, 
                                          int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
 {
     const int K = S.K, p = S.p, m = S.m;
-    const int RS = (p * (KW + 4) <= kBaLdsFloats) ? KW + 4 : KW;
+    constexpr int NQ = KW / 4;                                  // quads per row
+    constexpr int XS = KW == 32 ? 0 : (KW == 16 ? 1 : 2);      // row bits the row offset uses (32 / KW rows per bank sweep)
     const int64_t i = j * kBaThreads + threadIdx.x;
     const bool live = i < S.n;
     // this sample's entries in its tile: chunk c (eight entries) at element tb + 512 c
@@ -265,7 +269,8 @@ __device__ inline void batch_assign_item(const BatchSet& S, int set, int64_t j, 
         __syncthreads();  // the previous window's reads are done
         for (int e = threadIdx.x; e < p * KW; e += kBaThreads) {
             const int r = e / KW, k = e - r * KW;
-            lc[r * RS + k] = (kc + k < K) ? cT[(int64_t)r * K + kc + k] : 0.0f;
+            const int pq = (k >> 2) ^ ((r >> XS) & (NQ - 1));
+            lc[r * KW + pq * 4 + (k & 3)] = (kc + k < K) ? cT[(int64_t)r * K + kc + k] : 0.0f;
         }
         __syncthreads();
         float d[KW];
@@ -303,11 +308,18 @@ __device__ inline void batch_assign_item(const BatchSet& S, int set, int64_t j, 
                                 const int l = (int)((iw[u >> 1] >> ((u & 1) * 16)) & 0xFFFFu);
                                 const float x = xw[u];
                                 if (kc == 0) sv = fmaf(x, x, sv);
-                                const float* cc = lc + l * RS;
+                                // byte offset of quad q of row l: (l NQ + ((l >> XS) mod NQ)) 16 XOR 16 q
+                                const uint32_t rb = (uint32_t)(l * NQ + ((l >> XS) & (NQ - 1))) << 4;
+                                const unsigned char* lcb = reinterpret_cast<const unsigned char*>(lc);
 #pragma unroll
-                                for (int q = 0; q < KW; ++q) {
-                                    const float diff = x - cc[q];
-                                    d[q] = fmaf(diff, diff, d[q]);
+                                for (int q4 = 0; q4 < NQ; ++q4) {
+                                    const float4 c = *reinterpret_cast<const float4*>(lcb + (rb ^ ((uint32_t)q4 << 4)));
+                                    const float cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+                                    for (int r = 0; r < 4; ++r) {
+                                        const float diff = x - cc[r];
+                                        d[4 * q4 + r] = fmaf(diff, diff, d[4 * q4 + r]);
+                                    }
                                 }
                             }
                         }
