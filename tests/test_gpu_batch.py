@@ -23,7 +23,9 @@ pytestmark = pytest.mark.gpu
 # (p, n, m, K, seed, ld_extra)
 SETS = [(128, 300, 13, 3, 1, 0), (256, 65, 26, 5, 2, 4), (512, 1, 51, 2, 3, 0), (1024, 1000, 102, 10, 4, 0),
         (2048, 200, 205, 7, 5, 0), (256, 0, 10, 3, 6, 0), (512, 777, 512, 4, 7, 0), (1024, 64, 1, 2, 8, 0),
-        (128, 129, 128, 1, 9, 0), (2048, 3000, 41, 37, 10, 8)]
+        (128, 129, 128, 1, 9, 0), (2048, 3000, 41, 37, 10, 8),
+        # one accumulation chunk of 9000 samples (listed 4096 at a time), a 32-cluster assignment window
+        (256, 9000, 13, 30, 11, 0)]
 
 
 @pytest.fixture(scope="module", autouse=True)
