@@ -1,10 +1,11 @@
 // Split-BF16 matrix-core transform for the split plan at p = 4096 (Sec. III,
 // eq. ROS): H_4096 = H_64 (x) H_64, so for the row-major 64 x 64 reshape X of
 // D x (X[r][c] = D_{64r+c} x_{64r+c}) the transform is Y = H_64 X H_64 with
-// Y[r][c] = y_{64r+c} (times 1/64).  Both factors are products on
+// Y[r][c] = y_{64r+c} (times 1/64, applied as 1/8 in each factor's +-1
+// entries).  Both factors are products on
 // v_mfma_f32_32x32x16_bf16 with FP32 accumulation:
 //   stage 1  Z = X H_64  (A operand: 8 consecutive values of a row of X,
-//            straight from memory; B operand: constant +-1 entries of H_64)
+//            straight from memory; B operand: constant +-1/8 entries of H_64)
 //   stage 2  Y = H_64 Z  (B operand: Z as it sits in stage 1's accumulator
 //            registers; the K index runs over Z's rows in the order those
 //            registers hold them, and the constant A operand H_64[r'][k] uses
@@ -46,9 +47,11 @@ __device__ inline void split3(const float (&v)[8], Parts8& hi, Parts8& mid, Part
     }
 }
 
-__device__ inline uint32_t hsign_bits(int a, int b)  // bf16 bits of H_64[a][b] (unnormalized +-1)
+// bf16 bits of H_64[a][b] / 8 (+-0.125): each stage carries half of the
+// transform's 1/64, which, a power of two, changes no rounding
+__device__ inline uint32_t hsign_bits(int a, int b)
 {
-    return (__popc(a & b) & 1) ? 0xBF80u : 0x3F80u;
+    return (__popc(a & b) & 1) ? 0xBE00u : 0x3E00u;
 }
 
 // stage-2 K order: logical slot (h, j) of K-block (rb, kk) is row
@@ -79,7 +82,7 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
     }
     __syncthreads();
 
-    // Constant +-1 operands.  Stage 1's B operand at (kb, cb) holds
+    // Constant +-1/8 operands.  Stage 1's B operand at (kb, cb) holds
     // H[16 kb + 8 h + j][32 cb + i32], j < 8; the row index splits into
     // disjoint bits 16 kb + 8 h and j, so the entry is the sign of
     // popc((16 kb + 8 h) & c) times the sign of popc(j & c): one 8-entry
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     const int e = 64 * (32 * rb2 + 8 * (v >> 2) + 4 * h + (v & 3)) + 32 * cb + i32;
-                    yb[lds_pad<float>(e)] = y[rb2][v] * (1.0f / 64.0f);
+                    yb[lds_pad<float>(e)] = y[rb2][v];
                 }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
