@@ -904,7 +904,8 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
         const bool stage = (size_t)kChunk * m * 2 <= (size_t)kPackStageBytes &&
                            pack_lds_bytes(g.geom.nbc) + kPackStageBytes <= (size_t)kLdsMax &&
                            (reinterpret_cast<uintptr_t>(idx) & 15) == 0;
-        const size_t lds = pack_lds_bytes(g.geom.nbc) + (stage ? (size_t)kPackStageBytes : 0);
+        // the staged rows take what they need (more workgroups per CU than a fixed 32 KB)
+        const size_t lds = pack_lds_bytes(g.geom.nbc) + (stage ? (((size_t)kChunk * m * 2 + 15) & ~(size_t)15) : 0);
         static bool pack_attr = false;
         if (!pack_attr) {
             (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<false>),
