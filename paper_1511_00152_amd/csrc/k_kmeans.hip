@@ -568,15 +568,11 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_kmeans_prep(const double* __restrict__ cin, int K, int p, int global,
                                                      T* __restrict__ cT, double* __restrict__ gsum,
                                                      uint32_t* __restrict__ gcnt, double* __restrict__ gsum_r,
-                                                     uint32_t* __restrict__ gcnt_r, uint32_t* __restrict__ rcount,
-                                                     uint32_t* __restrict__ vmax)
+                                                     uint32_t* __restrict__ gcnt_r, uint32_t* __restrict__ rcount)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t KP = (int64_t)K * p;
-    if (g == 0) {
-        *rcount = 0u;
-        *vmax = 0u;
-    }
+    if (g == 0) *rcount = 0u;
     if (g >= KP) return;
     gsum_r[g] = 0.0;
     gcnt_r[g] = 0u;
@@ -683,12 +679,12 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
     w += k.gsumr_bytes;
     uint32_t* gcnt_r = reinterpret_cast<uint32_t*>(w);
     w += k.gcntr_bytes;
-    uint32_t* vmax = reinterpret_cast<uint32_t*>(w);
+    uint32_t* vmax = reinterpret_cast<uint32_t*>(w);  // per-workgroup largest |value| (cooperative path)
     const int64_t KP = (int64_t)K * p;
     {
         ProfScope ps_("kmeans_prep", s);
         hipLaunchKernelGGL(k_kmeans_prep<T>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, cin, K, p,
-                           k.global ? 1 : 0, cT, gsum, gcnt, gsum_r, gcnt_r, rcount, vmax);
+                           k.global ? 1 : 0, cT, gsum, gcnt, gsum_r, gcnt_r, rcount);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
