@@ -31,7 +31,7 @@ def main(argv=None):
     ap.add_argument("--heldout", type=int, default=10000)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch-blocks", type=int, default=64, help="blocks per batched basis draw")
-    ap.add_argument("--out-dir", default="gpurun_out/msel")
+    ap.add_argument("--out-dir", default="msel_out")
     ap.add_argument("--install", action="store_true", help="write the trained weights into the package")
     ap.add_argument("--save-data", default=None, help="write the training features and labels (npz)")
     ap.add_argument("--load-data", default=None, help="train on features and labels from an npz instead")
