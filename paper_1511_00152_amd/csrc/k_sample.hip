@@ -5,8 +5,10 @@
 // Lemire's method on the sample's own Philox word stream, so the subset of
 // sample i is a function of (seed, i) only.
 //
-// One lane per sample.  The kept-set bitmaps of the wave's samples live in
-// LDS, word w of lane l at w * (spw + 1) + l: an odd stride, so both the
+// One lane per sample (with at most 32 samples per wave, the upper 32 lanes
+// evaluate every other Philox block for the lower ones).  The kept-set
+// bitmaps of the wave's samples live in LDS, word w of lane l at
+// w * (spw + 1) + l: an odd stride, so both the
 // Floyd loop (each lane at its own random word) and the emission below (the
 // lanes at consecutive words of one sample) spread over the LDS banks.
 // Emission is cooperative, one sample at a time: each lane takes a contiguous
@@ -35,7 +37,15 @@ __global__ __launch_bounds__(64) void k_sample_indices(uint64_t seed, int p, int
 
     for (int e = lane; e < words * stride; e += 64) bitmap[e] = 0u;
     __syncthreads();
-    if (lane < spw && r < n) floyd_bitmap(seed, i0 + (uint64_t)r, p, m, bitmap, stride, lane);
+    if (spw <= 32) {
+        // lane q + 32 evaluates every other Philox block for lane q's sample
+        const int q = lane & 31;
+        const int64_t rq = (int64_t)blockIdx.x * spw + q;
+        const bool owner = lane < 32 && q < spw && rq < n;
+        floyd_bitmap_pair(seed, i0 + (uint64_t)rq, p, m, bitmap, stride, q, owner);
+    } else if (lane < spw && r < n) {
+        floyd_bitmap(seed, i0 + (uint64_t)r, p, m, bitmap, stride, lane);
+    }
     __syncthreads();
 
     // cooperative, coalesced emission of each sample's ascending index row
