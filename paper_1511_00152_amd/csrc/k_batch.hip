@@ -102,7 +102,13 @@ __global__ __launch_bounds__(64) void k_batch_compress(const BatchSet* __restric
         const int64_t r0 = (g - gprefix[d]) * (int64_t)spw;
         const int64_t left = S.n - r0;
         const int nrows = left < spw ? (int)left : spw;
-        if (lane < nrows) floyd_bitmap(S.seed, (uint64_t)(r0 + lane), p, S.m, bitmap, stride, lane);
+        if (spw <= 32) {
+            // lane q + 32 evaluates every other Philox block for lane q's sample
+            const int q = lane & 31;
+            floyd_bitmap_pair(S.seed, (uint64_t)(r0 + q), p, S.m, bitmap, stride, q, lane < 32 && q < nrows);
+        } else if (lane < nrows) {
+            floyd_bitmap(S.seed, (uint64_t)(r0 + lane), p, S.m, bitmap, stride, lane);
+        }
         __syncthreads();
         switch (S.L) {
             case 7: batch_rows<7>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
