@@ -64,7 +64,7 @@ hipError_t launch_sample_indices(uint64_t seed, int p, int m, int64_t n, uint64_
     if (n <= 0) return hipSuccess;
     const int words = (p + 31) / 32;
     int spw = kSampleLdsBytes / (words * 4) - 1;
-    if (spw > 64) spw = 64;
+    if (spw > 32) spw = 32;  // lane pairs (at most 32 samples per wave)
     if (spw < 1) spw = 1;
     const size_t lds = (size_t)words * (spw + 1) * 4;
     const int64_t blocks = (n + spw - 1) / spw;
