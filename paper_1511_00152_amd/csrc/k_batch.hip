@@ -398,10 +398,20 @@ __global__ __launch_bounds__(kBaThreads) void k_batch_assign(const BatchSet* __r
         const int64_t j = it - aprefix[d];
         if (j == 0 && threadIdx.x == 0) cmax_next[d] = 0u;
         const float cmax = __uint_as_float(cmax_cur[d]);
-        // cluster window: the smallest of 8 / 16 / 32 covering K (32 for larger
-        // K) that fits all p coordinates in LDS
-        int kw = S.K <= 8 ? 8 : (S.K <= 16 ? 16 : 32);
-        while (kw > 8 && S.p * kw > kBaLdsFloats) kw >>= 1;
+        // cluster window of 8 / 16 / 32 (all p coordinates must fit in LDS):
+        // per kept entry a pass reads 4 KW bytes of centers and about 24 bytes'
+        // worth of sample data and bookkeeping, so take the fewest of
+        // ceil(K / KW) (4 KW + 24) (K = 40: three windows of 16, not two of 32)
+        int kw = 8;
+        int best_cost = ((S.K + 7) / 8) * (4 * 8 + 24);
+        for (int w = 16; w <= 32; w <<= 1) {
+            if (S.p * w > kBaLdsFloats) break;
+            const int cost = ((S.K + w - 1) / w) * (4 * w + 24);
+            if (cost <= best_cost) {
+                best_cost = cost;
+                kw = w;
+            }
+        }
         switch (kw) {
             case 8: batch_assign_item<8>(S, d, j, ct, cmax, vtile, itile, lc, dist, rlist, rcount); break;
             case 16: batch_assign_item<16>(S, d, j, ct, cmax, vtile, itile, lc, dist, rlist, rcount); break;
