@@ -428,6 +428,62 @@ void orc_kmeans_step(int64_t p, int64_t m, const double* vals, const uint16_t* i
     free(counts);
 }
 
+/* Two-pass sparsified K-means (Alg. "Sparsified K-means, 2-pass"): one pass
+ * over the original rows X (n x p) after the one-pass run, given its
+ * assignments c_hat and its centers mu_hat in the original domain.  Each row
+ * is added to the center of its one-pass cluster (the pseudocode's garbled
+ * increment is read as x_i), and is re-assigned to the nearest one-pass
+ * center in the original domain (FP64, ascending coordinate order, fma; ties
+ * to the lowest k).  A cluster with no rows keeps its one-pass center.
+ * margin[i] (optional): second smallest - smallest distance, +inf if K == 1. */
+void orc_kmeans_2pass(int64_t p, const double* X, int64_t n, int K, const int32_t* c_hat, const double* mu_hat,
+                      double* mu_out, int32_t* c_out, double* margin, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    /* re-assignment to the nearest one-pass center */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const double* x = X + i * p;
+        int best = 0;
+        double dbest = INFINITY, dsecond = INFINITY;
+        for (int k = 0; k < K; ++k) {
+            const double* mu = mu_hat + (int64_t)k * p;
+            double d = 0.0;
+            for (int64_t j = 0; j < p; ++j) {
+                const double diff = x[j] - mu[j];
+                d = fma(diff, diff, d);
+            }
+            if (d < dbest) {
+                dsecond = dbest;
+                dbest = d;
+                best = k;
+            } else if (d < dsecond) {
+                dsecond = d;
+            }
+        }
+        c_out[i] = best;
+        if (margin) margin[i] = dsecond - dbest;
+    }
+    /* centers: mean of the rows of each one-pass cluster */
+    double* sums = (double*)calloc((size_t)K * (size_t)p, sizeof(double));
+    int64_t* counts = (int64_t*)calloc((size_t)K, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        const int k = c_hat[i];
+        counts[k] += 1;
+        for (int64_t j = 0; j < p; ++j) sums[(int64_t)k * p + j] += X[i * p + j];
+    }
+    for (int k = 0; k < K; ++k)
+        for (int64_t j = 0; j < p; ++j)
+            mu_out[(int64_t)k * p + j] =
+                counts[k] > 0 ? sums[(int64_t)k * p + j] / (double)counts[k] : mu_hat[(int64_t)k * p + j];
+    free(sums);
+    free(counts);
+}
+
 /* Unmixing (eq. mu-mu'): mu = (HD)^T mu' = D H mu' since H is symmetric. */
 void orc_unmix(uint64_t seed, int64_t p, const double* centers_pre, int K, double* centers_out)
 {

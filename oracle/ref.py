@@ -31,6 +31,11 @@ Functions and the passages they follow (paper = arXiv 1511.00152):
   a reading.
 * ``y_entry`` -- one entry of H D x from the definition (row of H times D x).
 * ``mean_estimate`` -- Thm. "sampleMean"; pinned by enumeration (unbiased).
+* ``kmeans_2pass`` -- Alg. "Sparsified K-means, 2-pass": one pass over the
+  original rows after the one-pass run; pinned against per-label means
+  (``numpy.add.at``) and nearest centers (``scipy.spatial.distance.cdist``),
+  by the Lloyd fixed point (converged assignments and centers come back
+  unchanged) and by the empty-cluster rule.
 """
 import ctypes
 import os
@@ -72,6 +77,7 @@ def lib():
         L.orc_unmix.argtypes = [u64, i64, P, i32, P]
         L.orc_kmeanspp.argtypes = [u64, i64, i64, P, P, i64, i32, P, P]
         L.orc_mean_estimate.argtypes = [i64, i64, P, P, i64, P]
+        L.orc_kmeans_2pass.argtypes = [i64, P, i64, i32, P, P, P, P, P, i32]
         L.orc_max_threads.restype = i32
         L.orc_sample_batch.argtypes = [u64, u64, i64, i64, i64, P, i32]
         L.orc_sample_words_used.argtypes = [u64, u64, i64, i64]
@@ -230,6 +236,20 @@ def kmeanspp(seed: int, p: int, vals, idx, K: int):
     chosen = np.zeros(K, dtype=np.int64)
     lib().orc_kmeanspp(seed, p, m, _ptr(vals), _ptr(idx), n, K, _ptr(centers), _ptr(chosen))
     return centers, chosen
+
+
+def kmeans_2pass(X, c_hat, mu_hat, nthreads: int = 0):
+    """Returns (centers float64 K x p, assign int32 n, margin float64 n)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    c_hat = np.ascontiguousarray(c_hat, dtype=np.int32)
+    mu_hat = np.ascontiguousarray(mu_hat, dtype=np.float64)
+    n, p = X.shape
+    K = mu_hat.shape[0]
+    mu = np.zeros_like(mu_hat)
+    c = np.zeros(n, dtype=np.int32)
+    margin = np.zeros(n, dtype=np.float64)
+    lib().orc_kmeans_2pass(p, _ptr(X), n, K, _ptr(c_hat), _ptr(mu_hat), _ptr(mu), _ptr(c), _ptr(margin), nthreads)
+    return mu, c, margin
 
 
 def mean_estimate(p: int, vals, idx):

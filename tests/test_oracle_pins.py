@@ -426,6 +426,61 @@ def test_unmix_matches_literal_oracle():
     assert np.max(np.abs(ref.unmix(6, c) - oracle_def.unmix(6, c.T).T)) < 1e-13
 
 
+# ------------------------------------------------------- 2-pass K-means --
+def test_kmeans2pass_centers_are_one_pass_cluster_means():
+    """Alg. "Sparsified K-means, 2-pass": each center is the mean of the
+    original rows of its one-pass cluster (numpy.add.at), and a cluster with
+    no rows keeps its one-pass center."""
+    rng = np.random.default_rng(21)
+    n, p, K = 400, 16, 5
+    X = rng.standard_normal((n, p))
+    c_hat = rng.integers(0, K - 1, n).astype(np.int32)  # cluster K - 1 stays empty
+    mu_hat = rng.standard_normal((K, p))
+    mu, _, _ = ref.kmeans_2pass(X, c_hat, mu_hat)
+    sums = np.zeros((K, p))
+    np.add.at(sums, c_hat, X)
+    cnt = np.bincount(c_hat, minlength=K).astype(np.float64)
+    for k in range(K - 1):
+        assert np.allclose(mu[k], sums[k] / cnt[k], rtol=1e-13, atol=1e-15)
+    assert np.array_equal(mu[K - 1], mu_hat[K - 1])
+
+
+def test_kmeans2pass_reassigns_to_nearest_one_pass_center():
+    """The second pass assigns every row to its nearest one-pass center in the
+    original domain (scipy's cdist), ties to the lowest index."""
+    import scipy.spatial.distance as ssd
+    rng = np.random.default_rng(22)
+    n, p, K = 300, 12, 6
+    X = rng.standard_normal((n, p))
+    mu_hat = rng.standard_normal((K, p))
+    mu_hat[4] = mu_hat[1]  # an exact tie: index 1 wins
+    _, c, margin = ref.kmeans_2pass(X, np.zeros(n, np.int32), mu_hat)
+    D = ssd.cdist(X, mu_hat, "sqeuclidean")
+    assert np.array_equal(c, np.argmin(D, axis=1).astype(np.int32))
+    assert not np.any(c == 4)
+    Ds = np.sort(D, axis=1)
+    assert np.allclose(margin, Ds[:, 1] - Ds[:, 0], atol=1e-12)
+
+
+def test_kmeans2pass_lloyd_fixed_point():
+    """At a converged Lloyd state on the original rows (a brute-force loop),
+    the two-pass step returns the same assignments and centers."""
+    rng = np.random.default_rng(23)
+    K, p, per = 4, 10, 60
+    means = rng.standard_normal((K, p)) * 6.0
+    X = np.concatenate([means[k] + rng.standard_normal((per, p)) for k in range(K)])
+    mu = X[rng.choice(len(X), K, replace=False)].copy()
+    for _ in range(100):
+        lab = np.argmin(((X[:, None, :] - mu[None]) ** 2).sum(-1), axis=1)
+        new = np.array([X[lab == k].mean(0) if np.any(lab == k) else mu[k] for k in range(K)])
+        if np.array_equal(new, mu):
+            break
+        mu = new
+    mu2, c2, _ = ref.kmeans_2pass(X, lab.astype(np.int32), mu)
+    assert np.array_equal(c2, lab)
+    assert np.allclose(mu2, mu, rtol=1e-13, atol=1e-13)
+
+
 def test_kmeanspp_picks_distinct_samples():
     p, n, m, K = 64, 200, 10, 6
     X = np.random.default_rng(15).standard_normal((n, p))
