@@ -63,7 +63,7 @@ typedef enum {
 typedef enum { PDS_F64 = 0, PDS_F32 = 1, PDS_SPLIT_BF16 = 2 } pds_prec;
 
 /* Operation selector for pds_workspace_size. */
-typedef enum { PDS_OP_COMPRESS = 0, PDS_OP_COVARIANCE = 1, PDS_OP_KMEANS = 2 } pds_op;
+typedef enum { PDS_OP_COMPRESS = 0, PDS_OP_COVARIANCE = 1, PDS_OP_KMEANS = 2, PDS_OP_KMEANS2 = 3 } pds_op;
 
 typedef struct pds_plan_s* pds_plan;
 
@@ -86,7 +86,7 @@ pds_status pds_plan_destroy(pds_plan plan);
 pds_status pds_signs(pds_plan plan, int8_t* D_host);
 
 /* Device workspace bytes that `op` needs for n samples (and K clusters for
- * PDS_OP_KMEANS); PDS_OP_COVARIANCE also reports what its accumulator needs
+ * PDS_OP_KMEANS and PDS_OP_KMEANS2); PDS_OP_COVARIANCE also reports what its accumulator needs
  * through pds_covariance_acc_size.  Host-only. */
 pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, size_t* bytes);
 
@@ -162,6 +162,27 @@ pds_status pds_kmeans_step(pds_plan plan, const void* vals, const uint16_t* idx,
  * centers_pre / centers_out: device, K x p doubles (may not alias).
  * Errors: PDS_E_ARG (null pointers, K < 1). */
 pds_status pds_unmix(pds_plan plan, const double* centers_pre, int32_t K, double* centers_out, void* stream);
+
+/* Second pass of two-pass sparsified K-means (Alg. "Sparsified K-means,
+ * 2-pass"), one more pass over the original rows after the one-pass run:
+ *   c_out[i]  = argmin_k sum_j (X[i][j] - mu_hat[k][j])^2 over all p
+ *               coordinates, ties to the lowest k (FP32 plans: FP32 distances,
+ *               rows closer to a tie than a rounding bound decided in FP64 in
+ *               ascending coordinate order, so the result is the FP64 argmin);
+ *   mu_out[k] = mean of the rows X[i] with c_hat[i] == k; a cluster with no
+ *               rows keeps mu_hat[k].  Rows with c_hat outside [0, K) count
+ *               for no center.
+ * X: device, n x p row-major with leading dimension ldx >= p, FP64 for FP64
+ * plans, FP32 otherwise (the original, not preconditioned, data).
+ * c_hat: device, n int32, the one-pass assignments.  mu_hat: device, K x p
+ * doubles, the one-pass centers in the original domain (pds_unmix output).
+ * mu_out: device, K x p doubles (must not alias mu_hat).  c_out: device, n
+ * int32.  ws: device, >= pds_workspace_size(KMEANS2, n, K).
+ * Errors: PDS_E_ARG (null pointers with n > 0, n < 0, ldx < p, K < 1 or
+ * K > 1024, aliasing), PDS_E_WORKSPACE. */
+pds_status pds_kmeans_2pass(pds_plan plan, const void* X, int64_t n, int64_t ldx, int32_t K, const int32_t* c_hat,
+                            const double* mu_hat, double* mu_out, int32_t* c_out, void* ws, size_t ws_bytes,
+                            void* stream);
 
 /* ---------------------------------------------------------------------------
  * Learned m-selector.  Not part of the paper's method: a small model that

@@ -13,11 +13,11 @@ the current HIP device; every call enqueues the library's kernels on
 import ctypes
 
 from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_F32, PDS_F64,
-                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_SPLIT_BF16, EXPORTS, PdsError,
+                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_SPLIT_BF16, EXPORTS, PdsError,
                    check, lib)
 
 __all__ = [
-    "Plan", "compress", "covariance", "CovarianceAccumulator", "kmeans_step", "unmix", "sparsified_kmeans",
+    "Plan", "compress", "covariance", "CovarianceAccumulator", "kmeans_step", "unmix", "kmeans_2pass", "sparsified_kmeans",
     "top_eigenvalues",
     "PdsError", "PDS_F64", "PDS_F32", "PDS_SPLIT_BF16", "lib", "EXPORTS",
 ]
@@ -206,6 +206,28 @@ def unmix(plan: Plan, centers_pre, out=None):
         out = torch.empty_like(centers_pre)
     check(lib().pds_unmix(plan.handle, _ptr(centers_pre), centers_pre.shape[0], _ptr(out), _stream()), "pds_unmix")
     return out
+
+
+def kmeans_2pass(plan: Plan, X, c_hat, mu_hat, out=None, assign=None, ws=None):
+    """Second pass of two-pass sparsified K-means over the original rows X
+    (n x p; FP64 for FP64 plans, FP32 otherwise): returns (centers K x p FP64,
+    the means of the rows of each one-pass cluster c_hat; assign int32, the
+    nearest one-pass center mu_hat in the original domain)."""
+    import torch
+
+    n, p = X.shape
+    K = mu_hat.shape[0]
+    dev = X.device
+    if out is None:
+        out = torch.empty_like(mu_hat)
+    if assign is None:
+        assign = torch.empty(n, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = plan.workspace(PDS_OP_KMEANS2, n, K, device=dev)
+    check(lib().pds_kmeans_2pass(plan.handle, _ptr(X), n, X.stride(0), K, _ptr(c_hat), _ptr(mu_hat), _ptr(out),
+                                 _ptr(assign), _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
+          "pds_kmeans_2pass")
+    return out, assign
 
 
 def sparsified_kmeans(plan: Plan, X, init_centers, iterations: int):

@@ -205,6 +205,10 @@ pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, s
             if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
             *bytes = pds::kmeans_workspace(plan->prec, p, m, n, K, dev);
             return PDS_OK;
+        case PDS_OP_KMEANS2:
+            if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
+            *bytes = pds::kmeans2_workspace(plan->prec, p, n, K, dev);
+            return PDS_OK;
         default:
             return fail(PDS_E_ARG, "unknown op %d", (int)op);
     }
@@ -291,6 +295,31 @@ pds_status pds_kmeans_step(pds_plan plan, const void* vals, const uint16_t* idx,
     e = pds::launch_kmeans_step(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, K, centers_in, centers_out,
                                 assign, objective, ws, ws_bytes, dev, s);
     if (e != hipSuccess) return hip_fail(e, "kmeans_step");
+    return PDS_OK;
+}
+
+pds_status pds_kmeans_2pass(pds_plan plan, const void* X, int64_t n, int64_t ldx, int32_t K, const int32_t* c_hat,
+                            const double* mu_hat, double* mu_out, int32_t* c_out, void* ws, size_t ws_bytes,
+                            void* stream)
+{
+    if (pds_status st = check_plan(plan)) return st;
+    if (n < 0) return fail(PDS_E_ARG, "n < 0");
+    if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
+    if (!pds::kmeans2_supported(K)) return fail(PDS_E_ARG, "K = %d: too many clusters for the second pass", (int)K);
+    if (n == 0) return PDS_OK;
+    if (!X || !c_hat || !mu_hat || !mu_out || !c_out)
+        return fail(PDS_E_ARG, "X, c_hat, mu_hat, mu_out and c_out must be non-NULL");
+    if (ldx < plan->p) return fail(PDS_E_ARG, "ldx = %lld < p = %lld", (long long)ldx, (long long)plan->p);
+    if (mu_hat == mu_out) return fail(PDS_E_ARG, "mu_hat and mu_out must not alias");
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_kmeans_2pass");
+    const size_t need = pds::kmeans2_workspace(plan->prec, (int)plan->p, n, K, dev);
+    if (!ws || ws_bytes < need)
+        return fail(PDS_E_WORKSPACE, "kmeans_2pass needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
+    e = pds::launch_kmeans_2pass(plan->prec, (int)plan->p, X, n, ldx, K, c_hat, mu_hat, mu_out, c_out, ws, ws_bytes,
+                                 dev, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kmeans_2pass");
     return PDS_OK;
 }
 

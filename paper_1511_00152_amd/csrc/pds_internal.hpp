@@ -57,6 +57,13 @@ hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const ui
                               const double* cin, double* cout, int32_t* assign, double* objective, void* ws,
                               size_t ws_bytes, const DeviceInfo& dev, hipStream_t s);
 
+// ---- two-pass K-means -------------------------------------------------------
+size_t kmeans2_workspace(int prec, int p, int64_t n, int K, const DeviceInfo& dev);
+bool kmeans2_supported(int K);
+hipError_t launch_kmeans_2pass(int prec, int p, const void* X, int64_t n, int64_t ldx, int K, const int32_t* c_hat,
+                               const double* mu_hat, double* mu_out, int32_t* c_out, void* ws, size_t ws_bytes,
+                               const DeviceInfo& dev, hipStream_t s);
+
 // ---- unmix ------------------------------------------------------------------
 hipError_t launch_unmix(uint64_t seed, int p, const double* cpre, int K, double* cout, hipStream_t s);
 

@@ -214,6 +214,86 @@ def test_kmeans_step_matches_oracle(p, m, n, K, prec):
     assert abs(J.item() - J_o) <= tol * J_o
 
 
+# (p, n, K, prec, ld_extra): ragged row counts, ldx > p, one cluster window and several, K > 64
+KM2_SHAPES = [(256, 2000, 5, "f64", 0), (1024, 3001, 10, "f32", 0), (64, 777, 3, "split", 4), (4096, 300, 20, "f32", 0),
+              (128, 513, 37, "f32", 8), (8, 100, 2, "f64", 0), (512, 1500, 100, "f32", 0), (2, 50, 1, "f32", 0)]
+
+
+@pytest.mark.parametrize("p,n,K,prec,ld_extra", KM2_SHAPES)
+def test_kmeans_2pass_matches_oracle(p, n, K, prec, ld_extra):
+    """Second pass of two-pass K-means against the oracle on the same X, one-pass
+    assignments (one cluster left empty when K > 2) and centers: assignments
+    bit-exact, centers to the FP64 tolerance."""
+    pr, dt, _, _ = PRECS[prec]
+    log(f"kmeans 2-pass p={p} n={n} K={K} prec={prec}")
+    rng = np.random.default_rng([p, n, K])
+    means = rng.standard_normal((K, p)) * 2.0
+    X = (means[rng.integers(0, K, n)] + rng.standard_normal((n, p))).astype(dt)
+    Xl = np.zeros((n, p + ld_extra), dtype=dt)
+    Xl[:, :p] = X
+    c_hat = rng.integers(0, max(K - 1, 1), n).astype(np.int32) if K > 2 else rng.integers(0, K, n).astype(np.int32)
+    mu_hat = means + 0.1 * rng.standard_normal((K, p))
+    plan = pds.Plan(p, max(1, p // 10), prec=pr)
+    mu, c = pds.kmeans_2pass(plan, to_dev(Xl)[:, :p], to_dev(c_hat), to_dev(mu_hat))
+    torch.cuda.synchronize()
+    mu_o, c_o, _ = ref.kmeans_2pass(X.astype(np.float64), c_hat, mu_hat)
+    cg = c.cpu().numpy()
+    assert np.array_equal(cg, c_o), np.nonzero(cg != c_o)[0][:10]
+    assert nerr(mu.cpu().numpy(), mu_o) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_kmeans_2pass_near_ties_resolved_in_fp64(prec):
+    """One-pass centers 1e-9 apart and an exact duplicate: the FP64 recheck
+    gives the oracle's argmin, duplicates go to the lower index."""
+    pr, dt, _, _ = PRECS[prec]
+    p, n, K = 256, 3000, 4
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((n, p)).astype(dt)
+    mu_hat = rng.standard_normal((K, p)) * 0.5
+    mu_hat[1] = mu_hat[0]
+    mu_hat[1, 3] += 1e-9
+    mu_hat[3] = mu_hat[2]
+    c_hat = rng.integers(0, K, n).astype(np.int32)
+    plan = pds.Plan(p, 26, prec=pr)
+    _, c = pds.kmeans_2pass(plan, to_dev(X), to_dev(c_hat), to_dev(mu_hat))
+    torch.cuda.synchronize()
+    _, c_o, margin = ref.kmeans_2pass(X.astype(np.float64), c_hat, mu_hat)
+    cg = c.cpu().numpy()
+    assert np.sum(margin < 1e-6) > 0  # the case does exercise near ties
+    assert np.array_equal(cg, c_o)
+    assert not np.any(cg == 3)
+
+
+def test_kmeans_2pass_after_one_pass_pipeline():
+    """Alg. 2 on the mixture workload's shape: the oracle's own one-pass run
+    gives (c_hat, mu_hat); the GPU second pass equals the oracle's."""
+    w = synth.WORKLOADS["mixture_f32"]
+    p, K = w["p"], w["K"]
+    m = synth.m_from_gamma(w["gamma"], p)
+    n = 6000
+    X = synth.rows_numpy("mixture_f32", n).astype(np.float32)
+    one = ref.sparsified_kmeans(X, 0, m, K, 5)
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F32)
+    mu, c = pds.kmeans_2pass(plan, to_dev(X), to_dev(one["assign"].astype(np.int32)), to_dev(one["centers"]))
+    torch.cuda.synchronize()
+    mu_o, c_o, _ = ref.kmeans_2pass(X.astype(np.float64), one["assign"], one["centers"])
+    assert np.array_equal(c.cpu().numpy(), c_o)
+    assert nerr(mu.cpu().numpy(), mu_o) <= 1e-12
+
+
+def test_kmeans_2pass_argument_errors():
+    plan = pds.Plan(64, 8, prec=pds.PDS_F32)
+    X = torch.zeros((10, 64), dtype=torch.float32, device="cuda")
+    c = torch.zeros(10, dtype=torch.int32, device="cuda")
+    mu = torch.zeros((3, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(pds.PdsError):
+        pds.kmeans_2pass(plan, X, c, mu, out=mu)  # aliasing
+    with pytest.raises(pds.PdsError):
+        X32 = torch.zeros((10, 32), dtype=torch.float32, device="cuda")
+        pds.kmeans_2pass(plan, X32, c, mu)  # ldx = 32 < p = 64
+
+
 @pytest.mark.parametrize("prec", ["f32", "split"])
 def test_kmeans_near_ties_resolved_in_fp64(prec):
     """Centers that differ by ~1e-9 relative in one coordinate: FP32 distances
