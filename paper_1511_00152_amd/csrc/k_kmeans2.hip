@@ -7,8 +7,9 @@
 // Three launches:
 //   prep    FP32 copy of mu_hat (FP32 plans) and the largest |center| entry,
 //           the scale of the near-tie bound
-//   assign  one wave per row: lanes over coordinates, clusters in windows of
-//           16 with per-lane partial distances, then wave sums; a row whose two
+//   assign  sixteen lanes per row: lanes over coordinates, clusters in
+//           windows of 16 with per-lane partial distances, then sums across
+//           the sixteen lanes (centers in LDS when they fit); a row whose two
 //           best distances are closer than the rounding bound is decided again
 //           in FP64 with every lane summing one cluster's distance in ascending
 //           coordinate order (the oracle's order, ties to the lowest index)
@@ -25,7 +26,8 @@ namespace pds {
 
 constexpr int kK2Window = 16;          // clusters per assignment window
 constexpr int kK2SumLds = 131072;      // LDS bytes of the per-column cluster sums (the K counts come on top)
-constexpr int kK2AssignThreads = 256;  // four rows at a time per workgroup
+constexpr int kK2AssignThreads = 256;  // sixteen rows at a time per workgroup
+constexpr int kK2CenterLds = 65536;    // centers in LDS up to this size (else read from memory)
 
 template <typename T>
 struct K2Center;  // center element type of the assignment
@@ -67,8 +69,12 @@ __device__ inline T wave_sum(T v)
     return v;
 }
 
-// Nearest one-pass center of each row.
-template <typename T>
+// Nearest one-pass center of each row: sixteen lanes per row (four rows per
+// wave), each lane over every sixteenth coordinate, clusters in windows of 16
+// with per-lane partial distances summed across the sixteen lanes (xor
+// butterflies, every lane gets the totals).  With LDS set, the centers sit in
+// LDS (the four rows of a wave read the same words: broadcasts).
+template <typename T, bool LDS>
 __global__ __launch_bounds__(kK2AssignThreads) void k_km2_assign(const T* __restrict__ X, int64_t n, int64_t ldx,
                                                                  int p, int K,
                                                                  const typename K2Center<T>::type* __restrict__ ct,
@@ -76,12 +82,22 @@ __global__ __launch_bounds__(kK2AssignThreads) void k_km2_assign(const T* __rest
                                                                  const uint32_t* __restrict__ cmax_bits,
                                                                  int32_t* __restrict__ c_out)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * (kK2AssignThreads / 64);
+    using C = typename K2Center<T>::type;
+    extern __shared__ __align__(16) unsigned char k2_smem[];
+    const C* cs = ct;
+    if constexpr (LDS) {
+        C* l = reinterpret_cast<C*>(k2_smem);
+        for (int64_t e = threadIdx.x; e < (int64_t)K * p; e += kK2AssignThreads) l[e] = ct[e];
+        __syncthreads();
+        cs = l;
+    }
+    const int sl = threadIdx.x & 15;
+    constexpr int kRows = kK2AssignThreads / 16;
+    const int64_t nr = (int64_t)gridDim.x * kRows;
     const T cmax = (T)__uint_as_float(*cmax_bits);
     // unit roundoff of the distance arithmetic
     const T u = sizeof(T) == 4 ? (T)5.9604645e-8 : (T)1.1102230246251565e-16;
-    for (int64_t i = (int64_t)blockIdx.x * (kK2AssignThreads / 64) + (threadIdx.x >> 6); i < n; i += nw) {
+    for (int64_t i = (int64_t)blockIdx.x * kRows + (threadIdx.x >> 4); i < n; i += nr) {
         const T* x = X + i * ldx;
         T best = (T)INFINITY, second = (T)INFINITY, sx = 0;
         int bestk = 0;
@@ -89,21 +105,37 @@ __global__ __launch_bounds__(kK2AssignThreads) void k_km2_assign(const T* __rest
             T d[kK2Window];
 #pragma unroll
             for (int q = 0; q < kK2Window; ++q) d[q] = 0;
-            for (int j = lane; j < p; j += 64) {
-                const T v = x[j];
-                if (kc == 0) sx = fma(v, v, sx);
+            // 256 coordinates of the row at a time: the lane's sixteen loads
+            // are issued together, then used
+            for (int j0 = 0; j0 < p; j0 += 256) {
+                T xb[16];
 #pragma unroll
-                for (int q = 0; q < kK2Window; ++q) {
-                    if (kc + q < K) {
-                        const T diff = v - (T)ct[(int64_t)(kc + q) * p + j];
-                        d[q] = fma(diff, diff, d[q]);
+                for (int u = 0; u < 16; ++u) {
+                    const int j = j0 + sl + 16 * u;
+                    xb[u] = j < p ? x[j] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int j = j0 + sl + 16 * u;
+                    if (j < p) {
+                        const T v = xb[u];
+                        if (kc == 0) sx = fma(v, v, sx);
+#pragma unroll
+                        for (int q = 0; q < kK2Window; ++q) {
+                            if (kc + q < K) {
+                                const T diff = v - (T)cs[(int64_t)(kc + q) * p + j];
+                                d[q] = fma(diff, diff, d[q]);
+                            }
+                        }
                     }
                 }
             }
 #pragma unroll
             for (int q = 0; q < kK2Window; ++q) {
                 if (kc + q < K) {
-                    const T dq = wave_sum(d[q]);
+                    T dq = d[q];
+#pragma unroll
+                    for (int off = 8; off > 0; off >>= 1) dq += __shfl_xor(dq, off, 16);
                     if (dq < best) {
                         second = best;
                         best = dq;
@@ -114,7 +146,8 @@ __global__ __launch_bounds__(kK2AssignThreads) void k_km2_assign(const T* __rest
                 }
             }
         }
-        sx = wave_sum(sx);
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) sx += __shfl_xor(sx, off, 16);
         bool flag = false;
         if (K > 1) {
             // |d - d_exact| <= u (8 (sum x^2 + p max|mu|^2) + 1.01 p d) per
@@ -125,10 +158,11 @@ __global__ __launch_bounds__(kK2AssignThreads) void k_km2_assign(const T* __rest
             flag = !(second - best > bound);
         }
         if (flag) {
-            // FP64, one cluster per lane, ascending coordinates (the oracle's sums)
+            // FP64, one cluster per lane of the row, ascending coordinates (the
+            // oracle's sums), ties to the lowest index
             double bd = INFINITY;
             int bk = 0x7fffffff;
-            for (int k = lane; k < K; k += 64) {
+            for (int k = sl; k < K; k += 16) {
                 const double* mu = mu_hat + (int64_t)k * p;
                 double dd = 0.0;
                 for (int j = 0; j < p; ++j) {
@@ -141,9 +175,9 @@ __global__ __launch_bounds__(kK2AssignThreads) void k_km2_assign(const T* __rest
                 }
             }
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double od = __shfl_xor(bd, off, 64);
-                const int ok = __shfl_xor(bk, off, 64);
+            for (int off = 8; off > 0; off >>= 1) {
+                const double od = __shfl_xor(bd, off, 16);
+                const int ok = __shfl_xor(bk, off, 16);
                 if (od < bd || (od == bd && ok < bk)) {
                     bd = od;
                     bk = ok;
@@ -151,7 +185,7 @@ __global__ __launch_bounds__(kK2AssignThreads) void k_km2_assign(const T* __rest
             }
             bestk = bk;
         }
-        if (lane == 0) c_out[i] = bestk;
+        if (sl == 0) c_out[i] = bestk;
     }
 }
 
@@ -288,14 +322,36 @@ hipError_t launch_kmeans_2pass(int prec, int p, const void* X, int64_t n, int64_
     if (e != hipSuccess) return e;
     {
         ProfScope ps_("km2_assign", s);
-        int64_t grid = (n + 3) / 4;
+        int64_t grid = (n + 15) / 16;
         if (grid > (int64_t)dev.cus * 8) grid = (int64_t)dev.cus * 8;
-        if (prec == 0)
-            hipLaunchKernelGGL(k_km2_assign<double>, dim3((unsigned)grid), dim3(kK2AssignThreads), 0, s,
-                               reinterpret_cast<const double*>(X), n, ldx, p, K, mu_hat, mu_hat, cmax, c_out);
-        else
-            hipLaunchKernelGGL(k_km2_assign<float>, dim3((unsigned)grid), dim3(kK2AssignThreads), 0, s,
-                               reinterpret_cast<const float*>(X), n, ldx, p, K, ct, mu_hat, cmax, c_out);
+        const size_t ce = prec == 0 ? 8 : 4;
+        const size_t clds = (size_t)KP * ce;
+        const bool lds = clds <= (size_t)kK2CenterLds;
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_km2_assign<double, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kK2CenterLds);
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_km2_assign<float, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kK2CenterLds);
+            attr = true;
+        }
+        if (prec == 0) {
+            const double* Xd = reinterpret_cast<const double*>(X);
+            if (lds)
+                hipLaunchKernelGGL((k_km2_assign<double, true>), dim3((unsigned)grid), dim3(kK2AssignThreads), clds,
+                                   s, Xd, n, ldx, p, K, mu_hat, mu_hat, cmax, c_out);
+            else
+                hipLaunchKernelGGL((k_km2_assign<double, false>), dim3((unsigned)grid), dim3(kK2AssignThreads), 0, s,
+                                   Xd, n, ldx, p, K, mu_hat, mu_hat, cmax, c_out);
+        } else {
+            const float* Xf = reinterpret_cast<const float*>(X);
+            if (lds)
+                hipLaunchKernelGGL((k_km2_assign<float, true>), dim3((unsigned)grid), dim3(kK2AssignThreads), clds, s,
+                                   Xf, n, ldx, p, K, ct, mu_hat, cmax, c_out);
+            else
+                hipLaunchKernelGGL((k_km2_assign<float, false>), dim3((unsigned)grid), dim3(kK2AssignThreads), 0, s,
+                                   Xf, n, ldx, p, K, ct, mu_hat, cmax, c_out);
+        }
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
