@@ -359,6 +359,33 @@ def run_mixture(pds, steps, warmup):
     }
 
 
+def run_mean(pds, r, n, p, m, steps):
+    """The sample-mean estimator (Sec. IV) over the kept entries of the step
+    just timed, timed on its own (not part of the step): per-kernel times from
+    the library's event timing."""
+    import torch
+
+    plan, vals, idx = r["plan"], r["vals"], r["idx"]
+    ws = plan.workspace(pds.PDS_OP_MEAN, n, device=vals.device)
+    acc = torch.zeros(p, dtype=torch.float64, device=vals.device)
+    mean = torch.empty_like(acc)
+    pds.sample_mean(plan, vals, idx, acc=acc, out=mean, ws=ws)
+    torch.cuda.synchronize()
+    lib = pds.lib()
+    lib.pds_profile_enable(1)
+    for _ in range(steps):
+        acc.zero_()
+        pds.sample_mean(plan, vals, idx, acc=acc, out=mean, ws=ws)
+    torch.cuda.synchronize()
+    lib.pds_profile_enable(0)
+    kern = profile_report(lib)
+    t = kern["mean_partial"]["avg_ms"] + kern["mean_reduce"]["avg_ms"]
+    alg = n * m * (vals.element_size() + 2)  # each kept value and index read once
+    return {"what": f"sample-mean estimate over the {n} x {m} kept entries, not part of the step",
+            "ms": t, "algorithmic_gb": alg / 1e9, "frac_hbm": alg / (t / 1e3) / 1e9 / PEAK_HBM_GBS,
+            "kernels_ms": {k: d["avg_ms"] for k, d in kern.items()}}
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the FETCH_SIZE /
     WRITE_SIZE counters of a profiled run."""
@@ -468,6 +495,8 @@ def main():
         torch.cuda.synchronize()
         out["eigen"] = {"ms": e0.elapsed_time(e1), "what": f"top 20 eigenvalues of the {p}x{p} FP64 estimate "
                         "(device symmetric eigensolver), not part of the step", "largest": float(ev_top[0])}
+    out["sample_mean"] = run_mean(pds, res[head], n, p, m, max(1, min(args.steps, 10)))
+    log(f"sample_mean: {json.dumps(out['sample_mean'])}")
     for v in res.values():
         v.pop("vals", None), v.pop("idx", None), v.pop("C", None)
     if not args.no_cpu_baseline:

@@ -63,7 +63,13 @@ typedef enum {
 typedef enum { PDS_F64 = 0, PDS_F32 = 1, PDS_SPLIT_BF16 = 2 } pds_prec;
 
 /* Operation selector for pds_workspace_size. */
-typedef enum { PDS_OP_COMPRESS = 0, PDS_OP_COVARIANCE = 1, PDS_OP_KMEANS = 2, PDS_OP_KMEANS2 = 3 } pds_op;
+typedef enum {
+    PDS_OP_COMPRESS = 0,
+    PDS_OP_COVARIANCE = 1,
+    PDS_OP_KMEANS = 2,
+    PDS_OP_KMEANS2 = 3,
+    PDS_OP_MEAN = 4
+} pds_op;
 
 typedef struct pds_plan_s* pds_plan;
 
@@ -136,6 +142,26 @@ pds_status pds_compress(pds_plan plan, const void* X, int64_t n, int64_t ldx, ui
 pds_status pds_covariance(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, double* acc,
                           int32_t finalize, int64_t n_total, double* C_out, void* ws, size_t ws_bytes,
                           void* stream);
+
+/* Sample-mean estimator of Sec. IV (Thm. "sampleMean") on compressed data,
+ * streamed:
+ *   acc += sum over the n given samples of w_i (w_i = the zero-filled
+ *          compressed sample), per coordinate, in FP64.  acc: device, p
+ *          doubles, caller-owned, zeroed by the caller before the first batch.
+ *   if finalize != 0, mean_out (device, p doubles) receives
+ *          (p / (m n_total)) * acc, unbiased for the mean of the y_i over all
+ *          n_total samples.  It is in the preconditioned domain: pds_unmix
+ *          with K = 1 maps it back to the mean of the x_i.
+ * vals / idx as written by pds_compress (n x m; FP64 values for PDS_F64
+ * plans, FP32 otherwise; indices < p).  Sums inside a work-group are added in
+ * no fixed order, so the last bits may differ from run to run.
+ * n may be 0 (finalize only).  ws: device, >= pds_workspace_size(MEAN, n)
+ * (p doubles per sample range, about 4 ranges per compute unit).
+ * Errors: PDS_E_ARG (null pointers, n < 0, finalize with n_total < 1,
+ * mean_out aliasing acc), PDS_E_WORKSPACE. */
+pds_status pds_sample_mean(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, double* acc,
+                           int32_t finalize, int64_t n_total, double* mean_out, void* ws, size_t ws_bytes,
+                           void* stream);
 
 /* One iteration of sparsified K-means (Sec. VI; Alg. 1, loop body) on
  * compressed data, centers in the preconditioned domain:

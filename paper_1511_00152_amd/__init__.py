@@ -13,7 +13,7 @@ the current HIP device; every call enqueues the library's kernels on
 import ctypes
 
 from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_F32, PDS_F64,
-                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_SPLIT_BF16, EXPORTS, PdsError,
+                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_MEAN, PDS_SPLIT_BF16, EXPORTS, PdsError,
                    check, lib)
 
 __all__ = [
@@ -160,6 +160,29 @@ def covariance(plan: Plan, vals, idx, acc=None, ws=None, C=None):
     check(lib().pds_covariance(plan.handle, _ptr(vals), _ptr(idx), n, _ptr(acc), 1, n, _ptr(C), _ptr(ws),
                                ws.numel() if ws is not None else 0, _stream()), "pds_covariance")
     return C
+
+
+def sample_mean(plan: Plan, vals, idx, acc=None, finalize: bool = True, n_total=None, out=None, ws=None):
+    """Sample-mean estimate (Sec. IV) of the compressed samples, in the
+    preconditioned domain: acc (p FP64, zeroed when None) += the per-coordinate
+    sums of vals; when finalize, returns (p/(m n_total)) acc (n_total defaults
+    to this batch's n), else returns acc."""
+    import torch
+
+    n = vals.shape[0]
+    dev = vals.device
+    if acc is None:
+        acc = torch.zeros(plan.p, dtype=torch.float64, device=dev)
+    if n_total is None:
+        n_total = n
+    if finalize and out is None:
+        out = torch.empty(plan.p, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = plan.workspace(PDS_OP_MEAN, n, device=dev)
+    check(lib().pds_sample_mean(plan.handle, _ptr(vals), _ptr(idx), n, _ptr(acc), 1 if finalize else 0, n_total,
+                                _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
+                                _stream()), "pds_sample_mean")
+    return out if finalize else acc
 
 
 def top_eigenvalues(C, k: int = 20):

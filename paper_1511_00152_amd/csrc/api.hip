@@ -209,6 +209,9 @@ pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, s
             if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
             *bytes = pds::kmeans2_workspace(plan->prec, p, n, K, dev);
             return PDS_OK;
+        case PDS_OP_MEAN:
+            *bytes = pds::mean_workspace(p, m, n, dev);
+            return PDS_OK;
         default:
             return fail(PDS_E_ARG, "unknown op %d", (int)op);
     }
@@ -271,6 +274,29 @@ pds_status pds_covariance(pds_plan plan, const void* vals, const uint16_t* idx, 
         e = pds::launch_covariance_finalize(plan->prec, (int)plan->p, (int)plan->m, n_total, acc, C_out, s);
         if (e != hipSuccess) return hip_fail(e, "covariance finalize");
     }
+    return PDS_OK;
+}
+
+pds_status pds_sample_mean(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, double* acc,
+                           int32_t finalize, int64_t n_total, double* mean_out, void* ws, size_t ws_bytes,
+                           void* stream)
+{
+    if (pds_status st = check_plan(plan)) return st;
+    if (n < 0) return fail(PDS_E_ARG, "n < 0");
+    if (!acc) return fail(PDS_E_ARG, "acc is NULL");
+    if (n > 0 && (!vals || !idx)) return fail(PDS_E_ARG, "vals and idx must be non-NULL");
+    if (finalize && (!mean_out || n_total < 1)) return fail(PDS_E_ARG, "finalize needs mean_out and n_total >= 1");
+    if (finalize && mean_out == acc) return fail(PDS_E_ARG, "acc and mean_out must not alias");
+    if (n == 0 && !finalize) return PDS_OK;
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_sample_mean");
+    const size_t need = pds::mean_workspace((int)plan->p, (int)plan->m, n, dev);
+    if (need > 0 && (!ws || ws_bytes < need))
+        return fail(PDS_E_WORKSPACE, "sample_mean needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
+    e = pds::launch_mean(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, acc, finalize, n_total, mean_out, ws,
+                         dev, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "sample_mean");
     return PDS_OK;
 }
 

@@ -51,6 +51,12 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
 hipError_t launch_covariance_finalize(int prec, int p, int m, int64_t n_total, const double* acc, double* C,
                                       hipStream_t s);
 
+// ---- sample mean -------------------------------------------------------------
+size_t mean_workspace(int p, int m, int64_t n, const DeviceInfo& dev);
+hipError_t launch_mean(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, double* acc,
+                       int finalize, int64_t n_total, double* mean_out, void* ws, const DeviceInfo& dev,
+                       hipStream_t s);
+
 // ---- K-means ----------------------------------------------------------------
 size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceInfo& dev);
 hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, int K,
