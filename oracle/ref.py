@@ -31,6 +31,11 @@ Functions and the passages they follow (paper = arXiv 1511.00152):
   a reading.
 * ``y_entry`` -- one entry of H D x from the definition (row of H times D x).
 * ``mean_estimate`` -- Thm. "sampleMean"; pinned by enumeration (unbiased).
+* ``principal_components`` / ``explained_variance`` -- PCA on the covariance
+  estimate (Sec. V) and the fraction of explained variance used in the
+  column-sampling comparison (Sec. II); pinned by the canonical-subset closed
+  form, the full-basis value 1, rotation invariance within the span, and the
+  Ky Fan value (top-k singular values of X from an independent SVD).
 * ``kmeans_2pass`` -- Alg. "Sparsified K-means, 2-pass": one pass over the
   original rows after the one-pass run; pinned against per-label means
   (``numpy.add.at``) and nearest centers (``scipy.spatial.distance.cdist``),
@@ -259,6 +264,25 @@ def mean_estimate(p: int, vals, idx):
     mean = np.zeros(p, dtype=np.float64)
     lib().orc_mean_estimate(p, m, _ptr(vals), _ptr(idx), n, _ptr(mean))
     return mean
+
+
+def principal_components(C, k: int):
+    """The k leading eigenvectors of the symmetric matrix C as the columns of a
+    p x k matrix, eigenvalues descending (PCA on the estimate, Sec. V)."""
+    w, V = np.linalg.eigh(np.asarray(C, dtype=np.float64))
+    order = np.argsort(w)[::-1][:k]
+    return np.ascontiguousarray(V[:, order])
+
+
+def explained_variance(X, U):
+    """Fraction of explained variance (Sec. II, comparison with column
+    sampling): tr(U^T A A^T U) / tr(A A^T) for the p x n data matrix A whose
+    columns are the samples and p x k orthonormal components U.  The samples
+    are the rows of X here (A = X^T), so the fraction is ||X U||_F^2 / ||X||_F^2."""
+    X = np.asarray(X, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    P = X @ U
+    return float(np.sum(P * P) / np.sum(X * X))
 
 
 def sparsified_kmeans(X, seed: int, m: int, K: int, T: int, init_centers=None, nthreads: int = 0):

@@ -282,6 +282,51 @@ def test_mean_estimator_unbiased_by_enumeration():
     assert np.max(np.abs(acc / len(subs) - y)) < 1e-14
 
 
+# ------------------------------------------------ PCA quality (Sec. II, V) --
+def test_explained_variance_canonical_subset_closed_form():
+    """U = canonical vectors e_j, j in S: the fraction is the energy of the
+    columns S over the total, summed coordinate by coordinate."""
+    rng = np.random.default_rng(31)
+    n, p = 300, 40
+    X = rng.standard_normal((n, p)) * rng.uniform(0.1, 5.0, p)
+    S = [3, 7, 11, 39]
+    U = np.eye(p)[:, S]
+    num = sum(sum(X[i, j] ** 2 for i in range(n)) for j in S)
+    den = sum(sum(X[i, j] ** 2 for i in range(n)) for j in range(p))
+    assert abs(ref.explained_variance(X, U) - num / den) < 1e-13
+
+
+def test_explained_variance_full_basis_and_rotation():
+    """Any orthonormal basis of R^p explains everything; rotating the
+    components inside their span changes nothing."""
+    rng = np.random.default_rng(32)
+    n, p, k = 200, 24, 5
+    X = rng.standard_normal((n, p))
+    Q, _ = np.linalg.qr(rng.standard_normal((p, p)))
+    assert abs(ref.explained_variance(X, Q) - 1.0) < 1e-13
+    R, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    U = Q[:, :k]
+    assert abs(ref.explained_variance(X, U) - ref.explained_variance(X, U @ R)) < 1e-13
+
+
+def test_principal_components_ky_fan():
+    """The top-k eigenvectors of X^T X explain the largest possible fraction,
+    sum_{i<k} s_i^2 / sum s_i^2 with s the singular values of X (Ky Fan),
+    computed by an independent SVD; ascending order would explain far less."""
+    rng = np.random.default_rng(33)
+    n, p, k = 500, 30, 4
+    X = rng.standard_normal((n, p)) @ np.diag(np.linspace(5.0, 0.5, p))
+    s = np.linalg.svd(X, compute_uv=False)
+    U = ref.principal_components(X.T @ X, k)
+    assert U.shape == (p, k)
+    assert np.allclose(U.T @ U, np.eye(k), atol=1e-12)
+    assert abs(ref.explained_variance(X, U) - np.sum(s[:k] ** 2) / np.sum(s ** 2)) < 1e-12
+    lam = np.sort(np.linalg.eigvalsh(X.T @ X))[::-1][:k]
+    assert np.allclose((X.T @ X) @ U, U * lam, atol=1e-9 * lam[0])
+    low = np.linalg.eigh(X.T @ X)[1][:, :k]
+    assert ref.explained_variance(X, low) < 0.5 * ref.explained_variance(X, U)
+
+
 def test_covariance_matches_literal_oracle():
     p, n, m, seed = 16, 40, 6, 2
     X = np.random.default_rng(5).standard_normal((n, p))
