@@ -386,6 +386,41 @@ def run_mean(pds, r, n, p, m, steps):
             "kernels_ms": {k: d["avg_ms"] for k, d in kern.items()}}
 
 
+def run_pca(pds, plan, C, X, name, k=20):
+    """PCA on the estimate (Sec. V) and its quality (Sec. II): the top-k
+    components of C mapped back to the original domain, and the fraction of
+    explained variance over all rows of X of those components and of the
+    workload's planted ones; not part of the step."""
+    import torch
+
+    import synth
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    comps, lam = pds.principal_components(plan, C, k)
+    e1.record()
+    torch.cuda.synchronize()
+    eig_ms = e0.elapsed_time(e1)
+    planted = torch.as_tensor(synth.model(name)["U"].T.copy(), dtype=torch.float64, device=X.device)
+    pds.explained_variance(X, comps)
+    torch.cuda.synchronize()
+    lib = pds.lib()
+    lib.pds_profile_enable(1)
+    ev = pds.explained_variance(X, comps).cpu().numpy()
+    lib.pds_profile_enable(0)
+    kern = profile_report(lib)
+    ev_true = pds.explained_variance(X, planted).cpu().numpy()
+    n, p = X.shape
+    t = kern["explained"]["avg_ms"]
+    return {"what": f"top {k} components of the estimate, explained-variance fraction over all {n} rows; "
+                    "not part of the step",
+            "explained_estimate": float(ev[0] / ev[1]), "explained_planted": float(ev_true[0] / ev_true[1]),
+            "eigh_unmix_ms": eig_ms, "explained_ms": t,
+            "explained_frac_hbm": n * p * X.element_size() / (t / 1e3) / 1e9 / PEAK_HBM_GBS,
+            "top_eigenvalues": [float(v) for v in lam[:5].cpu()]}
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the FETCH_SIZE /
     WRITE_SIZE counters of a profiled run."""
@@ -497,6 +532,9 @@ def main():
                         "(device symmetric eigensolver), not part of the step", "largest": float(ev_top[0])}
     out["sample_mean"] = run_mean(pds, res[head], n, p, m, max(1, min(args.steps, 10)))
     log(f"sample_mean: {json.dumps(out['sample_mean'])}")
+    if not args.no_eigen:
+        out["pca"] = run_pca(pds, res[head]["plan"], res[head]["C"], X, name)
+        log(f"pca: {json.dumps(out['pca'])}")
     for v in res.values():
         v.pop("vals", None), v.pop("idx", None), v.pop("C", None)
     if not args.no_cpu_baseline:

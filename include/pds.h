@@ -163,6 +163,23 @@ pds_status pds_sample_mean(pds_plan plan, const void* vals, const uint16_t* idx,
                            int32_t finalize, int64_t n_total, double* mean_out, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* Fraction of explained variance of k principal components (Sec. II,
+ * comparison with column sampling; PCA on the estimate of Sec. V), FP64:
+ *   out2[0] = sum_i sum_j (x_i . U[j])^2 = ||X U^T||_F^2,
+ *   out2[1] = sum_i ||x_i||^2 = ||X||_F^2,
+ * so the fraction is out2[0] / out2[1] when the rows of U are orthonormal.
+ * Summed in a fixed order (run-to-run identical).
+ *   U:  device, k x p doubles, row j = component j in the original domain
+ *       (e.g. eigenvectors of C_n mapped back by pds_unmix), 1 <= k <= 32.
+ *   X:  device, n x p rows with leading dimension ldx >= p; double when
+ *       x_prec = PDS_F64, float when x_prec = PDS_F32.
+ *   out2: device, 2 doubles.  ws: device, >= PDS_EXPLAINED_WS_BYTES bytes.
+ * Errors: PDS_E_ARG (null pointers, n < 1, p < 1, k out of range, ldx < p,
+ * x_prec), PDS_E_WORKSPACE. */
+#define PDS_EXPLAINED_WS_BYTES 16384
+pds_status pds_explained_variance(const double* U, int32_t k, const void* X, int32_t x_prec, int64_t n, int64_t p,
+                                  int64_t ldx, double* out2, void* ws, size_t ws_bytes, void* stream);
+
 /* One iteration of sparsified K-means (Sec. VI; Alg. 1, loop body) on
  * compressed data, centers in the preconditioned domain:
  *   step 1 (eq. assignments): assign[i] = argmin_k sum_{l in idx_i}

@@ -13,7 +13,7 @@ the current HIP device; every call enqueues the library's kernels on
 import ctypes
 
 from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_F32, PDS_F64,
-                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_MEAN, PDS_SPLIT_BF16, EXPORTS, PdsError,
+                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_MEAN, PDS_EXPLAINED_WS_BYTES, PDS_SPLIT_BF16, EXPORTS, PdsError,
                    check, lib)
 
 __all__ = [
@@ -198,6 +198,43 @@ def top_eigenvalues(C, k: int = 20):
     w = torch.linalg.eigvalsh(C.to(torch.float64))
     k = min(int(k), C.shape[0])
     return torch.flip(w, dims=[0])[:k]
+
+
+def principal_components(plan: Plan, C, k: int):
+    """PCA on the covariance estimate (Sec. V): the k leading eigenvectors of
+    C (p x p FP64, preconditioned domain) from the device's symmetric
+    eigensolver (rocSOLVER through torch.linalg), mapped back to the original
+    domain by pds_unmix.  Returns (components k x p FP64, rows orthonormal;
+    eigenvalues (k,) descending)."""
+    import torch
+
+    k = int(k)
+    if C.dim() != 2 or C.shape[0] != C.shape[1] or C.shape[0] != plan.p or not 1 <= k <= plan.p:
+        raise ValueError("C must be p x p and 1 <= k <= p")
+    w, V = torch.linalg.eigh(C.to(torch.float64))
+    top = torch.flip(V[:, -k:], dims=[1]).T.contiguous()
+    return unmix(plan, top), torch.flip(w[-k:], dims=[0])
+
+
+def explained_variance(X, comps, out=None, ws=None):
+    """Fraction of explained variance (Sec. II) of the components `comps`
+    (k x p FP64, orthonormal rows) over the rows of X (n x p, FP32 or FP64):
+    returns the device tensor (||X comps^T||_F^2, ||X||_F^2) (2,) FP64."""
+    import torch
+
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D tensor with unit column stride")
+    if X.dtype not in (torch.float32, torch.float64) or comps.dtype != torch.float64:
+        raise TypeError("X must be FP32 or FP64 and comps FP64")
+    comps = comps.contiguous()
+    if ws is None:
+        ws = torch.empty(PDS_EXPLAINED_WS_BYTES, dtype=torch.uint8, device=X.device)
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=X.device)
+    xp = PDS_F64 if X.dtype == torch.float64 else PDS_F32
+    check(lib().pds_explained_variance(_ptr(comps), comps.shape[0], _ptr(X), xp, X.shape[0], X.shape[1], X.stride(0),
+                                       _ptr(out), _ptr(ws), ws.numel(), _stream()), "pds_explained_variance")
+    return out
 
 
 def kmeans_step(plan: Plan, vals, idx, centers, out=None, assign=None, objective=None, ws=None):

@@ -300,6 +300,23 @@ pds_status pds_sample_mean(pds_plan plan, const void* vals, const uint16_t* idx,
     return PDS_OK;
 }
 
+pds_status pds_explained_variance(const double* U, int32_t k, const void* X, int32_t x_prec, int64_t n, int64_t p,
+                                  int64_t ldx, double* out2, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!U || !X || !out2) return fail(PDS_E_ARG, "U, X and out2 must be non-NULL");
+    if (k < 1 || k > pds::explained_max_k())
+        return fail(PDS_E_ARG, "k = %d: must be in [1, %d]", (int)k, pds::explained_max_k());
+    if (n < 1 || p < 1 || p > (1 << 30)) return fail(PDS_E_ARG, "n = %lld, p = %lld", (long long)n, (long long)p);
+    if (ldx < p) return fail(PDS_E_ARG, "ldx = %lld < p = %lld", (long long)ldx, (long long)p);
+    if (x_prec != PDS_F64 && x_prec != PDS_F32) return fail(PDS_E_ARG, "x_prec must be PDS_F64 or PDS_F32");
+    if (!ws || ws_bytes < pds::explained_workspace())
+        return fail(PDS_E_WORKSPACE, "explained_variance needs %zu workspace bytes", pds::explained_workspace());
+    hipError_t e = pds::launch_explained(U, (int)k, X, x_prec == PDS_F64, n, (int)p, ldx, out2, ws,
+                                         reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "explained_variance");
+    return PDS_OK;
+}
+
 pds_status pds_kmeans_step(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K,
                            const double* centers_in, double* centers_out, int32_t* assign, double* objective, void* ws,
                            size_t ws_bytes, void* stream)

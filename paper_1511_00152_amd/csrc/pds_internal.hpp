@@ -57,6 +57,12 @@ hipError_t launch_mean(int prec, int p, int m, const void* vals, const uint16_t*
                        int finalize, int64_t n_total, double* mean_out, void* ws, const DeviceInfo& dev,
                        hipStream_t s);
 
+// ---- PCA quality -------------------------------------------------------------
+size_t explained_workspace();
+int explained_max_k();
+hipError_t launch_explained(const double* U, int k, const void* X, int x_f64, int64_t n, int p, int64_t ldx,
+                            double* out2, void* ws, hipStream_t s);
+
 // ---- K-means ----------------------------------------------------------------
 size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceInfo& dev);
 hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, int K,
