@@ -68,7 +68,8 @@ typedef enum {
     PDS_OP_COVARIANCE = 1,
     PDS_OP_KMEANS = 2,
     PDS_OP_KMEANS2 = 3,
-    PDS_OP_MEAN = 4
+    PDS_OP_MEAN = 4,
+    PDS_OP_KMEANSPP = 5
 } pds_op;
 
 typedef struct pds_plan_s* pds_plan;
@@ -179,6 +180,27 @@ pds_status pds_sample_mean(pds_plan plan, const void* vals, const uint16_t* idx,
 #define PDS_EXPLAINED_WS_BYTES 16384
 pds_status pds_explained_variance(const double* U, int32_t k, const void* X, int32_t x_prec, int64_t n, int64_t p,
                                   int64_t ldx, double* out2, void* ws, size_t ws_bytes, void* stream);
+
+/* K-means++ seeding on compressed data (Alg. 1 seeds with K-means++; D^2
+ * sampling of Arthur & Vassilvitskii with the sparsified distance of Sec. VI):
+ *   center 0 = sample floor(u_0 n) (at most n - 1);
+ *   center k = the first sample i whose running sum of D^2 (ascending i)
+ *              exceeds u_k sum_j D^2, else sample n - 1, where D^2(i) is the
+ *              smallest sum over sample i's kept coordinates l of
+ *              (vals_i,l - center[l])^2 over the centers chosen so far;
+ *   centers[k] = the chosen sample's zero-filled compressed vector.
+ * u_k = (w_k >> 11) 2^-53 with w_k word (k mod 4) of the Philox4x64-10 block
+ * with key (plan seed, 0) and counter (k div 4, 0, 2, 0).  Distances are the
+ * FP64 sequential sums (fused multiply-adds in ascending l); the running sums
+ * are formed per block of samples, so a draw within rounding of a boundary
+ * between two samples may take the neighbour a sequential scan would take.
+ *   vals / idx: as written by pds_compress (n x m, indices < p).
+ *   centers: device, K x p doubles.  chosen: device, K int64 (or NULL).
+ *   ws: device, >= pds_workspace_size(KMEANSPP, n).
+ * Errors: PDS_E_ARG (null pointers, n < 1, K < 1 or K > 1024),
+ * PDS_E_WORKSPACE. */
+pds_status pds_kmeanspp(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, double* centers,
+                        int64_t* chosen, void* ws, size_t ws_bytes, void* stream);
 
 /* One iteration of sparsified K-means (Sec. VI; Alg. 1, loop body) on
  * compressed data, centers in the preconditioned domain:

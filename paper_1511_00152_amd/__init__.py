@@ -13,7 +13,7 @@ the current HIP device; every call enqueues the library's kernels on
 import ctypes
 
 from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_F32, PDS_F64,
-                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_MEAN, PDS_EXPLAINED_WS_BYTES, PDS_SPLIT_BF16, EXPORTS, PdsError,
+                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_MEAN, PDS_OP_KMEANSPP, PDS_EXPLAINED_WS_BYTES, PDS_SPLIT_BF16, EXPORTS, PdsError,
                    check, lib)
 
 __all__ = [
@@ -235,6 +235,26 @@ def explained_variance(X, comps, out=None, ws=None):
     check(lib().pds_explained_variance(_ptr(comps), comps.shape[0], _ptr(X), xp, X.shape[0], X.shape[1], X.stride(0),
                                        _ptr(out), _ptr(ws), ws.numel(), _stream()), "pds_explained_variance")
     return out
+
+
+def kmeanspp(plan: Plan, vals, idx, K: int, centers=None, chosen=None, ws=None):
+    """K-means++ seeding (Alg. 1) on the compressed samples with the plan's
+    seed: returns (centers K x p FP64, zero-filled compressed vectors of the
+    chosen samples; chosen (K,) int64)."""
+    import torch
+
+    n = vals.shape[0]
+    dev = vals.device
+    K = int(K)
+    if centers is None:
+        centers = torch.empty((K, plan.p), dtype=torch.float64, device=dev)
+    if chosen is None:
+        chosen = torch.empty(K, dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = plan.workspace(PDS_OP_KMEANSPP, n, device=dev)
+    check(lib().pds_kmeanspp(plan.handle, _ptr(vals), _ptr(idx), n, K, _ptr(centers), _ptr(chosen), _ptr(ws),
+                             ws.numel() if ws is not None else 0, _stream()), "pds_kmeanspp")
+    return centers, chosen
 
 
 def kmeans_step(plan: Plan, vals, idx, centers, out=None, assign=None, objective=None, ws=None):

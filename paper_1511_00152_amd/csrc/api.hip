@@ -212,6 +212,9 @@ pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, s
         case PDS_OP_MEAN:
             *bytes = pds::mean_workspace(p, m, n, dev);
             return PDS_OK;
+        case PDS_OP_KMEANSPP:
+            *bytes = pds::kmeanspp_workspace(n);
+            return PDS_OK;
         default:
             return fail(PDS_E_ARG, "unknown op %d", (int)op);
     }
@@ -314,6 +317,22 @@ pds_status pds_explained_variance(const double* U, int32_t k, const void* X, int
     hipError_t e = pds::launch_explained(U, (int)k, X, x_prec == PDS_F64, n, (int)p, ldx, out2, ws,
                                          reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "explained_variance");
+    return PDS_OK;
+}
+
+pds_status pds_kmeanspp(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, double* centers,
+                        int64_t* chosen, void* ws, size_t ws_bytes, void* stream)
+{
+    if (pds_status st = check_plan(plan)) return st;
+    if (n < 1) return fail(PDS_E_ARG, "kmeanspp: n = %lld < 1", (long long)n);
+    if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
+    if (!vals || !idx || !centers) return fail(PDS_E_ARG, "vals, idx and centers must be non-NULL");
+    const size_t need = pds::kmeanspp_workspace(n);
+    if (!ws || ws_bytes < need)
+        return fail(PDS_E_WORKSPACE, "kmeanspp needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
+    hipError_t e = pds::launch_kmeanspp(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, K, plan->seed, centers,
+                                        chosen, ws, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kmeanspp");
     return PDS_OK;
 }
 

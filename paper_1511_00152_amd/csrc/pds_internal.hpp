@@ -63,6 +63,11 @@ int explained_max_k();
 hipError_t launch_explained(const double* U, int k, const void* X, int x_f64, int64_t n, int p, int64_t ldx,
                             double* out2, void* ws, hipStream_t s);
 
+// ---- K-means++ seeding ------------------------------------------------------
+size_t kmeanspp_workspace(int64_t n);
+hipError_t launch_kmeanspp(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, int K,
+                           uint64_t seed, double* centers, int64_t* chosen, void* ws, hipStream_t s);
+
 // ---- K-means ----------------------------------------------------------------
 size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceInfo& dev);
 hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, int K,

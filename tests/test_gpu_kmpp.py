@@ -1,0 +1,124 @@
+"""K-means++ seeding on the GPU (Alg. 1 seeds with K-means++; D^2 sampling
+with the sparsified distance of Sec. VI) against the oracle.
+
+Both sides draw the same uniforms and compute the same FP64 distances (same
+order, fused multiply-adds), so the chosen samples agree unless a draw lands
+within rounding of a boundary of the running sum, which the GPU forms per
+block of samples: a differing choice is accepted only there (the test then
+checks it against the sequential running sum from numpy and stops comparing,
+since later draws depend on it).  Centers are copies of the chosen samples and
+compare exactly.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1511_00152_amd as pds  # noqa: E402
+import synth  # noqa: E402
+from oracle import ref  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+U_RND = 2.0 ** -53
+PRECS = {"f64": (pds.PDS_F64, np.float64), "f32": (pds.PDS_F32, np.float32), "split": (pds.PDS_SPLIT_BF16, np.float32)}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def uniform(seed, k):
+    w = ref.philox4x64_10([k // 4, 0, 2, 0], [seed, 0])[k % 4]
+    return float(int(w) >> 11) * 2.0 ** -53
+
+
+def sparse_d2(vals, idx, centers):
+    """D^2 of every sample to the nearest of the given zero-filled centers."""
+    d = np.full(vals.shape[0], np.inf)
+    for c in centers:
+        d = np.minimum(d, np.sum((vals - c[idx.astype(np.int64)]) ** 2, axis=1))
+    return d
+
+
+def check_seeding(seed, vals, idx, K, centers_g, chosen_g):
+    n = vals.shape[0]
+    C_o, ch_o = ref.kmeanspp(seed, centers_g.shape[1], vals, idx, K)
+    for k in range(K):
+        if chosen_g[k] != ch_o[k]:
+            assert k > 0, "the first center is u n and cannot differ"
+            d2 = sparse_d2(vals, idx, C_o[:k])
+            run = np.cumsum(d2)
+            target = uniform(seed, k) * run[-1]
+            slack = 4 * n * U_RND * run[-1]
+            c = int(chosen_g[k])
+            lo = run[c - 1] if c > 0 else 0.0
+            assert lo - slack <= target < run[c] + slack, (k, c, int(ch_o[k]))
+            log(f"draw {k} within rounding of a boundary: GPU {c}, oracle {int(ch_o[k])}")
+            return k
+        assert np.array_equal(centers_g[k], C_o[k])
+    return K
+
+
+KMPP_CASES = [(2, 1, 50, 3, "f64"), (64, 7, 1000, 5, "f64"), (256, 26, 5000, 10, "f32"), (1024, 51, 20000, 10, "f32"),
+              (4096, 410, 3000, 20, "split"), (16384, 100, 600, 8, "f32"), (128, 13, 1, 1, "f64"),
+              (256, 26, 257, 300, "f32"), (512, 51, 70001, 37, "f32")]
+
+
+@pytest.mark.parametrize("p,m,n,K,prec", KMPP_CASES)
+def test_kmeanspp_matches_oracle(p, m, n, K, prec):
+    pr, dt = PRECS[prec]
+    log(f"kmeanspp p={p} m={m} n={n} K={K} prec={prec}")
+    d = synth.random_compressed(n, p, m, seed=7 * p + K, dtype=dt)
+    seed = 1000 + K
+    plan = pds.Plan(p, m, seed=seed, prec=pr)
+    C, ch = pds.kmeanspp(plan, to_dev(d["vals"]), to_dev(d["idx"].view(np.int16)), K)
+    torch.cuda.synchronize()
+    upto = check_seeding(seed, d["vals"].astype(np.float64), d["idx"], K, C.cpu().numpy(), ch.cpu().numpy())
+    assert upto >= min(K, 1)
+
+
+def test_kmeanspp_pipeline_matches_oracle():
+    """The mixture workload's shape at reduced n, FP64 plan: GPU compress and
+    GPU K-means++ against the oracle's compress and seeding of the same rows
+    (the preconditioned values agree to FP64 rounding, so the draws do)."""
+    w = synth.WORKLOADS["mixture_f32"]
+    p, K = w["p"], w["K"]
+    m = synth.m_from_gamma(w["gamma"], p)
+    n = 20000
+    X = synth.rows_numpy("mixture_f32", n).astype(np.float64)
+    log(f"kmeanspp pipeline p={p} m={m} n={n} K={K}")
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F64)
+    vals, idx = pds.compress(plan, to_dev(X))
+    C, ch = pds.kmeanspp(plan, vals, idx, K)
+    torch.cuda.synchronize()
+    ov, oi = ref.compress(X, 0, m)
+    assert np.array_equal(idx.cpu().numpy().view(np.uint16), oi)
+    C_o, ch_o = ref.kmeanspp(0, p, ov, oi, K)
+    assert np.array_equal(ch.cpu().numpy(), ch_o)
+    assert np.max(np.abs(C.cpu().numpy() - C_o)) <= 1e-13 * np.max(np.abs(C_o))
+
+
+def test_kmeanspp_argument_errors():
+    plan = pds.Plan(64, 8, prec=pds.PDS_F32)
+    vals = torch.zeros((10, 8), dtype=torch.float32, device="cuda")
+    idx = torch.zeros((10, 8), dtype=torch.int16, device="cuda")
+    with pytest.raises(pds.PdsError):
+        pds.kmeanspp(plan, vals, idx, 0)
+    with pytest.raises(pds.PdsError):
+        pds.kmeanspp(plan, vals, idx, 1025)
+    with pytest.raises(pds.PdsError):
+        pds.kmeanspp(plan, vals[:0], idx[:0], 3)
+    with pytest.raises(pds.PdsError):
+        pds.kmeanspp(plan, vals, idx, 3, ws=torch.empty(8, dtype=torch.uint8, device="cuda"))
