@@ -507,10 +507,10 @@ void orc_unmix(uint64_t seed, int64_t p, const double* centers_pre, int K, doubl
  * (b, 0, 2, 0).  The first center is sample floor(u * n); each next one is the
  * first sample whose running D^2 sum exceeds u * (total D^2).                */
 void orc_kmeanspp(uint64_t seed, int64_t p, int64_t m, const double* vals, const uint16_t* idx, int64_t n,
-                  int K, double* centers, int64_t* chosen)
+                  int K, uint64_t replicate, double* centers, int64_t* chosen)
 {
     uint64_t key[2] = {seed, 0};
-    uint64_t ctr[4] = {0, 0, 2, 0};
+    uint64_t ctr[4] = {0, replicate, 2, 0};
     uint64_t buf[4];
     int pos = 4;
     double* d2 = (double*)malloc(sizeof(double) * (size_t)n);

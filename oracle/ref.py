@@ -28,7 +28,11 @@ Functions and the passages they follow (paper = arXiv 1511.00152):
   Vassilvitskii with the sparsified distance of Sec. VI; it is pinned by its
   sampling law (first center uniform, the next one with probability D^2 / sum
   D^2), checked by Monte Carlo over seeds; which stream words it consumes is
-  a reading.
+  a reading (starting point r reads counter (b, r, 2, 0), pinned against
+  numpy's Philox).
+* ``sparsified_kmeans_best`` -- best of R starting points (Sec. VII runs):
+  the kept start is the argmin of the final objectives recomputed by a
+  direct numpy sum over each start's own assignment.
 * ``y_entry`` -- one entry of H D x from the definition (row of H times D x).
 * ``mean_estimate`` -- Thm. "sampleMean"; pinned by enumeration (unbiased).
 * ``principal_components`` / ``explained_variance`` -- PCA on the covariance
@@ -80,7 +84,7 @@ def lib():
         L.orc_cov_finalize.argtypes = [i64, i64, i64, P, P]
         L.orc_kmeans_step.argtypes = [i64, i64, P, P, i64, i32, P, P, P, P, P, i32]
         L.orc_unmix.argtypes = [u64, i64, P, i32, P]
-        L.orc_kmeanspp.argtypes = [u64, i64, i64, P, P, i64, i32, P, P]
+        L.orc_kmeanspp.argtypes = [u64, i64, i64, P, P, i64, i32, u64, P, P]
         L.orc_mean_estimate.argtypes = [i64, i64, P, P, i64, P]
         L.orc_kmeans_2pass.argtypes = [i64, P, i64, i32, P, P, P, P, P, i32]
         L.orc_max_threads.restype = i32
@@ -233,13 +237,15 @@ def unmix(seed: int, centers_pre):
     return out
 
 
-def kmeanspp(seed: int, p: int, vals, idx, K: int):
+def kmeanspp(seed: int, p: int, vals, idx, K: int, replicate: int = 0):
+    """K-means++ seeding; starting point `replicate` draws its uniforms from
+    the Philox blocks with counter (b, replicate, 2, 0)."""
     vals = np.ascontiguousarray(vals, dtype=np.float64)
     idx = np.ascontiguousarray(idx, dtype=np.uint16)
     n, m = vals.shape
     centers = np.zeros((K, p), dtype=np.float64)
     chosen = np.zeros(K, dtype=np.int64)
-    lib().orc_kmeanspp(seed, p, m, _ptr(vals), _ptr(idx), n, K, _ptr(centers), _ptr(chosen))
+    lib().orc_kmeanspp(seed, p, m, _ptr(vals), _ptr(idx), n, K, replicate, _ptr(centers), _ptr(chosen))
     return centers, chosen
 
 
@@ -264,6 +270,29 @@ def mean_estimate(p: int, vals, idx):
     mean = np.zeros(p, dtype=np.float64)
     lib().orc_mean_estimate(p, m, _ptr(vals), _ptr(idx), n, _ptr(mean))
     return mean
+
+
+def sparsified_kmeans_best(X, seed: int, m: int, K: int, T: int, R: int, nthreads: int = 0):
+    """Alg. 1 with R random starting points on one compression: each start r
+    is a K-means++ seeding (replicate r) followed by T rounds; the start whose
+    last round reports the smallest objective (eq. CK_means; the earliest on
+    ties) is kept.  Returns dict with best, objectives (R x T), centers_pre,
+    assign, centers (unmixed) of the kept start."""
+    n, p = X.shape
+    vals, idx = compress(X, seed, m, nthreads=nthreads)
+    objs = np.zeros((R, T))
+    best = None
+    for r in range(R):
+        mu, _ = kmeanspp(seed, p, vals, idx, K, r)
+        assign = None
+        for t in range(T):
+            mu, assign, J, _ = kmeans_step(p, vals, idx, mu, nthreads=nthreads)
+            objs[r, t] = J
+        if best is None or objs[r, T - 1] < objs[best[0], T - 1]:
+            best = (r, mu, assign)
+    r, mu, assign = best
+    return {"vals": vals, "idx": idx, "best": r, "objectives": objs, "centers_pre": mu, "assign": assign,
+            "centers": unmix(seed, mu)}
 
 
 def principal_components(C, k: int):

@@ -540,6 +540,37 @@ def test_kmeanspp_picks_distinct_samples():
     assert np.array_equal(chosen, chosen2)
 
 
+def test_kmeanspp_replicate_stream_and_best_of_r():
+    """Starting point r draws from Philox counter (b, r, 2, 0): its first
+    center is floor(u n) with u the top 53 bits of word 0 of that block,
+    computed here with numpy's own Philox.  Best of R: the kept start has the
+    smallest final objective, recomputed by a direct sum over its own
+    assignment (the oracle's objective of the last round is taken with the
+    centers entering that round)."""
+    p, n, m, K, T, R, seed = 32, 400, 8, 4, 3, 6, 11
+    X = np.random.default_rng(41).standard_normal((n, p)) + np.repeat(np.eye(p)[:4] * 6, n // 4, axis=0)
+    vals, idx = ref.compress(X, seed, m)
+    for r in range(R):
+        c = (r << 64) - 1 + (2 << 128)  # counter (0, r, 2, 0) minus one: numpy advances before each block
+        words = np.array([(c >> (64 * k)) & (2 ** 64 - 1) for k in range(4)], dtype=np.uint64)
+        u = (int(np.random.Philox(key=np.array([seed, 0], dtype=np.uint64), counter=words).random_raw(4)[0]) >> 11) \
+            * 2.0 ** -53
+        _, ch = ref.kmeanspp(seed, p, vals, idx, K, r)
+        assert ch[0] == min(int(u * n), n - 1)
+    out = ref.sparsified_kmeans_best(X, seed, m, K, T, R)
+    final = []
+    for r in range(R):
+        mu, _ = ref.kmeanspp(seed, p, vals, idx, K, r)
+        for _ in range(T - 1):
+            mu, _, _, _ = ref.kmeans_step(p, vals, idx, mu)
+        a = ref.kmeans_step(p, vals, idx, mu)[1]
+        ii = idx.astype(np.int64)
+        final.append(sum(float(np.sum((vals[i] - mu[a[i]][ii[i]]) ** 2)) for i in range(n)))
+    assert np.allclose(out["objectives"][:, -1], final, rtol=1e-12)
+    assert out["best"] == int(np.argmin(final))
+    assert len(set(np.round(final, 6))) > 1  # the starts really differ
+
+
 def test_kmeanspp_seeding_distribution():
     """K-means++ (Arthur & Vassilvitskii; Alg. 1 init, on compressed samples):
     the first center is uniform over the n samples; given it, the second is
