@@ -69,7 +69,8 @@ typedef enum {
     PDS_OP_KMEANS = 2,
     PDS_OP_KMEANS2 = 3,
     PDS_OP_MEAN = 4,
-    PDS_OP_KMEANSPP = 5
+    PDS_OP_KMEANSPP = 5,
+    PDS_OP_KMEANS_BEST = 6
 } pds_op;
 
 typedef struct pds_plan_s* pds_plan;
@@ -190,17 +191,34 @@ pds_status pds_explained_variance(const double* U, int32_t k, const void* X, int
  *              (vals_i,l - center[l])^2 over the centers chosen so far;
  *   centers[k] = the chosen sample's zero-filled compressed vector.
  * u_k = (w_k >> 11) 2^-53 with w_k word (k mod 4) of the Philox4x64-10 block
- * with key (plan seed, 0) and counter (k div 4, 0, 2, 0).  Distances are the
+ * with key (plan seed, 0) and counter (k div 4, replicate, 2, 0): each
+ * replicate >= 0 is an independent starting point.  Distances are the
  * FP64 sequential sums (fused multiply-adds in ascending l); the running sums
  * are formed per block of samples, so a draw within rounding of a boundary
  * between two samples may take the neighbour a sequential scan would take.
  *   vals / idx: as written by pds_compress (n x m, indices < p).
  *   centers: device, K x p doubles.  chosen: device, K int64 (or NULL).
  *   ws: device, >= pds_workspace_size(KMEANSPP, n).
- * Errors: PDS_E_ARG (null pointers, n < 1, K < 1 or K > 1024),
- * PDS_E_WORKSPACE. */
-pds_status pds_kmeanspp(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, double* centers,
-                        int64_t* chosen, void* ws, size_t ws_bytes, void* stream);
+ * Errors: PDS_E_ARG (null pointers, n < 1, K < 1 or K > 1024,
+ * replicate < 0), PDS_E_WORKSPACE. */
+pds_status pds_kmeanspp(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, int32_t replicate,
+                        double* centers, int64_t* chosen, void* ws, size_t ws_bytes, void* stream);
+
+/* Sparsified K-means from R starting points on one compression (Alg. 1; the
+ * experiments of Sec. VII keep the best of several random starts): for
+ * r = 0 .. R-1, K-means++ seeding with replicate r (pds_kmeanspp), then T
+ * rounds of pds_kmeans_step; objectives[r*T + t] = round t's objective of
+ * start r.  The kept start is the one whose last round reports the smallest
+ * objective (the earliest on ties): centers_out (device, K x p doubles,
+ * preconditioned domain) and assign_out (device, n int32) receive its final
+ * centers and last assignments, best (device, 1 int32) its index.  Every
+ * decision is taken on the device; nothing returns to the host in between.
+ * ws: device, >= pds_workspace_size(KMEANS_BEST, n, K).
+ * Errors: PDS_E_ARG (null pointers, n < 1, K out of [1, 1024], T < 1, R out of
+ * [1, 1024]), PDS_E_WORKSPACE. */
+pds_status pds_kmeans_best(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, int32_t T,
+                           int32_t R, double* centers_out, int32_t* assign_out, double* objectives, int32_t* best,
+                           void* ws, size_t ws_bytes, void* stream);
 
 /* One iteration of sparsified K-means (Sec. VI; Alg. 1, loop body) on
  * compressed data, centers in the preconditioned domain:

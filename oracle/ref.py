@@ -280,6 +280,14 @@ def sparsified_kmeans_best(X, seed: int, m: int, K: int, T: int, R: int, nthread
     assign, centers (unmixed) of the kept start."""
     n, p = X.shape
     vals, idx = compress(X, seed, m, nthreads=nthreads)
+    out = kmeans_best_compressed(p, vals, idx, seed, K, T, R, nthreads)
+    out.update({"vals": vals, "idx": idx, "centers": unmix(seed, out["centers_pre"])})
+    return out
+
+
+def kmeans_best_compressed(p: int, vals, idx, seed: int, K: int, T: int, R: int, nthreads: int = 0):
+    """The R starts and the choice of ``sparsified_kmeans_best`` on given
+    compressed samples (preconditioned domain)."""
     objs = np.zeros((R, T))
     best = None
     for r in range(R):
@@ -291,8 +299,7 @@ def sparsified_kmeans_best(X, seed: int, m: int, K: int, T: int, R: int, nthread
         if best is None or objs[r, T - 1] < objs[best[0], T - 1]:
             best = (r, mu, assign)
     r, mu, assign = best
-    return {"vals": vals, "idx": idx, "best": r, "objectives": objs, "centers_pre": mu, "assign": assign,
-            "centers": unmix(seed, mu)}
+    return {"best": r, "objectives": objs, "centers_pre": mu, "assign": assign}
 
 
 def principal_components(C, k: int):

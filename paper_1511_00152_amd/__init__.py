@@ -13,7 +13,7 @@ the current HIP device; every call enqueues the library's kernels on
 import ctypes
 
 from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_F32, PDS_F64,
-                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_MEAN, PDS_OP_KMEANSPP, PDS_EXPLAINED_WS_BYTES, PDS_SPLIT_BF16, EXPORTS, PdsError,
+                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_MEAN, PDS_OP_KMEANSPP, PDS_OP_KMEANS_BEST, PDS_EXPLAINED_WS_BYTES, PDS_SPLIT_BF16, EXPORTS, PdsError,
                    check, lib)
 
 __all__ = [
@@ -237,10 +237,10 @@ def explained_variance(X, comps, out=None, ws=None):
     return out
 
 
-def kmeanspp(plan: Plan, vals, idx, K: int, centers=None, chosen=None, ws=None):
+def kmeanspp(plan: Plan, vals, idx, K: int, centers=None, chosen=None, ws=None, replicate: int = 0):
     """K-means++ seeding (Alg. 1) on the compressed samples with the plan's
-    seed: returns (centers K x p FP64, zero-filled compressed vectors of the
-    chosen samples; chosen (K,) int64)."""
+    seed and starting point `replicate`: returns (centers K x p FP64,
+    zero-filled compressed vectors of the chosen samples; chosen (K,) int64)."""
     import torch
 
     n = vals.shape[0]
@@ -252,9 +252,30 @@ def kmeanspp(plan: Plan, vals, idx, K: int, centers=None, chosen=None, ws=None):
         chosen = torch.empty(K, dtype=torch.int64, device=dev)
     if ws is None:
         ws = plan.workspace(PDS_OP_KMEANSPP, n, device=dev)
-    check(lib().pds_kmeanspp(plan.handle, _ptr(vals), _ptr(idx), n, K, _ptr(centers), _ptr(chosen), _ptr(ws),
-                             ws.numel() if ws is not None else 0, _stream()), "pds_kmeanspp")
+    check(lib().pds_kmeanspp(plan.handle, _ptr(vals), _ptr(idx), n, K, int(replicate), _ptr(centers), _ptr(chosen),
+                             _ptr(ws), ws.numel() if ws is not None else 0, _stream()), "pds_kmeanspp")
     return centers, chosen
+
+
+def kmeans_best(plan: Plan, vals, idx, K: int, T: int, R: int, ws=None):
+    """Sparsified K-means from R K-means++ starting points, T rounds each, the
+    start with the smallest final objective kept (all on the device): returns
+    (centers K x p FP64 preconditioned domain, assign (n,) int32, objectives
+    (R, T) FP64, best (1,) int32)."""
+    import torch
+
+    n = vals.shape[0]
+    dev = vals.device
+    centers = torch.empty((int(K), plan.p), dtype=torch.float64, device=dev)
+    assign = torch.empty(n, dtype=torch.int32, device=dev)
+    objs = torch.empty((int(R), int(T)), dtype=torch.float64, device=dev)
+    best = torch.empty(1, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = plan.workspace(PDS_OP_KMEANS_BEST, n, int(K), device=dev)
+    check(lib().pds_kmeans_best(plan.handle, _ptr(vals), _ptr(idx), n, int(K), int(T), int(R), _ptr(centers),
+                                _ptr(assign), _ptr(objs), _ptr(best), _ptr(ws), ws.numel() if ws is not None else 0,
+                                _stream()), "pds_kmeans_best")
+    return centers, assign, objs, best
 
 
 def kmeans_step(plan: Plan, vals, idx, centers, out=None, assign=None, objective=None, ws=None):

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/pds.h"
@@ -187,6 +188,8 @@ pds_status pds_signs(pds_plan plan, int8_t* D_host)
     return PDS_OK;
 }
 
+static size_t kmeans_best_workspace(int prec, int p, int m, int64_t n, int K, const pds::DeviceInfo& dev);
+
 pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, size_t* bytes)
 {
     if (pds_status st = check_plan(plan)) return st;
@@ -214,6 +217,10 @@ pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, s
             return PDS_OK;
         case PDS_OP_KMEANSPP:
             *bytes = pds::kmeanspp_workspace(n);
+            return PDS_OK;
+        case PDS_OP_KMEANS_BEST:
+            if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
+            *bytes = kmeans_best_workspace(plan->prec, p, m, n, K, dev);
             return PDS_OK;
         default:
             return fail(PDS_E_ARG, "unknown op %d", (int)op);
@@ -320,19 +327,76 @@ pds_status pds_explained_variance(const double* U, int32_t k, const void* X, int
     return PDS_OK;
 }
 
-pds_status pds_kmeanspp(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, double* centers,
-                        int64_t* chosen, void* ws, size_t ws_bytes, void* stream)
+pds_status pds_kmeanspp(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, int32_t replicate,
+                        double* centers, int64_t* chosen, void* ws, size_t ws_bytes, void* stream)
 {
     if (pds_status st = check_plan(plan)) return st;
     if (n < 1) return fail(PDS_E_ARG, "kmeanspp: n = %lld < 1", (long long)n);
     if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
+    if (replicate < 0) return fail(PDS_E_ARG, "replicate = %d < 0", (int)replicate);
     if (!vals || !idx || !centers) return fail(PDS_E_ARG, "vals, idx and centers must be non-NULL");
     const size_t need = pds::kmeanspp_workspace(n);
     if (!ws || ws_bytes < need)
         return fail(PDS_E_WORKSPACE, "kmeanspp needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
-    hipError_t e = pds::launch_kmeanspp(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, K, plan->seed, centers,
-                                        chosen, ws, reinterpret_cast<hipStream_t>(stream));
+    hipError_t e = pds::launch_kmeanspp(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, K, plan->seed,
+                                        (uint64_t)replicate, centers, chosen, ws, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "kmeanspp");
+    return PDS_OK;
+}
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace of pds_kmeans_best: the K-means step's, the seeding's, two center
+// buffers and one assignment buffer.
+static size_t kmeans_best_workspace(int prec, int p, int m, int64_t n, int K, const pds::DeviceInfo& dev)
+{
+    return al256(pds::kmeans_workspace(prec, p, m, n, K, dev)) + al256(pds::kmeanspp_workspace(n)) +
+           2 * al256((size_t)K * p * sizeof(double)) + al256((size_t)n * sizeof(int32_t));
+}
+
+pds_status pds_kmeans_best(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, int32_t T,
+                           int32_t R, double* centers_out, int32_t* assign_out, double* objectives, int32_t* best,
+                           void* ws, size_t ws_bytes, void* stream)
+{
+    if (pds_status st = check_plan(plan)) return st;
+    if (n < 1) return fail(PDS_E_ARG, "kmeans_best: n = %lld < 1", (long long)n);
+    if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
+    if (T < 1 || R < 1 || R > 1024) return fail(PDS_E_ARG, "T = %d, R = %d: need T >= 1 and 1 <= R <= 1024", T, R);
+    if (!vals || !idx || !centers_out || !assign_out || !objectives || !best)
+        return fail(PDS_E_ARG, "vals, idx, centers_out, assign_out, objectives and best must be non-NULL");
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_kmeans_best");
+    const int p = (int)plan->p, m = (int)plan->m;
+    const size_t need = kmeans_best_workspace(plan->prec, p, m, n, K, dev);
+    if (!ws || ws_bytes < need)
+        return fail(PDS_E_WORKSPACE, "kmeans_best needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+    const size_t km_bytes = pds::kmeans_workspace(plan->prec, p, m, n, K, dev);
+    void* km_ws = w;
+    w += al256(km_bytes);
+    void* pp_ws = w;
+    w += al256(pds::kmeanspp_workspace(n));
+    double* ca = reinterpret_cast<double*>(w);
+    w += al256((size_t)K * p * sizeof(double));
+    double* cb = reinterpret_cast<double*>(w);
+    w += al256((size_t)K * p * sizeof(double));
+    int32_t* asg = reinterpret_cast<int32_t*>(w);
+    for (int r = 0; r < R; ++r) {
+        e = pds::launch_kmeanspp(plan->prec, p, m, vals, idx, n, K, plan->seed, (uint64_t)r, ca, nullptr, pp_ws, s);
+        if (e != hipSuccess) return hip_fail(e, "kmeans_best seeding");
+        double* a = ca;
+        double* c = cb;
+        for (int t = 0; t < T; ++t) {
+            e = pds::launch_kmeans_step(plan->prec, p, m, vals, idx, n, K, a, c, asg,
+                                        objectives + (int64_t)r * T + t, km_ws, km_bytes, dev, s);
+            if (e != hipSuccess) return hip_fail(e, "kmeans_best round");
+            std::swap(a, c);
+        }
+        e = pds::launch_keep_best(r, T, objectives, a, (int64_t)K * p, asg, n, centers_out, assign_out, best, dev, s);
+        if (e != hipSuccess) return hip_fail(e, "kmeans_best keep");
+    }
     return PDS_OK;
 }
 

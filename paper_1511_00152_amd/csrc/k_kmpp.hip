@@ -30,9 +30,9 @@ constexpr int kPPDistThreads = 256;    // samples per dist workgroup (one block 
 constexpr int kPPSelThreads = 1024;
 constexpr int kPPCenterLds = 65536;    // center row in LDS up to this many bytes
 
-__device__ inline double pp_uniform(uint64_t seed, int k)
+__device__ inline double pp_uniform(uint64_t seed, uint64_t rep, int k)
 {
-    const u64x4 b = philox_block((uint64_t)(k >> 2), 0, 2, 0, seed, 0);
+    const u64x4 b = philox_block((uint64_t)(k >> 2), rep, 2, 0, seed, 0);
     return (double)(b.w[k & 3] >> 11) * (1.0 / 9007199254740992.0);
 }
 
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kPPDistThreads) void k_pp_dist(const T* __restrict_
 template <typename T>
 __global__ __launch_bounds__(kPPSelThreads) void k_pp_select(const T* __restrict__ vals,
                                                             const uint16_t* __restrict__ idx, int64_t n, int m,
-                                                            int p, uint64_t seed, int k,
+                                                            int p, uint64_t seed, uint64_t rep, int k,
                                                             const double* __restrict__ d2,
                                                             const double* __restrict__ bsum, int64_t nb,
                                                             double* __restrict__ centers,
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kPPSelThreads) void k_pp_select(const T* __restrict
     __shared__ double scan[kPPSelThreads];
     __shared__ int64_t pick;
     const int t = threadIdx.x;
-    const double u = pp_uniform(seed, k);
+    const double u = pp_uniform(seed, rep, k);
     if (k == 0) {
         if (t == 0) {
             int64_t c = (int64_t)(u * (double)n);
@@ -203,7 +203,7 @@ size_t kmeanspp_workspace(int64_t n)
 
 template <typename T>
 static hipError_t launch_pp_t(int p, int m, const T* vals, const uint16_t* idx, int64_t n, int K, uint64_t seed,
-                              double* centers, int64_t* chosen, void* ws, hipStream_t s)
+                              uint64_t rep, double* centers, int64_t* chosen, void* ws, hipStream_t s)
 {
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     double* d2 = reinterpret_cast<double*>(w);
@@ -223,8 +223,8 @@ static hipError_t launch_pp_t(int p, int m, const T* vals, const uint16_t* idx, 
     for (int k = 0; k < K; ++k) {
         {
             ProfScope ps_("kmpp_select", s);
-            hipLaunchKernelGGL((k_pp_select<T>), dim3(1), dim3(kPPSelThreads), 0, s, vals, idx, n, m, p, seed, k, d2,
-                               bsum, nb, centers, chosen);
+            hipLaunchKernelGGL((k_pp_select<T>), dim3(1), dim3(kPPSelThreads), 0, s, vals, idx, n, m, p, seed, rep, k,
+                               d2, bsum, nb, centers, chosen);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -246,11 +246,47 @@ static hipError_t launch_pp_t(int p, int m, const T* vals, const uint16_t* idx, 
 }
 
 hipError_t launch_kmeanspp(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, int K,
-                           uint64_t seed, double* centers, int64_t* chosen, void* ws, hipStream_t s)
+                           uint64_t seed, uint64_t rep, double* centers, int64_t* chosen, void* ws, hipStream_t s)
 {
     if (prec == 0)
-        return launch_pp_t(p, m, reinterpret_cast<const double*>(vals), idx, n, K, seed, centers, chosen, ws, s);
-    return launch_pp_t(p, m, reinterpret_cast<const float*>(vals), idx, n, K, seed, centers, chosen, ws, s);
+        return launch_pp_t(p, m, reinterpret_cast<const double*>(vals), idx, n, K, seed, rep, centers, chosen, ws, s);
+    return launch_pp_t(p, m, reinterpret_cast<const float*>(vals), idx, n, K, seed, rep, centers, chosen, ws, s);
+}
+
+// Best of several starting points: after start r's last round, its centers and
+// assignments replace the kept ones when its final objective is below every
+// earlier start's (so ties keep the earliest).  Every thread takes the
+// decision from the objectives alone, so no workgroup waits for another.
+__global__ __launch_bounds__(256) void k_keep_best(int r, int T, const double* __restrict__ obj,
+                                                   const double* __restrict__ centers, int64_t kp,
+                                                   const int32_t* __restrict__ assign, int64_t n,
+                                                   double* __restrict__ centers_best,
+                                                   int32_t* __restrict__ assign_best, int32_t* __restrict__ best)
+{
+    const double mine = obj[(int64_t)r * T + T - 1];
+    bool take = true;
+    for (int q = 0; q < r; ++q)
+        if (!(mine < obj[(int64_t)q * T + T - 1])) take = false;
+    if (!take) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < kp + n; e += stride) {
+        if (e < kp)
+            centers_best[e] = centers[e];
+        else
+            assign_best[e - kp] = assign[e - kp];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *best = r;
+}
+
+hipError_t launch_keep_best(int r, int T, const double* obj, const double* centers, int64_t kp, const int32_t* assign,
+                            int64_t n, double* centers_best, int32_t* assign_best, int32_t* best, const DeviceInfo& dev,
+                            hipStream_t s)
+{
+    int64_t grid = (kp + n + 255) / 256;
+    if (grid > (int64_t)dev.cus * 4) grid = (int64_t)dev.cus * 4;
+    hipLaunchKernelGGL(k_keep_best, dim3((unsigned)grid), dim3(256), 0, s, r, T, obj, centers, kp, assign, n,
+                       centers_best, assign_best, best);
+    return hipGetLastError();
 }
 
 }  // namespace pds

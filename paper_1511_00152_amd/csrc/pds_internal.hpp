@@ -66,7 +66,10 @@ hipError_t launch_explained(const double* U, int k, const void* X, int x_f64, in
 // ---- K-means++ seeding ------------------------------------------------------
 size_t kmeanspp_workspace(int64_t n);
 hipError_t launch_kmeanspp(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, int K,
-                           uint64_t seed, double* centers, int64_t* chosen, void* ws, hipStream_t s);
+                           uint64_t seed, uint64_t rep, double* centers, int64_t* chosen, void* ws, hipStream_t s);
+hipError_t launch_keep_best(int r, int T, const double* obj, const double* centers, int64_t kp, const int32_t* assign,
+                            int64_t n, double* centers_best, int32_t* assign_best, int32_t* best, const DeviceInfo& dev,
+                            hipStream_t s);
 
 // ---- K-means ----------------------------------------------------------------
 size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceInfo& dev);

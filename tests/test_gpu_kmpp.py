@@ -39,8 +39,8 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def uniform(seed, k):
-    w = ref.philox4x64_10([k // 4, 0, 2, 0], [seed, 0])[k % 4]
+def uniform(seed, k, r=0):
+    w = ref.philox4x64_10([k // 4, r, 2, 0], [seed, 0])[k % 4]
     return float(int(w) >> 11) * 2.0 ** -53
 
 
@@ -52,15 +52,15 @@ def sparse_d2(vals, idx, centers):
     return d
 
 
-def check_seeding(seed, vals, idx, K, centers_g, chosen_g):
+def check_seeding(seed, vals, idx, K, centers_g, chosen_g, r=0):
     n = vals.shape[0]
-    C_o, ch_o = ref.kmeanspp(seed, centers_g.shape[1], vals, idx, K)
+    C_o, ch_o = ref.kmeanspp(seed, centers_g.shape[1], vals, idx, K, r)
     for k in range(K):
         if chosen_g[k] != ch_o[k]:
             assert k > 0, "the first center is u n and cannot differ"
             d2 = sparse_d2(vals, idx, C_o[:k])
             run = np.cumsum(d2)
-            target = uniform(seed, k) * run[-1]
+            target = uniform(seed, k, r) * run[-1]
             slack = 4 * n * U_RND * run[-1]
             c = int(chosen_g[k])
             lo = run[c - 1] if c > 0 else 0.0
@@ -110,6 +110,56 @@ def test_kmeanspp_pipeline_matches_oracle():
     assert np.max(np.abs(C.cpu().numpy() - C_o)) <= 1e-13 * np.max(np.abs(C_o))
 
 
+@pytest.mark.parametrize("r", [1, 5, 1023])
+def test_kmeanspp_replicates_match_oracle(r):
+    p, m, n, K = 512, 51, 6000, 12
+    log(f"kmeanspp replicate {r}")
+    d = synth.random_compressed(n, p, m, seed=99, dtype=np.float32)
+    plan = pds.Plan(p, m, seed=8, prec=pds.PDS_F32)
+    C, ch = pds.kmeanspp(plan, to_dev(d["vals"]), to_dev(d["idx"].view(np.int16)), K, replicate=r)
+    torch.cuda.synchronize()
+    assert check_seeding(8, d["vals"].astype(np.float64), d["idx"], K, C.cpu().numpy(), ch.cpu().numpy(), r) >= 1
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_kmeans_best_of_r_matches_oracle(prec):
+    """Best of R starting points on one compression (mixture shape, reduced
+    n): the same kept start, per-start objectives, final centers and
+    assignments as the oracle's.  FP64: GPU compress against the oracle's
+    compress of the same rows.  FP32: both sides take the oracle's compressed
+    values rounded to FP32 (so the seeding draws see the same numbers);
+    objectives to FP32 rounding of the distances, and the kept start must
+    agree unless two starts end within that rounding of each other."""
+    pr, dt = {"f64": (pds.PDS_F64, np.float64), "f32": (pds.PDS_F32, np.float32)}[prec]
+    w = synth.WORKLOADS["mixture_f32"]
+    p, K = w["p"], w["K"]
+    m = synth.m_from_gamma(w["gamma"], p)
+    n, T, R = 6000, 5, 6
+    X = synth.rows_numpy("mixture_f32", n).astype(np.float64)
+    log(f"kmeans best-of-{R} p={p} m={m} n={n} K={K} T={T} prec={prec}")
+    plan = pds.Plan(p, m, seed=2, prec=pr)
+    if prec == "f64":
+        vals, idx = pds.compress(plan, to_dev(X))
+        o = ref.sparsified_kmeans_best(X, 2, m, K, T, R)
+    else:
+        ov, oi = ref.compress(X, 2, m)
+        v32 = ov.astype(np.float32)
+        vals, idx = to_dev(v32), to_dev(oi.view(np.int16))
+        o = ref.kmeans_best_compressed(p, v32.astype(np.float64), oi, 2, K, T, R)
+    C, a, objs, best = pds.kmeans_best(plan, vals, idx, K, T, R)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == "f64" else 1e-5
+    og = objs.cpu().numpy()
+    assert np.max(np.abs(og - o["objectives"]) / o["objectives"]) <= tol
+    final = o["objectives"][:, -1]
+    b = int(best.cpu()[0])
+    if b != o["best"]:
+        assert prec == "f32" and abs(final[b] - final[o["best"]]) <= 2 * tol * final[o["best"]], (b, o["best"])
+        return
+    assert np.array_equal(a.cpu().numpy(), o["assign"])
+    assert np.max(np.abs(C.cpu().numpy() - o["centers_pre"])) <= tol * np.max(np.abs(o["centers_pre"]))
+
+
 def test_kmeanspp_argument_errors():
     plan = pds.Plan(64, 8, prec=pds.PDS_F32)
     vals = torch.zeros((10, 8), dtype=torch.float32, device="cuda")
@@ -122,3 +172,9 @@ def test_kmeanspp_argument_errors():
         pds.kmeanspp(plan, vals[:0], idx[:0], 3)
     with pytest.raises(pds.PdsError):
         pds.kmeanspp(plan, vals, idx, 3, ws=torch.empty(8, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(pds.PdsError):
+        pds.kmeanspp(plan, vals, idx, 3, replicate=-1)
+    with pytest.raises(pds.PdsError):
+        pds.kmeans_best(plan, vals, idx, 3, 0, 2)
+    with pytest.raises(pds.PdsError):
+        pds.kmeans_best(plan, vals, idx, 3, 2, 0)
