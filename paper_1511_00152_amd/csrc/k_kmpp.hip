@@ -68,21 +68,39 @@ __global__ __launch_bounds__(kPPDistThreads) void k_pp_dist(const T* __restrict_
     const int t = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * kPPDistThreads;
     const int rows = n - i0 < kPPDistThreads ? (int)(n - i0) : kPPDistThreads;
-    double d = 0.0;
-    for (int e0 = 0; e0 < m; e0 += E) {
+    // a thread's share of a chunk: E entries, all loads in flight together;
+    // the next chunk's loads are issued before the current chunk is summed
+    T rv[E];
+    uint32_t ri[E];
+    auto load = [&](int e0) {
         const int ne = m - e0 < E ? m - e0 : E;
-        __syncthreads();
 #pragma unroll
-        for (int sidx = 0; sidx < E; ++sidx) {  // all of a thread's loads in flight together
+        for (int sidx = 0; sidx < E; ++sidx) {
             const int q = t + sidx * kPPDistThreads;
             const int r = q / E, cc = q % E;
             if (r < rows && cc < ne) {
                 const int64_t g = (i0 + r) * m + e0 + cc;
-                sv[r * (E + 1) + cc] = vals[g];
-                si[r * (E + 1) + cc] = idx[g];
+                rv[sidx] = vals[g];
+                ri[sidx] = idx[g];
+            }
+        }
+    };
+    double d = 0.0;
+    load(0);
+    for (int e0 = 0; e0 < m; e0 += E) {
+        const int ne = m - e0 < E ? m - e0 : E;
+        __syncthreads();
+#pragma unroll
+        for (int sidx = 0; sidx < E; ++sidx) {
+            const int q = t + sidx * kPPDistThreads;
+            const int r = q / E, cc = q % E;
+            if (r < rows && cc < ne) {
+                sv[r * (E + 1) + cc] = rv[sidx];
+                si[r * (E + 1) + cc] = ri[sidx];
             }
         }
         __syncthreads();
+        if (e0 + E < m) load(e0 + E);
         if (t < rows) {
             for (int cc = 0; cc < ne; ++cc) {
                 const uint32_t j = si[t * (E + 1) + cc];
