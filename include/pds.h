@@ -165,6 +165,20 @@ pds_status pds_sample_mean(pds_plan plan, const void* vals, const uint16_t* idx,
                            int32_t finalize, int64_t n_total, double* mean_out, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* Rows of a dimension that is not a power of two, widened for a plan: Xp[r][j]
+ * = X[r][j] for j < p_data and 0 for p_data <= j < p_pad.  The Hadamard
+ * transform of Sec. III needs p a power of two (the paper used a DCT for
+ * p = 784); compressing the zero-padded rows with a plan of p = p_pad keeps
+ * norms, and the padded coordinates of means, covariances and centers mapped
+ * back by pds_unmix estimate zero (drop them).
+ *   X: device, n x p_data rows, leading dimension ldx >= p_data; Xp: device,
+ *   n x p_pad rows, contiguous; double when x_prec = PDS_F64, float when
+ *   PDS_F32.  Must not alias.
+ * Errors: PDS_E_ARG (null pointers, n < 0, p_data < 1, p_pad < p_data,
+ * ldx < p_data, x_prec, aliasing). */
+pds_status pds_pad_rows(const void* X, int32_t x_prec, int64_t n, int64_t p_data, int64_t ldx, void* Xp, int64_t p_pad,
+                        void* stream);
+
 /* Fraction of explained variance of k principal components (Sec. II,
  * comparison with column sampling; PCA on the estimate of Sec. V), FP64:
  *   out2[0] = sum_i sum_j (x_i . U[j])^2 = ||X U^T||_F^2,

@@ -84,11 +84,31 @@ class Plan:
         return torch.empty(nb, dtype=torch.uint8, device=device or "cuda")
 
 
+def pad_rows(X, p_pad: int, out=None):
+    """Rows of X (n x p_data, p_data <= p_pad) zero-padded to width p_pad on
+    the device (pds_pad_rows)."""
+    import torch
+
+    n, pd = X.shape
+    if X.stride(1) != 1:
+        raise ValueError("X rows must be contiguous")
+    if out is None:
+        out = torch.empty((n, int(p_pad)), dtype=X.dtype, device=X.device)
+    xp = PDS_F64 if X.dtype == torch.float64 else PDS_F32
+    check(lib().pds_pad_rows(_ptr(X), xp, n, pd, X.stride(0), _ptr(out), int(p_pad), _stream()), "pds_pad_rows")
+    return out
+
+
 def compress(plan: Plan, X, i0: int = 0, vals=None, idx=None, ws=None):
-    """Returns (vals n x m, idx n x m uint16 as torch.int16 storage)."""
+    """Returns (vals n x m, idx n x m uint16 as torch.int16 storage).  Rows
+    narrower than the plan's p (a dimension that is not a power of two) are
+    zero-padded first (pad_rows)."""
     import torch
 
     n, p = X.shape
+    if p < plan.p:
+        X = pad_rows(X, plan.p)
+        p = plan.p
     if p != plan.p:
         raise ValueError(f"X has {p} columns, plan has p={plan.p}")
     if X.dtype != plan.dtype:

@@ -33,7 +33,7 @@ PDS_EXPLAINED_WS_BYTES = 16384
 # every entry point declared in include/pds.h
 EXPORTS = (
     "pds_plan_create", "pds_plan_destroy", "pds_signs", "pds_workspace_size", "pds_covariance_acc_size",
-    "pds_compress", "pds_covariance", "pds_kmeans_step", "pds_unmix", "pds_kmeans_2pass", "pds_sample_mean", "pds_explained_variance", "pds_kmeanspp", "pds_kmeans_best", "pds_profile_enable", "pds_profile_report",
+    "pds_compress", "pds_covariance", "pds_kmeans_step", "pds_unmix", "pds_kmeans_2pass", "pds_sample_mean", "pds_explained_variance", "pds_kmeanspp", "pds_kmeans_best", "pds_pad_rows", "pds_profile_enable", "pds_profile_report",
     "pds_last_error", "pds_version",
     "pds_row_moments", "pds_frob_diff", "pds_msel_workspace_size", "pds_msel_label", "pds_msel_features",
     "pds_mlp_param_count", "pds_mlp_forward", "pds_mlp_backward", "pds_mlp_adam", "pds_mlp_pack_bf16",
@@ -89,6 +89,7 @@ def lib():
     L.pds_sample_mean.argtypes = [P, P, P, i64, P, i32, i64, P, P, sz, P]
     L.pds_kmeanspp.argtypes = [P, P, P, i64, i32, i32, P, P, P, sz, P]
     L.pds_kmeans_best.argtypes = [P, P, P, i64, i32, i32, i32, P, P, P, P, P, sz, P]
+    L.pds_pad_rows.argtypes = [P, i32, i64, i64, i64, P, i64, P]
     L.pds_explained_variance.argtypes = [P, i32, P, i32, i64, i64, i64, P, P, sz, P]
     L.pds_profile_enable.argtypes = [i32]
     L.pds_profile_report.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(sz)]

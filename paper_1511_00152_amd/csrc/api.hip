@@ -310,6 +310,25 @@ pds_status pds_sample_mean(pds_plan plan, const void* vals, const uint16_t* idx,
     return PDS_OK;
 }
 
+pds_status pds_pad_rows(const void* X, int32_t x_prec, int64_t n, int64_t p_data, int64_t ldx, void* Xp, int64_t p_pad,
+                        void* stream)
+{
+    if (n < 0) return fail(PDS_E_ARG, "n < 0");
+    if (n == 0) return PDS_OK;
+    if (!X || !Xp) return fail(PDS_E_ARG, "X and Xp must be non-NULL");
+    if (p_data < 1 || p_pad < p_data || ldx < p_data)
+        return fail(PDS_E_ARG, "need 1 <= p_data <= p_pad and ldx >= p_data (p_data = %lld, p_pad = %lld, ldx = %lld)",
+                    (long long)p_data, (long long)p_pad, (long long)ldx);
+    if (x_prec != PDS_F64 && x_prec != PDS_F32) return fail(PDS_E_ARG, "x_prec must be PDS_F64 or PDS_F32");
+    if (X == Xp) return fail(PDS_E_ARG, "X and Xp must not alias");
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_pad_rows");
+    e = pds::launch_pad_rows(x_prec == PDS_F64, X, n, p_data, ldx, Xp, p_pad, dev, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pad_rows");
+    return PDS_OK;
+}
+
 pds_status pds_explained_variance(const double* U, int32_t k, const void* X, int32_t x_prec, int64_t n, int64_t p,
                                   int64_t ldx, double* out2, void* ws, size_t ws_bytes, void* stream)
 {

@@ -57,6 +57,9 @@ hipError_t launch_mean(int prec, int p, int m, const void* vals, const uint16_t*
                        int finalize, int64_t n_total, double* mean_out, void* ws, const DeviceInfo& dev,
                        hipStream_t s);
 
+hipError_t launch_pad_rows(int x_f64, const void* X, int64_t n, int64_t p_data, int64_t ldx, void* Xp, int64_t p_pad,
+                           const DeviceInfo& dev, hipStream_t s);
+
 // ---- PCA quality -------------------------------------------------------------
 size_t explained_workspace();
 int explained_max_k();

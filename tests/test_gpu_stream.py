@@ -1,0 +1,110 @@
+"""Dimensions that are not a power of two (zero padding) and out-of-core
+streaming from host memory, on the GPU against the oracle.
+
+Padding: the oracle compresses the rows padded by numpy; the GPU pads on the
+device.  Streaming: the oracle takes all rows at once; the GPU copies chunks
+through pinned buffers and accumulates.  Bars as in the one-shot tests:
+indices bit-exact; covariance 1e-12 (FP64) / 1e-5 (FP32) of its largest
+entry; the sample mean within the recursive-summation bound (FP64) or the
+FP32 rounding of the transformed values (1e-5 of each row's largest value,
+summed per coordinate; FP64 adds 1e-13 of it for the transform's rounding).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1511_00152_amd as pds  # noqa: E402
+import synth  # noqa: E402
+from oracle import ref  # noqa: E402
+from paper_1511_00152_amd.stream import stream_estimates  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+U_RND = 2.0 ** -53
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def nerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def mean_bound(vals, idx, p, m, n, f32):
+    flat = idx.ravel().astype(np.int64)
+    rowmax = (np.max(np.abs(vals), axis=1, keepdims=True) * np.ones_like(vals)).ravel()
+    if f32:
+        w = 1e-5 * rowmax
+    else:
+        # summation order, plus the FP64 rounding of the transformed values
+        cnt = np.bincount(flat, minlength=p)[flat].astype(np.float64)
+        w = 2.0 * (cnt + 1.0) * U_RND * np.abs(vals).ravel() + 1e-13 * rowmax
+    return np.bincount(flat, weights=w, minlength=p) * (p / (m * n)) + 1e-300
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_pad_rows_matches_numpy(dt):
+    n, pd, ld, pp = 333, 784, 800, 1024
+    X = np.random.default_rng(3).standard_normal((n, ld)).astype(dt)
+    Xd = to_dev(X)[:, :pd]
+    Xp = pds.pad_rows(Xd, pp)
+    torch.cuda.synchronize()
+    assert np.array_equal(Xp.cpu().numpy(), np.pad(X[:, :pd], ((0, 0), (0, pp - pd))))
+
+
+def test_pad_rows_argument_errors():
+    X = torch.zeros((4, 10), dtype=torch.float32, device="cuda")
+    with pytest.raises(pds.PdsError):
+        pds.pad_rows(X, 8)  # p_pad < p_data
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "split"])
+def test_compress_padded_rows_matches_oracle(prec):
+    """p = 784 (the paper's image dimension) on a plan of p = 1024."""
+    pr, dt, tol = {"f64": (pds.PDS_F64, np.float64, 1e-13), "f32": (pds.PDS_F32, np.float32, 1e-6),
+                   "split": (pds.PDS_SPLIT_BF16, np.float32, 1e-6)}[prec]
+    n, pd, p, m = 1000, 784, 1024, 51
+    log(f"compress padded p_data={pd} p={p} prec={prec}")
+    X = synth.rows_numpy("mixture_f32", n)[:, :pd].astype(dt)
+    plan = pds.Plan(p, m, seed=5, prec=pr)
+    vals, idx = pds.compress(plan, to_dev(X))
+    torch.cuda.synchronize()
+    ov, oi = ref.compress(np.pad(X, ((0, 0), (0, p - pd))), 5, m)
+    assert np.array_equal(idx.cpu().numpy().view(np.uint16), oi)
+    assert nerr(vals.cpu().numpy().astype(np.float64), ov) <= tol
+
+
+@pytest.mark.parametrize("prec,pd,p,chunk", [("f64", 512, 512, 1300), ("f32", 784, 1024, 1300),
+                                             ("split", 784, 1024, 4999), ("f32", 256, 256, 10000)])
+def test_stream_estimates_match_oracle(prec, pd, p, chunk):
+    pr, dt, ctol = {"f64": (pds.PDS_F64, np.float64, 1e-12), "f32": (pds.PDS_F32, np.float32, 1e-5),
+                    "split": (pds.PDS_SPLIT_BF16, np.float32, 1e-5)}[prec]
+    n = 5000
+    m = max(2, p // 10)
+    log(f"stream_estimates p_data={pd} p={p} m={m} n={n} chunk={chunk} prec={prec}")
+    X = synth.rows_numpy("mixture_f32", n)[:, :pd].astype(dt)
+    plan = pds.Plan(p, m, seed=7, prec=pr)
+    C, mu = stream_estimates(plan, X, chunk)
+    Xp = np.pad(X, ((0, 0), (0, p - pd)))
+    ov, oi = ref.compress(Xp, 7, m)
+    C_o = ref.covariance(p, ov, oi)
+    mu_o = ref.mean_estimate(p, ov, oi)
+    Cg = C.cpu().numpy()
+    assert np.array_equal(Cg, Cg.T)
+    assert nerr(Cg, C_o) <= ctol, nerr(Cg, C_o)
+    b = mean_bound(ov, oi, p, m, n, dt == np.float32)
+    err = np.abs(mu.cpu().numpy() - mu_o)
+    assert np.all(err <= b), float(np.max(err / b))
