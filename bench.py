@@ -437,6 +437,28 @@ def run_pca(pds, plan, C, X, name, k=20):
             "top_eigenvalues": [float(v) for v in lam[:5].cpu()]}
 
 
+def run_stream(pds, X, p, m, nrows=1 << 18, chunk=1 << 15):
+    """Out-of-core form: the first nrows rows of the workload in pinned host
+    memory, streamed in chunks to the device (copies overlapping compression,
+    covariance and mean accumulation); the PCIe-inclusive rate, not the
+    metric's value."""
+    import torch
+
+    from paper_1511_00152_amd.stream import stream_estimates
+
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_SPLIT_BF16)
+    Xh = torch.empty((nrows, p), dtype=X.dtype, pin_memory=True)
+    Xh.copy_(X[:nrows])
+    stream_estimates(plan, Xh[:chunk], chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stream_estimates(plan, Xh, chunk)
+    t = time.perf_counter() - t0
+    gb = nrows * p * X.element_size() / 1e9
+    return {"what": f"{nrows} rows from pinned host memory in chunks of {chunk}: copy + compress + covariance + mean",
+            "s": t, "samples_per_s": nrows / t, "host_to_device_gbs": gb / t}
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the FETCH_SIZE /
     WRITE_SIZE counters of a profiled run."""
@@ -551,6 +573,8 @@ def main():
     if not args.no_eigen:
         out["pca"] = run_pca(pds, res[head]["plan"], res[head]["C"], X, name)
         log(f"pca: {json.dumps(out['pca'])}")
+        out["streamed"] = run_stream(pds, X, p, m)
+        log(f"streamed: {json.dumps(out['streamed'])}")
     for v in res.values():
         v.pop("vals", None), v.pop("idx", None), v.pop("C", None)
     if not args.no_cpu_baseline:

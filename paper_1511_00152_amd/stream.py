@@ -2,11 +2,12 @@
 
 The paper's out-of-core runs load the data in chunks (about 1 GB each) and
 compress every chunk once, so the full matrix is never resident.  Here the
-chunks of a host array go through two pinned staging buffers: the copy of
-chunk c + 1 to the device runs on its own stream while chunk c is compressed
-and accumulated on the caller's stream, and events order the reuse of each
-buffer.  Every chunk is compressed with its global row offset (sample i keeps
-the coordinates of sample i whatever the chunking), then fed to the streaming
+chunks of a host array (through two pinned staging buffers unless the array
+is itself in pinned memory) are copied to two device buffers on a stream of
+their own, so the copy of chunk c + 1 runs while chunk c is compressed and
+accumulated on the caller's stream; events order the reuse of each buffer.
+Every chunk is compressed with its global row offset (sample i keeps the
+coordinates of sample i whatever the chunking), then fed to the streaming
 covariance and sample-mean accumulators, so the results equal a single call
 on all rows up to the order of FP64 additions.  Rows narrower than the plan's
 p are zero-padded on the device.
@@ -33,7 +34,11 @@ def stream_estimates(plan: Plan, X_host, chunk_rows: int, covariance: bool = Tru
         raise ValueError("need 1 <= n, 1 <= chunk_rows and columns <= plan.p")
     dev = torch.device("cuda", torch.cuda.current_device())
     chunk_rows = min(int(chunk_rows), n)
-    pinned = [torch.empty((chunk_rows, pd), dtype=plan.dtype, pin_memory=True) for _ in range(2)]
+    # rows already in pinned memory go to the device directly; others are
+    # staged through two pinned buffers first
+    direct = X_host.is_pinned() and X_host.is_contiguous()
+    pinned = [None, None] if direct else [torch.empty((chunk_rows, pd), dtype=plan.dtype, pin_memory=True)
+                                          for _ in range(2)]
     staged = [torch.empty((chunk_rows, pd), dtype=plan.dtype, device=dev) for _ in range(2)]
     copied = [torch.cuda.Event() for _ in range(2)]
     consumed = [torch.cuda.Event() for _ in range(2)]
@@ -48,13 +53,17 @@ def stream_estimates(plan: Plan, X_host, chunk_rows: int, covariance: bool = Tru
         b = min(a + chunk_rows, n)
         rows = b - a
         s = c % 2
-        if used[s]:
-            copied[s].synchronize()  # the previous copy out of pinned[s] is done
-        pinned[s][:rows].copy_(X_host[a:b])
+        if direct:
+            src = X_host[a:b]
+        else:
+            if used[s]:
+                copied[s].synchronize()  # the previous copy out of pinned[s] is done
+            pinned[s][:rows].copy_(X_host[a:b])
+            src = pinned[s][:rows]
         with torch.cuda.stream(copier):
             if used[s]:
                 copier.wait_event(consumed[s])  # staged[s] is free again
-            staged[s][:rows].copy_(pinned[s][:rows], non_blocking=True)
+            staged[s][:rows].copy_(src, non_blocking=True)
             copied[s].record(copier)
         used[s] = True
         compute.wait_event(copied[s])

@@ -87,17 +87,19 @@ def test_compress_padded_rows_matches_oracle(prec):
     assert nerr(vals.cpu().numpy().astype(np.float64), ov) <= tol
 
 
-@pytest.mark.parametrize("prec,pd,p,chunk", [("f64", 512, 512, 1300), ("f32", 784, 1024, 1300),
-                                             ("split", 784, 1024, 4999), ("f32", 256, 256, 10000)])
-def test_stream_estimates_match_oracle(prec, pd, p, chunk):
+@pytest.mark.parametrize("prec,pd,p,chunk,pin", [("f64", 512, 512, 1300, False), ("f32", 784, 1024, 1300, False),
+                                                 ("split", 784, 1024, 4999, False), ("f32", 256, 256, 10000, False),
+                                                 ("split", 4096, 4096, 1024, True), ("f64", 784, 1024, 700, True)])
+def test_stream_estimates_match_oracle(prec, pd, p, chunk, pin):
     pr, dt, ctol = {"f64": (pds.PDS_F64, np.float64, 1e-12), "f32": (pds.PDS_F32, np.float32, 1e-5),
                     "split": (pds.PDS_SPLIT_BF16, np.float32, 1e-5)}[prec]
     n = 5000
     m = max(2, p // 10)
-    log(f"stream_estimates p_data={pd} p={p} m={m} n={n} chunk={chunk} prec={prec}")
-    X = synth.rows_numpy("mixture_f32", n)[:, :pd].astype(dt)
+    log(f"stream_estimates p_data={pd} p={p} m={m} n={n} chunk={chunk} prec={prec} pinned={pin}")
+    X = synth.rows_numpy("spiked4096_f32" if pd > 1024 else "mixture_f32", n)[:, :pd].astype(dt)
+    assert X.shape == (n, pd)
     plan = pds.Plan(p, m, seed=7, prec=pr)
-    C, mu = stream_estimates(plan, X, chunk)
+    C, mu = stream_estimates(plan, torch.from_numpy(X).pin_memory() if pin else X, chunk)
     Xp = np.pad(X, ((0, 0), (0, p - pd)))
     ov, oi = ref.compress(Xp, 7, m)
     C_o = ref.covariance(p, ov, oi)
