@@ -108,3 +108,55 @@ def test_workspace_queries():
     assert pds.lib().pds_covariance_acc_size(plan.handle, ctypes.byref(b)) == 0 and b.value == 4096 * 4096 * 8
     # huge p needs a compress workspace (transform staging outside LDS)
     assert pds.Plan(65536, 10).workspace_size(0, 1000) > 0
+
+
+def test_estimator_calls_validate_before_device_work():
+    """The sample-mean, seeding, best-of-R, padding and explained-variance
+    calls reject bad arguments on the host (status codes, no device work)."""
+    L = pds.lib()
+    plan = pds.Plan(256, 26, prec=pds.PDS_F32)
+    h = plan.handle
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    # sample mean
+    assert L.pds_sample_mean(h, fake, fake, -1, fake, 0, 0, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_sample_mean(h, fake, fake, 4, null, 0, 0, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_sample_mean(h, null, fake, 4, fake, 0, 0, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_sample_mean(h, fake, fake, 4, fake, 1, 0, ctypes.c_void_p(0x2000), fake, 1 << 30, null) == \
+        _lib.PDS_E_ARG  # finalize with n_total = 0
+    assert L.pds_sample_mean(h, fake, fake, 4, fake, 1, 4, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG  # alias
+    assert L.pds_sample_mean(h, null, null, 0, fake, 0, 0, null, null, 0, null) == _lib.PDS_OK  # nothing to do
+    # K-means++ and best of R
+    assert L.pds_kmeanspp(h, fake, fake, 0, 3, 0, fake, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeanspp(h, fake, fake, 4, 0, 0, fake, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeanspp(h, fake, fake, 4, 3, -1, fake, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeanspp(h, fake, fake, 4, 3, 0, null, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_best(h, fake, fake, 4, 3, 0, 2, fake, fake, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_best(h, fake, fake, 4, 3, 2, 0, fake, fake, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_best(h, fake, fake, 4, 3, 2, 2, fake, fake, null, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    # padding and explained variance
+    assert L.pds_pad_rows(fake, pds.PDS_F32, 4, 10, 10, ctypes.c_void_p(0x2000), 8, null) == _lib.PDS_E_ARG
+    assert L.pds_pad_rows(fake, pds.PDS_F32, 4, 10, 9, ctypes.c_void_p(0x2000), 16, null) == _lib.PDS_E_ARG
+    assert L.pds_pad_rows(fake, pds.PDS_F32, 4, 10, 10, fake, 16, null) == _lib.PDS_E_ARG  # alias
+    assert L.pds_pad_rows(fake, 7, 4, 10, 10, ctypes.c_void_p(0x2000), 16, null) == _lib.PDS_E_ARG
+    assert L.pds_pad_rows(null, pds.PDS_F32, 0, 10, 10, null, 16, null) == _lib.PDS_OK
+    ws = _lib.PDS_EXPLAINED_WS_BYTES
+    assert L.pds_explained_variance(fake, 33, fake, pds.PDS_F32, 4, 8, 8, fake, fake, ws, null) == _lib.PDS_E_ARG
+    assert L.pds_explained_variance(fake, 2, fake, pds.PDS_F32, 4, 8, 7, fake, fake, ws, null) == _lib.PDS_E_ARG
+    assert L.pds_explained_variance(fake, 2, fake, pds.PDS_F32, 0, 8, 8, fake, fake, ws, null) == _lib.PDS_E_ARG
+    assert L.pds_explained_variance(fake, 2, fake, pds.PDS_F32, 4, 8, 8, fake, fake, ws - 1, null) == \
+        _lib.PDS_E_WORKSPACE
+
+
+def test_estimator_workspace_queries():
+    plan = pds.Plan(4096, 410, prec=pds.PDS_SPLIT_BF16)
+    assert plan.workspace_size(_lib.PDS_OP_MEAN, 0) == 0
+    mean = plan.workspace_size(_lib.PDS_OP_MEAN, 1 << 20)
+    assert 0 < mean <= 1024 * 4096 * 8 * 2  # a few partial rows per CU, not per sample
+    pp = pds.Plan(1024, 51).workspace_size(_lib.PDS_OP_KMEANSPP, 1 << 20)
+    assert pp >= (1 << 20) * 8  # D^2 per sample
+    km = pds.Plan(1024, 51).workspace_size(_lib.PDS_OP_KMEANS, 1 << 20, 10)
+    best = pds.Plan(1024, 51).workspace_size(_lib.PDS_OP_KMEANS_BEST, 1 << 20, 10)
+    assert best >= km + pp + 2 * 10 * 1024 * 8 + (1 << 20) * 4
+    b = ctypes.c_size_t()
+    assert pds.lib().pds_workspace_size(plan.handle, _lib.PDS_OP_KMEANS_BEST, 10, 0, ctypes.byref(b)) == _lib.PDS_E_ARG
