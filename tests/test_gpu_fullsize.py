@@ -97,3 +97,37 @@ def test_mixture_full_size_kmeans():
     Jg = out["objectives"].cpu().numpy()
     assert np.max(np.abs(Jg - np.array(objs)) / np.array(objs)) <= 1e-5
     assert nerr(out["centers"].cpu().numpy(), ref.unmix(0, mu_o)) <= 1e-5
+
+
+def test_mixture_full_size_kmeanspp_and_best_of():
+    """K-means++ at the mixture size (n = 2^20, p = 1024, m = 51, K = 10) in the
+    launch configuration the bench times: both sides seed from the oracle's
+    compressed values rounded to FP32 (the GPU plan's value type), so the
+    draws see the same numbers and the chosen samples agree exactly; then the
+    best of 3 starts with 2 rounds each against the oracle's."""
+    w = synth.WORKLOADS["mixture_f32"]
+    p, n, K = w["p"], w["n"], w["K"]
+    m = synth.m_from_gamma(w["gamma"], p)
+    X = synth.rows_torch("mixture_f32", n, device="cuda").cpu().numpy()
+    print(f"mixture full K-means++: n={n} p={p} m={m} K={K}", flush=True)
+    v_o, i_o = ref.compress(X, 0, m)
+    v32 = v_o.astype(np.float32)
+    v64 = v32.astype(np.float64)
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F32)
+    vals, idx = torch.from_numpy(v32).cuda(), torch.from_numpy(i_o.view(np.int16)).cuda()
+    C, ch = pds.kmeanspp(plan, vals, idx, K)
+    torch.cuda.synchronize()
+    C_o, ch_o = ref.kmeanspp(0, p, v64, i_o, K)
+    assert np.array_equal(ch.cpu().numpy(), ch_o)
+    assert np.array_equal(C.cpu().numpy(), C_o)
+    Cb, ab, objs, best = pds.kmeans_best(plan, vals, idx, K, 2, 3)
+    torch.cuda.synchronize()
+    o = ref.kmeans_best_compressed(p, v64, i_o, 0, K, 2, 3)
+    og = objs.cpu().numpy()
+    assert np.max(np.abs(og - o["objectives"]) / o["objectives"]) <= 1e-5
+    fin = o["objectives"][:, -1]
+    b = int(best.cpu()[0])
+    assert b == o["best"] or abs(fin[b] - fin[o["best"]]) <= 2e-5 * fin[o["best"]]
+    if b == o["best"]:
+        assert np.sum(ab.cpu().numpy() != o["assign"]) == 0
+        assert nerr(Cb.cpu().numpy(), o["centers_pre"]) <= 1e-5
