@@ -160,3 +160,22 @@ def test_estimator_workspace_queries():
     assert best >= km + pp + 2 * 10 * 1024 * 8 + (1 << 20) * 4
     b = ctypes.c_size_t()
     assert pds.lib().pds_workspace_size(plan.handle, _lib.PDS_OP_KMEANS_BEST, 10, 0, ctypes.byref(b)) == _lib.PDS_E_ARG
+
+
+def test_stream_estimates_validates_on_the_host():
+    """The out-of-core helper rejects inputs it cannot stream before touching
+    the device."""
+    torch = pytest.importorskip("torch")
+    from paper_1511_00152_amd.stream import stream_estimates
+
+    plan = pds.Plan(256, 26, prec=pds.PDS_F32)
+    with pytest.raises(TypeError):
+        stream_estimates(plan, np.zeros((10, 256), dtype=np.float64), 4)  # FP64 rows for an FP32 plan
+    with pytest.raises(ValueError):
+        stream_estimates(plan, np.zeros((10, 300), dtype=np.float32), 4)  # wider than p
+    with pytest.raises(ValueError):
+        stream_estimates(plan, np.zeros((0, 256), dtype=np.float32), 4)  # no rows
+    with pytest.raises(ValueError):
+        stream_estimates(plan, np.zeros((10, 256), dtype=np.float32), 0)  # empty chunks
+    with pytest.raises(ValueError):
+        stream_estimates(plan, torch.zeros(10, dtype=torch.float32), 4)  # not 2-D
