@@ -9,16 +9,19 @@ the current HIP device; every call enqueues the library's kernels on
     C = covariance(plan, vals, idx)            # Sec. V, unbiased C_n (preconditioned domain)
     mu, c, J = kmeans_step(plan, vals, idx, mu0)   # Sec. VI, one Lloyd round
     centers = unmix(plan, mu)                  # eq. mu-mu'
+    mu0, chosen = kmeanspp(plan, vals, idx, K) # Alg. 1 seeding (K-means++)
+    xbar = sample_mean(plan, vals, idx)        # Sec. IV (preconditioned domain)
 """
 import ctypes
 
-from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_F32, PDS_F64,
-                   PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_MEAN, PDS_OP_KMEANSPP, PDS_OP_KMEANS_BEST, PDS_EXPLAINED_WS_BYTES, PDS_SPLIT_BF16, EXPORTS, PdsError,
-                   check, lib)
+from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_EXPLAINED_WS_BYTES, PDS_F32,
+                   PDS_F64, PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_KMEANS_BEST,
+                   PDS_OP_KMEANSPP, PDS_OP_MEAN, PDS_SPLIT_BF16, EXPORTS, PdsError, check, lib)
 
 __all__ = [
-    "Plan", "compress", "covariance", "CovarianceAccumulator", "kmeans_step", "unmix", "kmeans_2pass", "sparsified_kmeans",
-    "top_eigenvalues",
+    "Plan", "compress", "pad_rows", "covariance", "CovarianceAccumulator", "sample_mean", "kmeanspp", "kmeans_best",
+    "kmeans_step", "unmix", "kmeans_2pass", "sparsified_kmeans", "top_eigenvalues", "principal_components",
+    "explained_variance",
     "PdsError", "PDS_F64", "PDS_F32", "PDS_SPLIT_BF16", "lib", "EXPORTS",
 ]
 
@@ -351,13 +354,23 @@ def kmeans_2pass(plan: Plan, X, c_hat, mu_hat, out=None, assign=None, ws=None):
     return out, assign
 
 
-def sparsified_kmeans(plan: Plan, X, init_centers, iterations: int):
-    """Alg. 1 with given initial centers (preconditioned domain, K x p FP64):
-    one compression pass, `iterations` assignment/update rounds, unmixing.
-    Returns dict(vals, idx, assign, centers_pre, centers, objectives)."""
+def sparsified_kmeans(plan: Plan, X, init_centers, iterations: int, starts: int = 1):
+    """Alg. 1: one compression pass, `iterations` assignment/update rounds,
+    unmixing.  init_centers: K x p FP64 initial centers (preconditioned
+    domain), or an int K to seed on the device with K-means++ (with
+    starts > 1, the best of that many K-means++ starts is kept; objectives is
+    then starts x iterations).  Returns dict(vals, idx, assign, centers_pre,
+    centers, objectives)."""
     import torch
 
     vals, idx = compress(plan, X)
+    if isinstance(init_centers, int):
+        K = init_centers
+        if starts > 1:
+            c, assign, objs, best = kmeans_best(plan, vals, idx, K, iterations, starts)
+            return {"vals": vals, "idx": idx, "assign": assign, "centers_pre": c, "centers": unmix(plan, c),
+                    "objectives": objs, "best": best}
+        init_centers, _ = kmeanspp(plan, vals, idx, K)
     K = init_centers.shape[0]
     ws = plan.workspace(PDS_OP_KMEANS, X.shape[0], K, device=X.device)
     a = init_centers.clone()

@@ -160,6 +160,29 @@ def test_kmeans_best_of_r_matches_oracle(prec):
     assert np.max(np.abs(C.cpu().numpy() - o["centers_pre"])) <= tol * np.max(np.abs(o["centers_pre"]))
 
 
+def test_sparsified_kmeans_seeds_on_the_device():
+    """The end-to-end call with K instead of centers: K-means++ on the device
+    (one start, and best of 3), against the oracle's Alg. 1 with the same
+    seeding (FP64 plan, so both sides see the same compressed values)."""
+    w = synth.WORKLOADS["small_f64"]
+    p, n, K = w["p"], w["n"], w["K"]
+    m = synth.m_from_gamma(w["gamma"], p)
+    X = synth.rows_numpy("small_f64", n)
+    log(f"sparsified_kmeans with device seeding p={p} m={m} n={n} K={K}")
+    plan = pds.Plan(p, m, seed=3, prec=pds.PDS_F64)
+    out = pds.sparsified_kmeans(plan, to_dev(X), K, 6)
+    torch.cuda.synchronize()
+    o = ref.sparsified_kmeans(X, 3, m, K, 6)
+    assert np.array_equal(out["assign"].cpu().numpy(), o["assign"])
+    assert np.max(np.abs(out["centers"].cpu().numpy() - o["centers"])) <= 1e-12 * np.max(np.abs(o["centers"]))
+    out3 = pds.sparsified_kmeans(plan, to_dev(X), K, 6, starts=3)
+    torch.cuda.synchronize()
+    o3 = ref.sparsified_kmeans_best(X, 3, m, K, 6, 3)
+    assert int(out3["best"].cpu()[0]) == o3["best"]
+    assert np.array_equal(out3["assign"].cpu().numpy(), o3["assign"])
+    assert np.max(np.abs(out3["centers"].cpu().numpy() - o3["centers"])) <= 1e-12 * np.max(np.abs(o3["centers"]))
+
+
 def test_kmeanspp_argument_errors():
     plan = pds.Plan(64, 8, prec=pds.PDS_F32)
     vals = torch.zeros((10, 8), dtype=torch.float32, device="cuda")
