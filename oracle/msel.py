@@ -224,13 +224,14 @@ def mlp_predict_bf16(P, F, mu, sd, gmin, gmax, fallback):
     Pb = bf16_round(np.asarray(P, np.float32)).astype(np.float64)
     W1, b1, W2, b2, w3, b3 = unpack(Pb)
     F = np.asarray(F, np.float64)
-    xn = ((F.astype(np.float32) - np.asarray(mu, np.float32)) / np.asarray(sd, np.float32))
-    xn = bf16_round(xn).astype(np.float64)
-    h1 = np.maximum(xn @ W1.T + b1, 0.0)
-    h1 = bf16_round(h1.astype(np.float32)).astype(np.float64)
-    h2 = np.maximum(h1 @ W2.T + b2, 0.0)
-    y = h2 @ w3 + b3
+    # rows with non-finite features propagate NaN and take the fallback below
     with np.errstate(over="ignore", invalid="ignore"):
+        xn = ((F.astype(np.float32) - np.asarray(mu, np.float32)) / np.asarray(sd, np.float32))
+        xn = bf16_round(xn).astype(np.float64)
+        h1 = np.maximum(xn @ W1.T + b1, 0.0)
+        h1 = bf16_round(h1.astype(np.float32)).astype(np.float64)
+        h2 = np.maximum(h1 @ W2.T + b2, 0.0)
+        y = h2 @ w3 + b3
         g = np.exp(y)
     bad = ~np.isfinite(F).all(1) | ~np.isfinite(g)
     g = np.where(bad, fallback, g)
