@@ -327,6 +327,35 @@ def test_principal_components_ky_fan():
     assert ref.explained_variance(X, low) < 0.5 * ref.explained_variance(X, U)
 
 
+def test_mean_estimator_within_theorem_bound():
+    """Thm. "sampleMean" at its figure's setup (p = 100, m = 30, x_i = xbar +
+    eps_i with xbar and eps standard normal, kept sets by the sampler, no
+    preconditioning): over 200 runs the l_inf error never exceeds the bound t
+    for delta_1 = 0.001 (second remark's closed form, with ||X||_max the largest
+    entry and ||X||_maxRow the largest coordinate norm over the samples), and
+    the bound is not vacuous: the largest error reaches a quarter of t, as the
+    paper's figure shows it close to the maximum over runs.  A missing p/m
+    rescale gives errors above t at n = 1000."""
+    from oracle import bounds
+
+    p, m = 100, 30
+    for n in (50, 1000):
+        rng = np.random.default_rng([5, n])
+        xbar = rng.standard_normal(p)
+        ratio = []
+        for run in range(200):
+            X = xbar + rng.standard_normal((n, p))
+            idx = ref.sample_batch(1000 + run, 0, n, p, m)
+            vals = np.take_along_axis(X, idx.astype(np.int64), axis=1)
+            err = np.max(np.abs(ref.mean_estimate(p, vals, idx) - X.mean(axis=0)))
+            t = bounds.mean_error_t(0.001, n, m, p, np.max(np.abs(X)), np.max(np.linalg.norm(X, axis=0)))
+            ratio.append(err / t)
+        assert max(ratio) <= 1.0, (n, max(ratio))
+        assert max(ratio) >= 0.25, (n, max(ratio))
+        if n == 1000:  # at the larger n the bound is tight enough to reject it
+            assert np.max(np.abs(ref.mean_estimate(p, vals, idx) * m / p - X.mean(axis=0))) > t
+
+
 def test_covariance_matches_literal_oracle():
     p, n, m, seed = 16, 40, 6, 2
     X = np.random.default_rng(5).standard_normal((n, p))
