@@ -2,6 +2,9 @@
 
 Used by the statistical tests; pinned by the worked values the paper prints
 (Cor. "sampleMean": 137.2 / 15.1 / 1.6, golden fixture ``tests/golden``).
+``mean_error_t`` and ``cov_error_t`` are checked against the oracle's
+estimators at the setups of the theorems' figures (errors below the bounds and
+of the order the figures show).
 Logarithms are natural: the printed values reproduce only with ln.
 """
 import math
@@ -51,3 +54,27 @@ def cor_rho_norm_bound(m, p, alpha, n=1, eta=1.0):
 def thm1_tail(t, eta=1.0):
     """Thm. FJLT: P(|y_j| >= t ||x|| / sqrt(p)) <= 2 exp(-eta t^2 / 2)."""
     return 2.0 * math.exp(-eta * t * t / 2.0)
+
+
+def cov_error_t(delta2, X, m, rho=1.0):
+    """Thm. covariance: the spectral-norm error t of C_n that holds with
+    probability 1 - delta2, solving eq. cov-converge-delta2 for t with L from
+    eq. covariance-L and sigma^2 at its upper bound eq. covariance_sigma.  The
+    samples are the rows of X here (the paper's X is p x n): ||X||_maxCol is
+    the largest sample norm, max_j sum_i X_ji^4 runs over coordinates."""
+    import numpy as np
+
+    X = np.asarray(X, dtype=np.float64)
+    n, p = X.shape
+    maxcol2 = float(np.max(np.sum(X * X, axis=1)))
+    xmax2 = float(np.max(np.abs(X))) ** 2
+    C = X.T @ X / n
+    a = p * (p - 1) / (m * (m - 1))
+    b = p * (p - 1) * (p - m) / (m * (m - 1) ** 2)
+    L = ((a * rho + 1.0) * maxcol2 + p * (p - m) / (m * (m - 1)) * xmax2) / n
+    sigma2 = ((a * rho - 1.0) * maxcol2 * float(np.linalg.norm(C, 2))
+              + b * rho * maxcol2 * float(np.max(np.diag(C)))
+              + 2.0 * b * xmax2 * float(np.sum(X * X)) / n
+              + p * (p - m) ** 2 / (m * (m - 1) ** 2) * float(np.max(np.sum(X ** 4, axis=0))) / n) / n
+    ell = math.log(p / delta2)
+    return ell * L / 3.0 + math.sqrt((ell * L / 3.0) ** 2 + 2.0 * ell * sigma2)

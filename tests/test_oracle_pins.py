@@ -382,6 +382,29 @@ def test_explained_variance_spread_at_column_sampling_setup():
     assert means[0] > 4 * k / p and means[1] > means[0] + 0.1, means
 
 
+def test_covariance_estimator_within_theorem_bound():
+    """Thm. "covariance" at its figure's setup (p = 1000, gamma = 0.3, x_i =
+    sum_j kappa_ij lambda_j u_j with k = 5, lambda = (10, 8, 6, 4, 2), U the Q of
+    a Gaussian p x 5, kept sets by the sampler on the raw rows): in every run
+    ||C_n - C_emp||_2 stays below t(delta_2 = 0.01) from eq. cov-converge-delta2
+    with L and the variance bound of the theorem, and is of the order of
+    t / 10 (the figure draws the bound divided by 10 beside the errors)."""
+    from oracle import bounds
+
+    p, k, n = 1000, 5, 1000
+    m = 300
+    lam = np.array([10.0, 8.0, 6.0, 4.0, 2.0])
+    rng = np.random.default_rng(77)
+    U, _ = np.linalg.qr(rng.standard_normal((p, k)))
+    for run in range(4):
+        X = (rng.standard_normal((n, k)) * lam) @ U.T
+        idx = ref.sample_batch(run, 0, n, p, m)
+        vals = np.take_along_axis(X, idx.astype(np.int64), axis=1)
+        err = np.linalg.norm(ref.covariance(p, vals, idx) - X.T @ X / n, 2)
+        t = bounds.cov_error_t(0.01, X, m)
+        assert t / 100 <= err <= t, (run, err, t)
+
+
 def test_covariance_matches_literal_oracle():
     p, n, m, seed = 16, 40, 6, 2
     X = np.random.default_rng(5).standard_normal((n, p))
