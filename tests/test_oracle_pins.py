@@ -405,6 +405,29 @@ def test_covariance_estimator_within_theorem_bound():
         assert t / 100 <= err <= t, (run, err, t)
 
 
+def test_pairwise_distance_band():
+    """App. D, Thm. "ROS-distance-preserve": with beta = 30 and m at the
+    theorem's lower limit 4 [sqrt(beta) + sqrt(8 ln(beta p))]^2 ln(beta) (p =
+    4096), ||sqrt(p/m) R^T H D (x1 - x2)|| / ||x1 - x2|| lies in [0.40, 1.48]
+    with probability at least 1 - 3/beta = 0.9.  Over 300 draws of (D, R) (one
+    seed each) every ratio is in the band, and the squared ratios average to 1
+    (E ||sqrt(p/m) R^T y||^2 = ||y||^2), which a missing sqrt(p/m) (mean m/p)
+    fails."""
+    p, beta = 4096, 30.0
+    m = int(math.ceil(4 * (math.sqrt(beta) + math.sqrt(8 * math.log(beta * p))) ** 2 * math.log(beta)))
+    assert m <= p
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((1, p)) * np.exp(rng.standard_normal(p))  # uneven entries
+    r2 = []
+    for seed in range(300):
+        v, _ = ref.compress(x, seed, m)
+        r2.append(p / m * float(np.sum(v * v)) / float(np.sum(x * x)))
+    r = np.sqrt(r2)
+    assert np.all((r >= 0.40) & (r <= 1.48)), (r.min(), r.max())
+    se = np.std(r2) / math.sqrt(len(r2))
+    assert abs(np.mean(r2) - 1.0) <= 4 * se + 1e-12, (np.mean(r2), se)
+
+
 def test_covariance_matches_literal_oracle():
     p, n, m, seed = 16, 40, 6, 2
     X = np.random.default_rng(5).standard_normal((n, p))
