@@ -35,6 +35,10 @@ Functions and the passages they follow (paper = arXiv 1511.00152):
   direct numpy sum over each start's own assignment.
 * ``y_entry`` -- one entry of H D x from the definition (row of H times D x).
 * ``mean_estimate`` -- Thm. "sampleMean"; pinned by enumeration (unbiased).
+* ``dct_orthonormal`` / ``compress_dct`` / ``unmix_dct`` -- the DCT form of the
+  preconditioner (Sec. III; Thm. 1 with eta = 1/2) for p not a power of two;
+  pinned against the DCT-II matrix written from its definition, the inverse
+  round trip at m = p, and Thm. 1's tail with eta = 1/2 by Monte Carlo.
 * ``principal_components`` / ``explained_variance`` -- PCA on the covariance
   estimate (Sec. V) and the fraction of explained variance used in the
   column-sampling comparison (Sec. II); pinned by the canonical-subset closed
@@ -300,6 +304,36 @@ def kmeans_best_compressed(p: int, vals, idx, seed: int, K: int, T: int, R: int,
             best = (r, mu, assign)
     r, mu, assign = best
     return {"best": r, "objectives": objs, "centers_pre": mu, "assign": assign}
+
+
+def dct_orthonormal(v):
+    """y = C v with C the orthonormal DCT-II matrix (one of the fast
+    orthonormal transforms Sec. III allows for H; the paper uses it for p = 784,
+    Thm. 1 with eta = 1/2), along the last axis, by scipy's FFT-based DCT."""
+    import scipy.fft
+
+    return scipy.fft.dct(np.asarray(v, dtype=np.float64), type=2, norm="ortho", axis=-1)
+
+
+def compress_dct(X, seed: int, m: int, i0: int = 0):
+    """Alg. 1's first loop with the DCT in place of the Hadamard transform, for
+    any p: y_i = C D x_i with the plan's signs D, then the kept sets of the
+    sampler (the same (seed, i, p, m) streams).  Returns (vals n x m FP64,
+    idx n x m uint16)."""
+    X = np.asarray(X, dtype=np.float64)
+    n, p = X.shape
+    Y = dct_orthonormal(X * signs(seed, p).astype(np.float64))
+    idx = sample_batch(seed, i0, n, p, m)
+    return np.take_along_axis(Y, idx.astype(np.int64), axis=1), idx
+
+
+def unmix_dct(seed: int, centers_pre):
+    """mu = (C D)^T mu' = D C^T mu' for each row (the DCT form of eq. mu-mu')."""
+    import scipy.fft
+
+    c = np.asarray(centers_pre, dtype=np.float64)
+    p = c.shape[-1]
+    return scipy.fft.idct(c, type=2, norm="ortho", axis=-1) * signs(seed, p).astype(np.float64)
 
 
 def principal_components(C, k: int):

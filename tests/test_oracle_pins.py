@@ -428,6 +428,40 @@ def test_pairwise_distance_band():
     assert abs(np.mean(r2) - 1.0) <= 4 * se + 1e-12, (np.mean(r2), se)
 
 
+# ------------------------------------------------- DCT preconditioner (Sec. III) --
+def test_dct_matches_definition_and_round_trips():
+    """The orthonormal DCT-II from its definition, C[k][j] = sqrt(2/p) c_k
+    cos(pi (2j + 1) k / (2p)) with c_0 = 1/sqrt(2), c_k = 1 otherwise, at
+    p = 784 (the paper's image dimension) and p = 7; C is orthogonal; with
+    m = p the DCT compression keeps every coordinate and unmix_dct inverts it."""
+    for p in (7, 784):
+        j = np.arange(p)
+        Cm = np.sqrt(2.0 / p) * np.cos(np.pi * np.outer(j, 2 * j + 1) / (2 * p))
+        Cm[0] /= np.sqrt(2.0)
+        x = np.random.default_rng(p).standard_normal((3, p))
+        assert np.max(np.abs(ref.dct_orthonormal(x) - x @ Cm.T)) < 1e-12
+        assert np.max(np.abs(Cm @ Cm.T - np.eye(p))) < 1e-12
+        vals, idx = ref.compress_dct(x, 5, p)
+        assert np.array_equal(idx, np.tile(np.arange(p, dtype=np.uint16), (3, 1)))
+        D = ref.signs(5, p).astype(np.float64)
+        assert np.max(np.abs(vals - (x * D) @ Cm.T)) < 1e-12
+        assert np.max(np.abs(ref.unmix_dct(5, vals) - x)) < 1e-12
+
+
+def test_dct_tail_bound_eta_half():
+    """Thm. 1 with the DCT (eta = 1/2): P{|y_j| >= (t/sqrt(p)) ||x||} <=
+    2 exp(-t^2/4) over the random signs, for a spiky x at p = 784; Monte Carlo
+    over 400 seeds, every coordinate and t in {2, 3, 4}."""
+    p = 784
+    x = np.zeros(p)
+    x[[3, 100, 500]] = [5.0, -2.0, 1.0]  # few large entries: the case the preconditioner is for
+    ys = np.stack([ref.dct_orthonormal(x * ref.signs(s, p)) for s in range(400)])
+    r = np.abs(ys) * np.sqrt(p) / np.linalg.norm(x)
+    for t in (2.0, 3.0, 4.0):
+        frac = np.mean(r >= t, axis=0)
+        assert np.max(frac) <= 2 * np.exp(-t * t / 4) + 3 * np.sqrt(2 * np.exp(-t * t / 4) / 400) + 1e-12, t
+
+
 def test_covariance_matches_literal_oracle():
     p, n, m, seed = 16, 40, 6, 2
     X = np.random.default_rng(5).standard_normal((n, p))
