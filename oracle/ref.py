@@ -39,6 +39,8 @@ Functions and the passages they follow (paper = arXiv 1511.00152):
   preconditioner (Sec. III; Thm. 1 with eta = 1/2) for p not a power of two;
   pinned against the DCT-II matrix written from its definition, the inverse
   round trip at m = p, and Thm. 1's tail with eta = 1/2 by Monte Carlo.
+* ``clustering_accuracy`` -- Sec. VII's accuracy against ground-truth labels;
+  pinned by brute force over every matching at small K.
 * ``principal_components`` / ``explained_variance`` -- PCA on the covariance
   estimate (Sec. V) and the fraction of explained variance used in the
   column-sampling comparison (Sec. II); pinned by the canonical-subset closed
@@ -334,6 +336,20 @@ def unmix_dct(seed: int, centers_pre):
     c = np.asarray(centers_pre, dtype=np.float64)
     p = c.shape[-1]
     return scipy.fft.idct(c, type=2, norm="ortho", axis=-1) * signs(seed, p).astype(np.float64)
+
+
+def clustering_accuracy(labels, assign, K: int):
+    """Clustering accuracy of Sec. VII: the number of samples whose cluster
+    matches their ground-truth label under the best one-to-one matching of
+    clusters to labels, over n (the matching by the Hungarian method)."""
+    from scipy.optimize import linear_sum_assignment
+
+    labels = np.asarray(labels, dtype=np.int64)
+    assign = np.asarray(assign, dtype=np.int64)
+    M = np.zeros((K, K), dtype=np.int64)
+    np.add.at(M, (assign, labels), 1)
+    r, c = linear_sum_assignment(-M)
+    return float(M[r, c].sum()) / len(labels)
 
 
 def principal_components(C, k: int):

@@ -462,6 +462,22 @@ def test_dct_tail_bound_eta_half():
         assert np.max(frac) <= 2 * np.exp(-t * t / 4) + 3 * np.sqrt(2 * np.exp(-t * t / 4) / 400) + 1e-12, t
 
 
+def test_clustering_accuracy_brute_force():
+    """Sec. VII's accuracy: the best one-to-one matching of clusters to labels
+    equals the maximum over all K! matchings (K <= 5), a relabelled perfect
+    clustering scores 1, and a constant assignment scores the largest class."""
+    rng = np.random.default_rng(12)
+    for K in (2, 3, 5):
+        labels = rng.integers(0, K, 300)
+        assign = np.where(rng.random(300) < 0.7, labels, rng.integers(0, K, 300))
+        best = max(np.mean(np.array(perm)[assign] == labels) for perm in itertools.permutations(range(K)))
+        assert ref.clustering_accuracy(labels, assign, K) == pytest.approx(best, abs=1e-15)
+        perm = rng.permutation(K)
+        assert ref.clustering_accuracy(labels, perm[labels], K) == 1.0
+        assert ref.clustering_accuracy(labels, np.zeros(300, dtype=np.int64), K) == pytest.approx(
+            np.max(np.bincount(labels, minlength=K)) / 300)
+
+
 def test_covariance_matches_literal_oracle():
     p, n, m, seed = 16, 40, 6, 2
     X = np.random.default_rng(5).standard_normal((n, p))
