@@ -13,7 +13,8 @@
  * one sample is one contiguous row of a row-major n x p array; indices are
  * 0-based.  All arithmetic is IEEE double.  Parallel loops (OpenMP) split the
  * samples into contiguous ranges; sums over samples are formed per range and
- * then added range by range, which only changes the rounding order.
+ * then added range by range, which only changes the rounding order (the Gram
+ * of the covariance estimator instead sums every entry in sample order).
  */
 #include <math.h>
 #include <stdint.h>
@@ -308,43 +309,74 @@ void orc_compress_f32(uint64_t seed, int64_t p, int64_t m, const float* X, int64
 
 /* ------------------------------------------------------------------------- */
 /* Covariance estimator (Sec. V).  G = sum_i w_i w_i^T over the compressed
- * samples (added into G, p x p row-major, full square).                     */
+ * samples.  Every entry G[j][k] is summed over the samples in sample order
+ * (i = 0, 1, ..., n-1), so the result does not depend on the thread count:
+ * for each sample that keeps coordinate j, row j receives v_j * v_k for all
+ * kept k of that sample, and a row is updated by one thread at a time.
+ *
+ * orc_gram_rows: rows[0..nrows-1] of G (distinct coordinates), added into the
+ * nrows x p row-major array out.  orc_gram_accumulate: all p rows, added into
+ * the p x p row-major G.                                                    */
 /* ------------------------------------------------------------------------- */
+void orc_gram_rows(int64_t p, int64_t m, const double* vals, const uint16_t* idx, int64_t n,
+                   const int64_t* rows, int64_t nrows, double* out, int nthreads)
+{
+    /* Samples are taken in blocks of NB.  Within a block, the (sample, entry)
+     * pairs of each wanted coordinate are listed in sample order (a stable
+     * counting sort by coordinate), and each row of the output then walks its
+     * own list: every entry of G still receives its terms in sample order, and
+     * the row being updated stays in cache while it does.                   */
+    const int64_t NB = 8192;
+    int64_t* slot = (int64_t*)malloc(sizeof(int64_t) * (size_t)p);
+    for (int64_t j = 0; j < p; ++j) slot[j] = -1;
+    for (int64_t r = 0; r < nrows; ++r) slot[rows[r]] = r;
+    int64_t* start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nrows + 1));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nrows + 1));
+    int64_t* list = (int64_t*)malloc(sizeof(int64_t) * (size_t)(NB * m));  /* i * m + a */
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    for (int64_t i0 = 0; i0 < n; i0 += NB) {
+        const int64_t i1 = (i0 + NB < n) ? i0 + NB : n;
+        for (int64_t r = 0; r <= nrows; ++r) start[r] = 0;
+        for (int64_t e = i0 * m; e < i1 * m; ++e) {
+            const int64_t r = slot[idx[e]];
+            if (r >= 0) ++start[r + 1];
+        }
+        for (int64_t r = 0; r < nrows; ++r) start[r + 1] += start[r];
+        for (int64_t r = 0; r <= nrows; ++r) fill[r] = start[r];
+        for (int64_t e = i0 * m; e < i1 * m; ++e) {
+            const int64_t r = slot[idx[e]];
+            if (r >= 0) list[fill[r]++] = e - i0 * m;
+        }
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t r = 0; r < nrows; ++r) {
+            double* orow = out + r * p;
+            for (int64_t q = start[r]; q < start[r + 1]; ++q) {
+                const int64_t e = i0 * m + list[q];
+                const int64_t i = e / m;
+                const double va = vals[e];
+                const double* v = vals + i * m;
+                const uint16_t* ix = idx + i * m;
+                for (int64_t b = 0; b < m; ++b) orow[ix[b]] += va * v[b];
+            }
+        }
+    }
+    free(list);
+    free(fill);
+    free(start);
+    free(slot);
+}
+
 void orc_gram_accumulate(int64_t p, int64_t m, const double* vals, const uint16_t* idx, int64_t n,
                          double* G, int nthreads)
 {
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-    int T = omp_get_max_threads();
-#else
-    (void)nthreads;
-    int T = 1;
-#endif
-    if (T < 1) T = 1;
-    if ((int64_t)T > n) T = (int)(n > 0 ? n : 1);
-    double** part = (double**)malloc(sizeof(double*) * (size_t)T);
-    for (int t = 0; t < T; ++t) part[t] = (double*)calloc((size_t)(p * p), sizeof(double));
-#pragma omp parallel num_threads(T)
-    {
-#ifdef _OPENMP
-        int t = omp_get_thread_num();
-#else
-        int t = 0;
-#endif
-        int64_t lo = n * t / T, hi = n * (t + 1) / T;
-        double* Gt = part[t];
-        for (int64_t i = lo; i < hi; ++i) {
-            const double* v = vals + i * m;
-            const uint16_t* ix = idx + i * m;
-            for (int64_t a = 0; a < m; ++a)
-                for (int64_t b = 0; b < m; ++b) Gt[(int64_t)ix[a] * p + ix[b]] += v[a] * v[b];
-        }
-    }
-    for (int t = 0; t < T; ++t) {
-        for (int64_t e = 0; e < p * p; ++e) G[e] += part[t][e];
-        free(part[t]);
-    }
-    free(part);
+    int64_t* rows = (int64_t*)malloc(sizeof(int64_t) * (size_t)p);
+    for (int64_t j = 0; j < p; ++j) rows[j] = j;
+    orc_gram_rows(p, m, vals, idx, n, rows, p, G, nthreads);
+    free(rows);
 }
 
 /* C_emp_hat = p(p-1)/(m(m-1)) * G / n and

@@ -87,6 +87,7 @@ def lib():
         L.orc_compress_f64.argtypes = [u64, i64, i64, P, i64, i64, u64, P, P, i32]
         L.orc_compress_f32.argtypes = [u64, i64, i64, P, i64, i64, u64, P, P, i32]
         L.orc_gram_accumulate.argtypes = [i64, i64, P, P, i64, P, i32]
+        L.orc_gram_rows.argtypes = [i64, i64, P, P, i64, P, i64, P, i32]
         L.orc_cov_finalize.argtypes = [i64, i64, i64, P, P]
         L.orc_kmeans_step.argtypes = [i64, i64, P, P, i64, i32, P, P, P, P, P, i32]
         L.orc_unmix.argtypes = [u64, i64, P, i32, P]
@@ -195,6 +196,30 @@ def gram_accumulate(p: int, vals, idx, G=None, nthreads: int = 0):
         G = np.zeros((p, p), dtype=np.float64)
     lib().orc_gram_accumulate(p, m, _ptr(vals), _ptr(idx), n, _ptr(G), nthreads)
     return G
+
+
+def gram_rows(p: int, vals, idx, rows, nthreads: int = 0):
+    """Rows `rows` of G = sum_i w_i w_i^T (len(rows) x p), each entry summed
+    over the samples in order; the same sums as ``gram_accumulate``."""
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.uint16)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    if len(np.unique(rows)) != len(rows) or (len(rows) and (rows.min() < 0 or rows.max() >= p)):
+        raise ValueError("rows must be distinct coordinates in [0, p)")
+    n, m = vals.shape
+    out = np.zeros((len(rows), p), dtype=np.float64)
+    lib().orc_gram_rows(p, m, _ptr(vals), _ptr(idx), n, _ptr(rows), len(rows), _ptr(out), nthreads)
+    return out
+
+
+def cov_rows(p: int, m: int, n: int, Grows, rows):
+    """Rows `rows` of C_n from the matching rows of G (Sec. V): off-diagonal
+    entries p(p-1)/(m(m-1)) G/n, the diagonal one p/(m n) G (the closed form of
+    C_emp_hat - (p-m)/(p-1) diag(C_emp_hat))."""
+    C = (p * (p - 1)) / (m * (m - 1)) * (np.asarray(Grows, dtype=np.float64) / n)
+    r = np.arange(len(rows))
+    C[r, rows] = C[r, rows] - (p - m) / (p - 1) * C[r, rows]
+    return C
 
 
 def gram_submatrix(seed: int, m: int, X, J, i0: int = 0, nthreads: int = 0):

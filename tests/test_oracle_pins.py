@@ -799,3 +799,30 @@ def test_gram_submatrix_from_definitions_matches_fast_path():
     J = np.array([0, 3, 64, 511, 512, 1023])
     Gs = ref.gram_submatrix(5, m, X, J)
     assert np.max(np.abs(Gs - G[np.ix_(J, J)])) <= 1e-12 * np.max(np.abs(G))
+
+
+def test_gram_is_the_sample_ordered_sum_of_outer_products():
+    """G = sum_i w_i w_i^T (Sec. V) with every entry summed in sample order:
+    equal bit for bit to adding the zero-filled samples' outer products one
+    sample after another, whatever the thread count, across the oracle's
+    internal sample blocks (n > 8192) and with a ragged last block; rows of
+    G alone equal the same rows of the whole Gram, and the rows of C_n match
+    cov_finalize's."""
+    p, m, n = 32, 5, 8192 + 37
+    rng = np.random.default_rng(11)
+    idx = np.sort(np.stack([rng.choice(p, m, replace=False) for _ in range(n)]), axis=1).astype(np.uint16)
+    vals = rng.standard_normal((n, m))
+    Gs = np.zeros((p, p))
+    for i in range(n):
+        w = np.zeros(p)
+        w[idx[i].astype(np.int64)] = vals[i]
+        Gs += np.outer(w, w)
+    G1 = ref.gram_accumulate(p, vals, idx, nthreads=1)
+    G4 = ref.gram_accumulate(p, vals, idx, nthreads=4)
+    assert np.array_equal(G1, Gs) and np.array_equal(G4, Gs)
+    rows = np.array([31, 0, 7, 16])
+    assert np.array_equal(ref.gram_rows(p, vals, idx, rows), Gs[rows])
+    C = ref.cov_finalize(p, m, n, Gs)
+    assert np.array_equal(ref.cov_rows(p, m, n, Gs[rows], rows), C[rows])
+    with pytest.raises(ValueError):
+        ref.gram_rows(p, vals, idx, np.array([3, 3]))
