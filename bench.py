@@ -146,6 +146,91 @@ def roofline(kern, n, p, m, prec_name, steps):
             "algorithmic_per_launch": units}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def full_n_row_errors(pds, X, p, m, variants, per_block=8, seed=2024):
+    """Each variant's C_n against the oracle over all n samples on full rows:
+    `per_block` coordinates of every 128-coordinate block (every output tile
+    of the Gram kernels), each entry summed over the samples in order."""
+    import numpy as np
+    import torch
+
+    from oracle import ref
+
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    J = np.sort(np.concatenate([b * 128 + rng.choice(128, per_block, replace=False) for b in range(p // 128)]))
+    t0 = time.perf_counter()
+    v_o, i_o = ref.compress(X.cpu().numpy(), 0, m)
+    C_rows = ref.cov_rows(p, m, n, ref.gram_rows(p, v_o, i_o, J), J)
+    out = {"sample": f"all {n} samples, {len(J)} full rows of C_n ({per_block} per 128-coordinate block), "
+                     "vs the FP64 oracle", "oracle_s": time.perf_counter() - t0}
+    Jd = torch.as_tensor(J, device=X.device)
+    for name in variants:
+        prec = {"split": pds.PDS_SPLIT_BF16, "f32": pds.PDS_F32}[name]
+        plan = pds.Plan(p, m, seed=0, prec=prec)
+        vals, idx = pds.compress(plan, X)
+        C = pds.covariance(plan, vals, idx)
+        Cg = C[Jd].cpu().numpy()
+        out[name] = {"idx_bit_exact": bool(np.array_equal(idx.cpu().numpy().view(np.uint16), i_o)),
+                     "cov_rows_max_rel": float(np.max(np.abs(Cg - C_rows)) / np.max(np.abs(C_rows))),
+                     "cov_rows_fro_rel": float(np.linalg.norm(Cg - C_rows) / np.linalg.norm(C_rows))}
+        del vals, idx, C
+    return out
+
+
+def run_small(pds, steps):
+    """The small FP64 case (n = 2000, p = 256, m = 26, K = 5, T = 10): compress,
+    covariance, K-means++ seeding and T K-means rounds per step, with its error
+    against the oracle; too small to load the GPU, timed for completeness."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import ref
+
+    name = "small_f64"
+    w = synth.WORKLOADS[name]
+    p, n, K, T = w["p"], w["n"], w["K"], w["T"]
+    m = synth.m_from_gamma(w["gamma"], p)
+    Xh = synth.rows_numpy(name, n)
+    X = torch.from_numpy(Xh).cuda()
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F64)
+
+    def step():
+        vals, idx = pds.compress(plan, X)
+        C = pds.covariance(plan, vals, idx)
+        out = pds.sparsified_kmeans(plan, X, K, T)
+        return C, out
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        C, out = step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    v_o, i_o = ref.compress(Xh, 0, m)
+    C_o = ref.covariance(p, v_o, i_o)
+    mu, _ = ref.kmeanspp(0, p, v_o, i_o, K)
+    for _ in range(T):
+        mu, a_o, J_o, _ = ref.kmeans_step(p, v_o, i_o, mu)
+    return {"workload": f"{name}: n={n}, p={p}, m={m}, FP64, K={K}, T={T}; step = compress + covariance + "
+                        "K-means++ seeding + T kmeans_step (two compressions: one per estimator call)",
+            "ms_per_step": wall * 1e3, "samples_per_s": n / wall,
+            "cov_max_rel": float(np.max(np.abs(C.cpu().numpy() - C_o)) / np.max(np.abs(C_o))),
+            "assign_equal": bool(np.array_equal(out["assign"].cpu().numpy(), a_o)),
+            "centers_max_rel": float(np.max(np.abs(out["centers_pre"].cpu().numpy() - mu)) / np.max(np.abs(mu)))}
+
+
 def cpu_baseline_and_errors(pds, X, p, m, nsamp, variants):
     """Oracle on the first nsamp rows (timed), and each GPU variant's error
     against it on the same rows."""
@@ -161,7 +246,16 @@ def cpu_baseline_and_errors(pds, X, p, m, nsamp, variants):
     dt = time.perf_counter() - t0
     base = {"value": nsamp / dt, "unit": "samples/s", "cores": ref.max_threads(), "kind": "oracle",
             "sample": f"first {nsamp} samples of the workload: compress + covariance, FP64 C oracle, OpenMP",
-            "seconds": dt}
+            "seconds": dt, "cpu_model": cpu_model()}
+    n1 = max(1, nsamp // 8)
+    nt = ref.max_threads()
+    t0 = time.perf_counter()
+    v1, i1 = ref.compress(Xs[:n1], 0, m, nthreads=1)
+    ref.covariance(p, v1, i1, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    ref.compress(Xs[:1], 0, m, nthreads=nt)  # the oracle's thread count back to all cores
+    base["one_core"] = {"value": n1 / dt1, "unit": "samples/s", "cores": 1, "seconds": dt1,
+                        "sample": f"first {n1} samples, the same oracle on one thread"}
     ev_o = np.linalg.eigvalsh(C_o)[::-1][:20]
     errs = {"sample": f"first {nsamp} samples, vs the FP64 oracle"}
     for name in variants:
@@ -338,6 +432,22 @@ def run_mixture(pds, steps, warmup):
     lib.pds_profile_enable(0)
     kern2 = profile_report(lib)
     t_2 = sum(d["avg_ms"] for k2, d in kern2.items() if k2.startswith("km2"))
+    # the covariance estimator on the same compressed samples (this workload's
+    # step is compress + covariance + T rounds)
+    ws_c = plan.workspace(pds.PDS_OP_COVARIANCE, n, device="cuda")
+    acc = torch.zeros((p, p), dtype=torch.float64, device="cuda")
+    Cm = torch.empty_like(acc)
+    pds.covariance(plan, vals, idx, acc=acc, ws=ws_c, C=Cm)
+    torch.cuda.synchronize()
+    lib.pds_profile_enable(1)
+    for _ in range(steps):
+        acc.zero_()
+        pds.covariance(plan, vals, idx, acc=acc, ws=ws_c, C=Cm)
+    torch.cuda.synchronize()
+    lib.pds_profile_enable(0)
+    kern_c = profile_report(lib)
+    t_cov = sum(d["total_ms"] for d in kern_c.values()) / steps
+    del acc, Cm, ws_c
     # best of R K-means++ starts on the same compression (Sec. VII keeps the best of 20 random starts)
     R = 20
     ws_b = plan.workspace(pds.PDS_OP_KMEANS_BEST, n, K, device="cuda")
@@ -372,6 +482,9 @@ def run_mixture(pds, steps, warmup):
                      "kernels_ms": {k2: d["avg_ms"] for k2, d in kern2.items()},
                      "reassigned_frac": reassigned},
         "best_of": best_of,
+        "covariance": {"ms": t_cov, "kernels_ms": {k: d["avg_ms"] for k, d in kern_c.items()},
+                       "algorithmic_gflop": 2.0 * n * m * m / 1e9},
+        "ms_per_step_with_covariance": wall * 1e3 + t_cov,
     }
 
 
@@ -582,11 +695,16 @@ def main():
         base, errs = cpu_baseline_and_errors(pds, X, p, m, args.cpu_samples, variants)
         out["cpu_baseline"] = base
         out["errors"] = errs
+        log("full-n covariance rows vs the oracle")
+        out["errors_full_n"] = full_n_row_errors(pds, X, p, m, variants)
+        log(f"errors_full_n: {json.dumps(out['errors_full_n'])}")
     else:
         out["cpu_baseline"] = None
     if not args.no_batch or not args.no_mixture:
         del X
         torch.cuda.empty_cache()
+    out["small"] = run_small(pds, max(1, min(args.steps, 10)))
+    log(f"small: {json.dumps(out['small'])}")
     if not args.no_mixture:
         out["mixture"] = run_mixture(pds, max(1, min(args.steps, 3)), 1)
         log(f"mixture: {json.dumps(out['mixture'])}")

@@ -183,7 +183,7 @@ def m_from_gamma(gamma, p):
 class MSelector:
     """Trained selector: FP32 parameters, feature standardization, limits."""
 
-    def __init__(self, params, mu, sd, target=0.1, tau=0.9, gamma_fallback=0.2, nsub=512, p=1024, meta=None,
+    def __init__(self, params, mu, sd, target=0.1, tau=0.9, gamma_fallback=1.0, nsub=512, p=1024, meta=None,
                  device="cuda"):
         torch = _torch()
         self.params = torch.as_tensor(np.asarray(params, np.float32), device=device).contiguous()

@@ -7,7 +7,11 @@ blocks (the ``msel`` generator of ``synth``), on the GPU.
 Steps: (1) features and labels of the training blocks (stream 1); (2) FP32
 training of the network; (3) on held-out blocks (stream 2): the selector's m
 (BF16 inference), the realized relative Frobenius error of the covariance
-estimator at that m, at the label m and at the fixed fallback m = 0.2 p.
+estimator at that m, at the label m and at the fixed comparison m = 0.2 p.
+The selector's fallback (for blocks whose features or output are not finite)
+is then set to the smallest single fixed m that meets the target on as many
+held-out blocks as the selector does: a conservative m measured on data the
+network did not see.
 Writes DIR/msel_eval.json (and the weights when --install is given, into the
 package).  Progress goes to stdout as the work proceeds.
 """
@@ -95,14 +99,13 @@ def main(argv=None):
 
     # (2) training
     t0 = time.time()
-    sel = msel.MSelector.fit(ftr, ytr.contiguous(), epochs=args.epochs, log=log, target=t, nsub=nsub, p=p,
-                             gamma_fallback=cfg["gamma_fallback"])
+    sel = msel.MSelector.fit(ftr, ytr.contiguous(), epochs=args.epochs, log=log, target=t, nsub=nsub, p=p)
     torch.cuda.synchronize()
     t_train = time.time() - t0
     log(f"training: {t_train:.1f} s")
 
     # (3) held-out evaluation
-    m_fix = msel.m_from_gamma(cfg["gamma_fallback"], p)
+    m_fix = msel.m_from_gamma(cfg["gamma_baseline"], p)
     plans = {}
 
     def plan_for(m):
@@ -171,13 +174,14 @@ def main(argv=None):
         ms_per_train_block=round(1e3 * t_gen / max(int(ltr.shape[0]), 1), 3),
         selector=dict(success=ok_sel, mean_gamma=float(m_sel.mean() / p), median_gamma=float(np.median(m_sel) / p)),
         label=dict(success=float((e_lab <= t).mean()), mean_gamma=float(m_lab.mean() / p)),
-        fixed_fallback=dict(m=m_fix, success=float((e_fix <= t).mean()), mean_gamma=m_fix / p),
+        fixed_baseline=dict(m=m_fix, success=float((e_fix <= t).mean()), mean_gamma=m_fix / p),
         fixed_m_for_same_success=dict(m=m_equal, gamma=m_equal / p),
         log_ratio_sel_over_label=dict(mean=float(np.log(m_sel / m_lab).mean()),
                                       mae=float(np.abs(np.log(m_sel / m_lab)).mean())),
         realized_err=dict(sel_median=float(np.median(e_sel)), label_median=float(np.median(e_lab))),
     )
     sel.meta.update(summary)
+    sel.gamma_fallback = m_equal / p
     with open(os.path.join(args.out_dir, "msel_eval.json"), "w") as f:
         json.dump(summary, f, indent=1, sort_keys=True)
     with open(os.path.join(args.out_dir, "msel_heldout_rows.json"), "w") as f:

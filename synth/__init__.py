@@ -171,7 +171,7 @@ def random_compressed(n, p, m, seed, dtype=np.float32, K=None):
 # ---------------------------------------------------------------------------
 # m-selector blocks
 # ---------------------------------------------------------------------------
-MSEL = dict(p=1024, n=8192, rank=(1, 50), amp=(50.0, 5.0e4), target=0.1, nsub=512, gamma_fallback=0.2,
+MSEL = dict(p=1024, n=8192, rank=(1, 50), amp=(50.0, 5.0e4), target=0.1, nsub=512, gamma_baseline=0.2,
             data_seed=5)
 
 

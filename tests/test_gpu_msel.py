@@ -252,3 +252,56 @@ def test_shipped_selector_on_fresh_blocks():
         ratios.append(m / m_lab)
     assert ok >= 6
     assert 0.5 < float(np.median(ratios)) < 2.0
+
+
+@pytest.mark.skipif(not os.path.exists(msel.WEIGHTS), reason="selector weights not trained")
+def test_selector_gain_over_fixed_m():
+    """What the trained network gains over the method without it, on 40 fresh
+    blocks (a stream used neither for training nor for the held-out
+    evaluation): the share of blocks meeting the 10% target and the mean
+    m / p of (a) the selector's per-block m, (b) the fixed comparison
+    m = 0.2 p, and (c) the smallest single fixed m (on a grid of step 32)
+    that meets the target on at least as many blocks as the selector.  The
+    selector must meet the target far more often than (b) and, at equal
+    success, keep fewer coordinates than (c)."""
+    sel = msel.MSelector.load()
+    cfg = synth.MSEL
+    p, n, t = cfg["p"], cfg["n"], cfg["target"]
+    ctx = msel.MselContext(p=p, n=n, seed=0)
+    grid = list(range(192, p, 32))
+    m_base = msel.m_from_gamma(cfg["gamma_baseline"], p)
+    plans = {}
+    C = torch.empty((p, p), dtype=torch.float64, device="cuda")
+
+    def err_at(X, m):
+        if m >= p:
+            return 0.0
+        if m not in plans:
+            plans[m] = pds.Plan(p, m, 0, pds.PDS_F32)
+        vals, idx = pds.compress(plans[m], X)
+        d = msel.frob_diff(pds.covariance(plans[m], vals, idx), C).cpu().numpy()
+        return math.sqrt(d[0] / d[1])
+
+    nb = 40
+    m_sel, e_sel, e_base, e_grid = [], [], [], []
+    for b in range(nb):
+        Xn, prm = synth.msel_block_numpy(11, b)
+        X = to_dev(Xn)
+        m = sel.choose_m(ctx, X)
+        ctx.label(X, target=t, C_out=C)  # C = the exact C_emp of the block
+        m_sel.append(m)
+        e_sel.append(err_at(X, m))
+        e_base.append(err_at(X, m_base))
+        e_grid.append([err_at(X, mg) for mg in grid])
+    e_grid = np.array(e_grid)
+    s_sel = float(np.mean(np.array(e_sel) <= t))
+    s_base = float(np.mean(np.array(e_base) <= t))
+    s_grid = (e_grid <= t).mean(axis=0)
+    reach = [mg for mg, s in zip(grid, s_grid) if s >= s_sel]
+    m_equal = reach[0] if reach else p
+    g_sel = float(np.mean(m_sel)) / p
+    log(f"selector: success {s_sel:.3f}, mean m/p {g_sel:.3f}; fixed m = {m_base}: success {s_base:.3f}; "
+        f"fixed m with the selector's success: {m_equal} (m/p {m_equal / p:.3f})")
+    assert s_sel >= 0.7
+    assert s_base <= 0.2 and s_sel >= s_base + 0.5
+    assert g_sel <= 0.85 * (m_equal / p)
