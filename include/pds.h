@@ -254,6 +254,23 @@ pds_status pds_kmeans_step(pds_plan plan, const void* vals, const uint16_t* idx,
                            const double* centers_in, double* centers_out, int32_t* assign, double* objective,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * K-means iteration as pds_kmeans_step, same kernels and results, with its
+ * workspace taken from a scratch array the library holds in device memory
+ * (PDS_NOALLOC_SCRATCH_BYTES per GPU, reserved when the library is loaded and
+ * kept until the process ends) instead of a caller's buffer.  The call
+ * allocates nothing.  Every call on one GPU shares that GPU's array: calls
+ * that may overlap on one GPU (two streams, two threads) race and must be
+ * ordered by the caller.  Arguments as for pds_kmeans_step without ws.
+ * Errors: as pds_kmeans_step; PDS_E_WORKSPACE when the workspace
+ * pds_workspace_size(KMEANS, n, K) would exceed PDS_NOALLOC_SCRATCH_BYTES
+ * (64 MiB covers, e.g., n = 2^20, p = 1024, K = 10 in FP32). */
+#define PDS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pds_status pds_kmeans_step_noalloc(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K,
+                                   const double* centers_in, double* centers_out, int32_t* assign,
+                                   double* objective, void* stream);
+
 /* Unmixing of centers (eq. mu-mu'; Alg. 1, last step): centers_out[k] =
  * (H D)^T centers_pre[k] = D H centers_pre[k] (H is symmetric), FP64.
  * centers_pre / centers_out: device, K x p doubles (may not alias).

@@ -124,6 +124,36 @@ ProfScope::~ProfScope()
 
 }  // namespace pds
 
+// Scratch array of pds_kmeans_step_noalloc: one copy per GPU, reserved with
+// the code object and kept until the process ends.  In host code `scratch`
+// names a host-side stand-in, not device memory: kernels and copies take the
+// device address that hipGetSymbolAddress returns for the current device,
+// looked up once per device and cached.
+static constexpr size_t kNoAllocScratchBytes = PDS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+std::mutex g_scratch_mu;
+
+// `dev` must be the current device.
+hipError_t noalloc_scratch(int dev, void** out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
 static pds_status check_plan(pds_plan plan)
 {
     if (!plan) return fail(PDS_E_ARG, "plan is NULL");
@@ -440,6 +470,36 @@ pds_status pds_kmeans_step(pds_plan plan, const void* vals, const uint16_t* idx,
     e = pds::launch_kmeans_step(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, K, centers_in, centers_out,
                                 assign, objective, ws, ws_bytes, dev, s);
     if (e != hipSuccess) return hip_fail(e, "kmeans_step");
+    return PDS_OK;
+}
+
+pds_status pds_kmeans_step_noalloc(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K,
+                                   const double* centers_in, double* centers_out, int32_t* assign,
+                                   double* objective, void* stream)
+{
+    if (pds_status st = check_plan(plan)) return st;
+    if (n < 0) return fail(PDS_E_ARG, "n < 0");
+    if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
+    if (n == 0) return PDS_OK;
+    if (!vals || !idx || !centers_in || !centers_out || !assign || !objective)
+        return fail(PDS_E_ARG, "vals, idx, centers_in, centers_out, assign and objective must be non-NULL");
+    if (centers_in == centers_out) return fail(PDS_E_ARG, "centers_in and centers_out must not alias");
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_kmeans_step_noalloc");
+    const size_t need = pds::kmeans_workspace(plan->prec, (int)plan->p, (int)plan->m, n, K, dev);
+    if (need > kNoAllocScratchBytes)
+        return fail(PDS_E_WORKSPACE,
+                    "kmeans_step_noalloc: this call needs %zu workspace bytes, more than the %zu bytes of the "
+                    "library's scratch array; call pds_kmeans_step with a workspace instead",
+                    need, kNoAllocScratchBytes);
+    void* ws = nullptr;
+    e = noalloc_scratch(dev.device, &ws);
+    if (e != hipSuccess) return hip_fail(e, "kmeans_step_noalloc: address of the scratch array");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    e = pds::launch_kmeans_step(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, K, centers_in, centers_out,
+                                assign, objective, ws, kNoAllocScratchBytes, dev, s);
+    if (e != hipSuccess) return hip_fail(e, "kmeans_step_noalloc");
     return PDS_OK;
 }
 

@@ -87,6 +87,14 @@ def test_hot_calls_validate_before_device_work():
     assert L.pds_kmeans_step(h, fake, fake, 4, 3, fake, fake, null, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
     assert L.pds_kmeans_step(h, fake, fake, 4, 3, fake, fake, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG  # alias
     assert L.pds_kmeans_step(h, null, null, 0, 3, null, null, null, null, null, 0, null) == _lib.PDS_OK
+    # kmeans without allocation: same argument checks, before any device query
+    assert L.pds_kmeans_step_noalloc(None, fake, fake, 4, 3, fake, fake, fake, fake, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_step_noalloc(h, fake, fake, -1, 3, fake, fake, fake, fake, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_step_noalloc(h, fake, fake, 4, 0, fake, fake, fake, fake, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_step_noalloc(h, fake, fake, 4, 1025, fake, fake, fake, fake, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_step_noalloc(h, fake, fake, 4, 3, fake, fake, null, fake, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_step_noalloc(h, fake, fake, 4, 3, fake, fake, fake, fake, null) == _lib.PDS_E_ARG  # alias
+    assert L.pds_kmeans_step_noalloc(h, null, null, 0, 3, null, null, null, null, null) == _lib.PDS_OK
     # unmix
     assert L.pds_unmix(h, fake, 0, ctypes.c_void_p(0x2000), null) == _lib.PDS_E_ARG
     assert L.pds_unmix(h, null, 2, fake, null) == _lib.PDS_E_ARG
