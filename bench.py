@@ -5,9 +5,11 @@ HBM: compress (signs, normalized Walsh-Hadamard transform, exact-m sampling,
 gather) and the covariance estimator (Gram accumulation, FP64 split
 reduction, diagonal-corrected scaling).  Workload: n = 2^20 samples, p = 4096,
 m = 410 (gamma = 0.1), FP32 input with a rank-20 spiked covariance
-(lam_k = 50 / k) plus unit noise.  Two variants run back to back: the
-split-BF16 matrix-core form (reported as `value`) and plain FP32 (reported
-under `fp32_variant`).
+(lam_k = 50 / k) plus unit noise.  Three variants run back to back: the
+split-BF16 matrix-core form (reported as `value`), plain FP32 on dense FP32
+matrix-core tiles (`f32_variant`, the like-for-like comparison), and FP32 with
+the sparse Gram of exact products (`f32_sparse_variant`); the faster of the two
+FP32 forms is named in `fastest_exact_f32`.
 
 Prints one JSON line on stdout.  Per-kernel durations come from HIP events the
 library records around each launch on the launch stream (pds_profile_*).
@@ -53,7 +55,11 @@ def algorithmic_work(name, n, p, m, prec):
     """(bound, units per launch, unit, peak) for a kernel: bytes for HBM-bound
     kernels, flops for matrix-core kernels (2 flops per multiply-add)."""
     eb = 8 if prec == "f64" else 4
-    if name.startswith("gram_"):
+    if name == "gram_sparse":
+        # exact FP32 products between kept entries on the vector ALUs, summed
+        # with integer LDS atomics: priced as FP32 vector work
+        return "alu", 2.0 * n * m * m, "TFLOP/s", PEAK_TFLOPS["f32"]
+    if name.startswith("gram_") and name != "gram_pack" and name != "gram_reduce":
         dt = {"gram_bf16x3": "bf16", "gram_f32": "f32", "gram_f64": "f64"}[name]
         # G = sum_i w_i w_i^T: m^2 multiply-adds per sample (upper + lower)
         return "mfma", 2.0 * n * m * m, "TFLOP/s", PEAK_TFLOPS[dt]
@@ -96,12 +102,21 @@ def load_traffic(kernel, launches_per_step):
     return k.get("hbm_bytes_per_launch")
 
 
+def variant_plan(pds, name):
+    """(precision, Gram form) of a bench variant: split and f32 are the
+    metric's two matrix-core forms (dense Gram tiles); f32_sparse and
+    split_sparse take the sparse Gram (exact FP32 products)."""
+    return {"split": (pds.PDS_SPLIT_BF16, pds.PDS_GRAM_DENSE), "f32": (pds.PDS_F32, pds.PDS_GRAM_DENSE),
+            "f32_sparse": (pds.PDS_F32, pds.PDS_GRAM_SPARSE),
+            "split_sparse": (pds.PDS_SPLIT_BF16, pds.PDS_GRAM_SPARSE)}[name]
+
+
 def run_variant(pds, X, p, m, prec_name, steps, warmup):
     import torch
 
-    prec = {"split": pds.PDS_SPLIT_BF16, "f32": pds.PDS_F32}[prec_name]
+    prec, gram = variant_plan(pds, prec_name)
     n = X.shape[0]
-    plan = pds.Plan(p, m, seed=0, prec=prec)
+    plan = pds.Plan(p, m, seed=0, prec=prec, gram=gram)
     vals = torch.empty((n, m), dtype=torch.float32, device=X.device)
     idx = torch.empty((n, m), dtype=torch.int16, device=X.device)
     ws = plan.workspace(pds.PDS_OP_COVARIANCE if hasattr(pds, "PDS_OP_COVARIANCE") else 1, n, device=X.device)
@@ -175,8 +190,8 @@ def full_n_row_errors(pds, X, p, m, variants, per_block=8, seed=2024):
                      "vs the FP64 oracle", "oracle_s": time.perf_counter() - t0}
     Jd = torch.as_tensor(J, device=X.device)
     for name in variants:
-        prec = {"split": pds.PDS_SPLIT_BF16, "f32": pds.PDS_F32}[name]
-        plan = pds.Plan(p, m, seed=0, prec=prec)
+        prec, gram = variant_plan(pds, name)
+        plan = pds.Plan(p, m, seed=0, prec=prec, gram=gram)
         vals, idx = pds.compress(plan, X)
         C = pds.covariance(plan, vals, idx)
         Cg = C[Jd].cpu().numpy()
@@ -259,8 +274,8 @@ def cpu_baseline_and_errors(pds, X, p, m, nsamp, variants):
     ev_o = np.linalg.eigvalsh(C_o)[::-1][:20]
     errs = {"sample": f"first {nsamp} samples, vs the FP64 oracle"}
     for name in variants:
-        prec = {"split": pds.PDS_SPLIT_BF16, "f32": pds.PDS_F32}[name]
-        plan = pds.Plan(p, m, seed=0, prec=prec)
+        prec, gram = variant_plan(pds, name)
+        plan = pds.Plan(p, m, seed=0, prec=prec, gram=gram)
         vals, idx = pds.compress(plan, X[:nsamp])
         C = pds.covariance(plan, vals, idx)
         torch.cuda.synchronize()
@@ -483,7 +498,8 @@ def run_mixture(pds, steps, warmup):
                      "reassigned_frac": reassigned},
         "best_of": best_of,
         "covariance": {"ms": t_cov, "kernels_ms": {k: d["avg_ms"] for k, d in kern_c.items()},
-                       "algorithmic_gflop": 2.0 * n * m * m / 1e9},
+                       "algorithmic_gflop": 2.0 * n * m * m / 1e9,
+                       "gram_form": "sparse" if plan.gram_form(n) == pds.PDS_GRAM_SPARSE else "dense"},
         "ms_per_step_with_covariance": wall * 1e3 + t_cov,
     }
 
@@ -591,7 +607,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="samples (default: the workload's 2^20)")
-    ap.add_argument("--variants", default="split,f32")
+    ap.add_argument("--variants", default="split,f32,f32_sparse")
     ap.add_argument("--cpu-samples", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -667,7 +683,15 @@ def main():
                                "kernels_ms": {k: d["avg_ms"] for k, d in res[v]["kernels"].items()},
                                "roofline": roofline(res[v]["kernels"], n, p, m, v, args.steps)}
     if len(variants) > 1:
+        # like for like: both forms on dense matrix-core Gram tiles
         out["split_over_f32"] = res["split"]["value"] / res["f32"]["value"] if "f32" in res and "split" in res else None
+        exact = [v for v in ("f32", "f32_sparse") if v in res]
+        if exact:
+            best = max(exact, key=lambda v: res[v]["value"])
+            out["fastest_exact_f32"] = {"variant": best, "value": res[best]["value"],
+                                        "ms_per_step": res[best]["ms_per_step"],
+                                        "split_over_it": res["split"]["value"] / res[best]["value"]
+                                        if "split" in res else None}
     # the eigen-solve (top 20 of C_n, FP64) is timed on its own, outside the step
     if not args.no_eigen:
         C_head = res[head]["C"]

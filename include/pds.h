@@ -62,6 +62,24 @@ typedef enum {
  *                  across sample ranges stay in FP64.  K-means as PDS_F32.   */
 typedef enum { PDS_F64 = 0, PDS_F32 = 1, PDS_SPLIT_BF16 = 2 } pds_prec;
 
+/* How pds_covariance accumulates G = sum_i w_i w_i^T (Sec. V, the definition
+ * of C_emp_hat) for FP32 and split plans.
+ *   PDS_GRAM_DENSE  the precision's matrix-core form above: dense output
+ *                   tiles over chunks of samples, p^2 / 2 multiply-adds per
+ *                   sample (x 3 products for split plans), of which only the
+ *                   m^2 / 2 between kept entries are non-zero.
+ *   PDS_GRAM_SPARSE only the m^2 / 2 products between each sample's kept
+ *                   entries: exact FP32 products of the FP32 values, summed
+ *                   as 32-bit fixed point over ranges of at most 2048 samples
+ *                   (scale from the range's largest |value|, every sum exact
+ *                   and independent of the order of addition) and then in
+ *                   FP64; deterministic.  A non-finite value makes the
+ *                   affected tiles NaN.  Not available for FP64 plans.
+ *   PDS_GRAM_AUTO   (the default) the form a cost model of both on MI355X
+ *                   predicts to be faster for (p, m, n): the sparse form at
+ *                   small m / p, the dense form as m approaches p.        */
+typedef enum { PDS_GRAM_AUTO = 0, PDS_GRAM_DENSE = 1, PDS_GRAM_SPARSE = 2 } pds_gram_algo;
+
 /* Operation selector for pds_workspace_size. */
 typedef enum {
     PDS_OP_COMPRESS = 0,
@@ -92,6 +110,16 @@ pds_status pds_plan_destroy(pds_plan plan);
  * Philox4x64-10 block with key (seed, 0) and counter (j div 256, 0, 1, 0) is
  * zero.  Host-only. */
 pds_status pds_signs(pds_plan plan, int8_t* D_host);
+
+/* Sets the plan's Gram form (pds_gram_algo; the plan starts with
+ * PDS_GRAM_AUTO).  Host-only.  Errors: PDS_E_ARG (unknown value),
+ * PDS_E_UNSUPPORTED (PDS_GRAM_SPARSE on an FP64 plan). */
+pds_status pds_plan_set_gram(pds_plan plan, int32_t algo);
+
+/* The form pds_covariance will run for a call with n samples
+ * (PDS_GRAM_DENSE or PDS_GRAM_SPARSE) into *algo.  Host-only.
+ * Errors: PDS_E_ARG (NULL algo, n < 0). */
+pds_status pds_plan_gram(pds_plan plan, int64_t n, int32_t* algo);
 
 /* Device workspace bytes that `op` needs for n samples (and K clusters for
  * PDS_OP_KMEANS and PDS_OP_KMEANS2); PDS_OP_COVARIANCE also reports what its accumulator needs

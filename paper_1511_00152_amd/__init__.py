@@ -15,14 +15,15 @@ the current HIP device; every call enqueues the library's kernels on
 import ctypes
 
 from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_EXPLAINED_WS_BYTES, PDS_F32,
-                   PDS_F64, PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_KMEANS_BEST,
+                   PDS_F64, PDS_GRAM_AUTO, PDS_GRAM_DENSE, PDS_GRAM_SPARSE, PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_KMEANS_BEST,
                    PDS_OP_KMEANSPP, PDS_OP_MEAN, PDS_SPLIT_BF16, EXPORTS, PdsError, check, lib)
 
 __all__ = [
     "Plan", "compress", "pad_rows", "covariance", "CovarianceAccumulator", "sample_mean", "kmeanspp", "kmeans_best",
     "kmeans_step", "unmix", "kmeans_2pass", "sparsified_kmeans", "top_eigenvalues", "principal_components",
     "explained_variance",
-    "PdsError", "PDS_F64", "PDS_F32", "PDS_SPLIT_BF16", "lib", "EXPORTS",
+    "PdsError", "PDS_F64", "PDS_F32", "PDS_SPLIT_BF16", "PDS_GRAM_AUTO", "PDS_GRAM_DENSE", "PDS_GRAM_SPARSE", "lib",
+    "EXPORTS",
 ]
 
 
@@ -37,13 +38,22 @@ def _ptr(t):
 
 
 class Plan:
-    """pds_plan: dimension p, kept coordinates m, seed, precision."""
+    """pds_plan: dimension p, kept coordinates m, seed, precision, and the
+    covariance's Gram form (PDS_GRAM_AUTO, PDS_GRAM_DENSE or PDS_GRAM_SPARSE)."""
 
-    def __init__(self, p: int, m: int, seed: int = 0, prec: int = PDS_F32):
+    def __init__(self, p: int, m: int, seed: int = 0, prec: int = PDS_F32, gram: int = PDS_GRAM_AUTO):
         self.p, self.m, self.seed, self.prec = int(p), int(m), int(seed), int(prec)
         h = ctypes.c_void_p()
         check(lib().pds_plan_create(ctypes.byref(h), self.p, self.m, self.seed, self.prec), "pds_plan_create")
         self._h = h
+        if gram != PDS_GRAM_AUTO:
+            check(lib().pds_plan_set_gram(h, int(gram)), "pds_plan_set_gram")
+
+    def gram_form(self, n: int) -> int:
+        """PDS_GRAM_DENSE or PDS_GRAM_SPARSE: the form a covariance call over n samples runs."""
+        a = ctypes.c_int32(0)
+        check(lib().pds_plan_gram(self._h, int(n), ctypes.byref(a)), "pds_plan_gram")
+        return int(a.value)
 
     @property
     def handle(self):

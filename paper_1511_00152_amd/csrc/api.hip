@@ -23,6 +23,7 @@ struct pds_plan_s {
     int64_t m;
     uint64_t seed;
     int32_t prec;
+    int32_t gram;  // pds_gram_algo
 };
 
 struct pds_batch_s {
@@ -194,7 +195,30 @@ pds_status pds_plan_create(pds_plan* out, int64_t p, int64_t m, uint64_t seed, i
     pl->m = m;
     pl->seed = seed;
     pl->prec = prec;
+    pl->gram = PDS_GRAM_AUTO;
     *out = pl;
+    return PDS_OK;
+}
+
+pds_status pds_plan_set_gram(pds_plan plan, int32_t algo)
+{
+    if (pds_status st = check_plan(plan)) return st;
+    if (algo != PDS_GRAM_AUTO && algo != PDS_GRAM_DENSE && algo != PDS_GRAM_SPARSE)
+        return fail(PDS_E_ARG, "unknown Gram form %d", (int)algo);
+    if (algo == PDS_GRAM_SPARSE && plan->prec == PDS_F64)
+        return fail(PDS_E_UNSUPPORTED, "the sparse Gram form takes FP32 values (FP32 and split plans)");
+    plan->gram = algo;
+    return PDS_OK;
+}
+
+pds_status pds_plan_gram(pds_plan plan, int64_t n, int32_t* algo)
+{
+    if (pds_status st = check_plan(plan)) return st;
+    if (!algo) return fail(PDS_E_ARG, "algo is NULL");
+    if (n < 0) return fail(PDS_E_ARG, "n < 0");
+    pds::DeviceInfo dev = query_dev_or_default();
+    *algo = pds::covariance_is_sparse(plan->prec, (int)plan->p, (int)plan->m, n, dev, plan->gram) ? PDS_GRAM_SPARSE
+                                                                                                  : PDS_GRAM_DENSE;
     return PDS_OK;
 }
 
@@ -232,7 +256,7 @@ pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, s
             *bytes = pds::compress_workspace(plan->prec, p, n, dev);
             return PDS_OK;
         case PDS_OP_COVARIANCE:
-            *bytes = pds::covariance_workspace(plan->prec, p, m, n, dev);
+            *bytes = pds::covariance_workspace(plan->prec, p, m, n, dev, plan->gram);
             return PDS_OK;
         case PDS_OP_KMEANS:
             if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
@@ -301,13 +325,13 @@ pds_status pds_covariance(pds_plan plan, const void* vals, const uint16_t* idx, 
     pds::DeviceInfo dev;
     hipError_t e = pds::device_info(dev);
     if (e != hipSuccess) return hip_fail(e, "pds_covariance");
-    const size_t need = pds::covariance_workspace(plan->prec, (int)plan->p, (int)plan->m, n, dev);
+    const size_t need = pds::covariance_workspace(plan->prec, (int)plan->p, (int)plan->m, n, dev, plan->gram);
     if (need > 0 && (!ws || ws_bytes < need))
         return fail(PDS_E_WORKSPACE, "covariance needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (n > 0) {
         e = pds::launch_covariance_accumulate(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, acc, ws, ws_bytes,
-                                              dev, s);
+                                              dev, s, plan->gram);
         if (e != hipSuccess) return hip_fail(e, "covariance accumulate");
     }
     if (finalize) {
@@ -596,7 +620,7 @@ MselLayout msel_layout(int p, int64_t n, const pds::DeviceInfo& dev)
     L.c = o;
     o += up256((size_t)p * p * sizeof(double));
     L.cov = o;
-    o += up256(pds::covariance_workspace(PDS_F32, p, p, n, dev) + pds::compress_workspace(PDS_F32, p, n, dev));
+    o += up256(pds::covariance_workspace(PDS_F32, p, p, n, dev, PDS_GRAM_DENSE) + pds::compress_workspace(PDS_F32, p, n, dev));
     L.frob = o;
     o += up256(pds::frob_workspace());
     L.sums = o;
@@ -630,7 +654,7 @@ pds_status msel_exact(pds_plan plan, const float* X, int64_t n, int64_t ldx, uns
     if (e == hipSuccess) e = pds::launch_compress(PDS_F32, plan->seed, p, p, X, n, ldx, idx, Y, cws, cws_bytes, dev, s);
     if (e == hipSuccess) e = pds::launch_row_moments(X, n, p, ldx, reinterpret_cast<double*>(w + L.mr), dev, s);
     if (e == hipSuccess) e = pds::launch_row_moments(Y, n, p, p, reinterpret_cast<double*>(w + L.my), dev, s);
-    if (e == hipSuccess) e = pds::launch_covariance_accumulate(PDS_F32, p, p, Y, idx, n, acc, cws, cws_bytes, dev, s);
+    if (e == hipSuccess) e = pds::launch_covariance_accumulate(PDS_F32, p, p, Y, idx, n, acc, cws, cws_bytes, dev, s, PDS_GRAM_DENSE);
     if (e == hipSuccess) e = pds::launch_covariance_finalize(PDS_F32, p, p, n, acc, C, s);
     if (e == hipSuccess)
         e = pds::launch_frob_diff(C, C, (int64_t)p * p, reinterpret_cast<double*>(w + L.sums),

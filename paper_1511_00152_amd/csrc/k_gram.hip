@@ -179,11 +179,17 @@ constexpr int kPackStageBytes = 32768;  // chunk index rows staged in LDS up to 
 
 // STAGE: the chunk's index rows (at most kPackStageBytes, 16-byte aligned
 // source) are copied to LDS with 16-byte loads first; otherwise read in place.
+// eb: bytes of one sample slot in OA.  The sparse Gram packs with tr = tc,
+// rowbytes = 1 and eb = 128, so that OA = (sample << 7) | coordinate-in-block,
+// and also takes SS[c][b][s] (start of sample s inside block b's run, uint16)
+// and CM[c] (the chunk's largest |value|, FP32 bits); both are skipped when
+// NULL.
 template <bool STAGE>
 __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
-                                                   int64_t n, int m, int tr, int tc, int nbc, int rowbytes, int split,
-                                                   uint32_t* __restrict__ P, uint16_t* __restrict__ OA,
-                                                   uint32_t* __restrict__ BS)
+                                                   int64_t n, int m, int tr, int tc, int nbc, int rowbytes, int eb,
+                                                   int split, uint32_t* __restrict__ P, uint16_t* __restrict__ OA,
+                                                   uint32_t* __restrict__ BS, uint16_t* __restrict__ SS,
+                                                   uint32_t* __restrict__ CM)
 {
     extern __shared__ __align__(16) uint32_t pk_sh[];
     const int nb1 = nbc + 1;
@@ -194,7 +200,6 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     const int64_t i0 = c * kChunk;
     const int ns = (int)((n - i0) < kChunk ? (n - i0) : kChunk);
     const int tid = threadIdx.x;
-    const int eb = split ? 2 : 4;
     const int sh_c = __builtin_ctz((unsigned)tc);
 
     const int tot = ns * m;
@@ -258,10 +263,21 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     }
     if (tid == 0) bs[nbc] = (uint32_t)ns * (uint32_t)m;
     __syncthreads();
+    if (SS) {
+        // start of segment (b, s) relative to block b's run
+        uint16_t* ssc = SS + c * (int64_t)Q;
+        for (int q = tid; q < Q; q += 256) {
+            const int b = q >> 5, s = q & 31;
+            const uint32_t st = seg[q] + off[s * nb1 + b];
+            const uint32_t s0 = seg[b * kChunk] + off[b];
+            ssc[q] = (uint16_t)(st - s0);
+        }
+    }
 
     uint32_t* Pc = P + c * (int64_t)kChunk * m;
     uint16_t* OAc = OA + c * (int64_t)kChunk * m;
     const float* cval = vals + i0 * (int64_t)m;
+    uint32_t vmax = 0u;  // largest |value| as FP32 bits: NaN and infinity order above every finite value
 #pragma unroll 4
     for (int f = tid; f < tot; f += 256) {
         int s = (int)((float)f * inv_m);
@@ -270,8 +286,25 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
         const uint32_t j = cidx[f];
         const uint32_t q = seg[((int)j >> sh_c) * kChunk + s] + (uint32_t)(f - s * m);
         const float v = cval[f];
+        const uint32_t vb = __float_as_uint(v) & 0x7fffffffu;
+        vmax = vb > vmax ? vb : vmax;
         Pc[q] = split ? split_bits(v) : __float_as_uint(v);
         OAc[q] = (uint16_t)((j & (uint32_t)(tr - 1)) * rowbytes + s * eb);
+    }
+    if (CM) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t t = (uint32_t)__shfl_xor((int)vmax, o, 64);
+            vmax = t > vmax ? t : vmax;
+        }
+        __syncthreads();  // wsum is free again
+        if ((tid & 63) == 0) wsum[tid >> 6] = vmax;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t mx = wsum[0];
+            for (int w = 1; w < 4; ++w) mx = wsum[w] > mx ? wsum[w] : mx;
+            CM[c] = mx;
+        }
     }
 }
 
@@ -631,6 +664,359 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Sparse Gram (FP32 values, exact products): each workgroup owns one W x W
+// upper tile (row block A, column block B, W = min(p, 128)) and one span of
+// chunks.  For every sample of a chunk, each of its kept entries in block A
+// (one per thread) is multiplied with each of its kept entries in block B
+// (staged in LDS) and the product is added into the tile at (row, column) --
+// m^2 multiply-adds per sample in all instead of the dense tile's p^2.
+//
+// The adds are integer LDS atomics (the FP32 ones are far slower): over a
+// range of at most 2048 samples the products are fixed point, v_a v_b 2^F
+// rounded to the nearest integer, with F the largest integer for which
+// c v^2 2^F + c / 2 < 2^31: v is the range's largest |value| (the pack's
+// per-chunk maxima) and c the largest number of the range's samples that
+// kept any one coordinate (k_range_counts).  An entry (j, k) receives one
+// product per sample that kept both j and k -- at most c of them -- so its
+// sum cannot overflow and is exact.  At the end of each range the integer tile is added
+// into FP64 registers (sum * 2^-F, exact conversion) and cleared; the span's
+// tile is written once as FP32 partials, which the fixed-order FP64 reduction
+// sums.  Every sum is order-independent, so the result is deterministic.
+// ---------------------------------------------------------------------------
+constexpr int kSpRangeChunks = 64;                // chunks per fixed-point range (2048 samples)
+
+// RC[r] = the largest number of samples of range r (kSpRangeChunks chunks)
+// that kept one coordinate: a histogram of the range's indices in LDS, two
+// 16-bit counters per word (a range has at most 2048 samples).
+__global__ __launch_bounds__(1024) void k_range_counts(const uint16_t* __restrict__ idx, int64_t n, int m, int p,
+                                                       uint32_t* __restrict__ RC)
+{
+    extern __shared__ uint32_t hist[];
+    __shared__ uint32_t red[16];
+    const int tid = threadIdx.x;
+    const int nw = (p + 1) / 2;
+    const int64_t i0 = (int64_t)blockIdx.x * kSpRangeChunks * kChunk;
+    int64_t i1 = i0 + (int64_t)kSpRangeChunks * kChunk;
+    if (i1 > n) i1 = n;
+    for (int e = tid; e < nw; e += 1024) hist[e] = 0u;
+    __syncthreads();
+    const uint16_t* base = idx + i0 * (int64_t)m;
+    const int64_t tot = (i1 - i0) * (int64_t)m;
+#pragma unroll 4
+    for (int64_t f = tid; f < tot; f += 1024) {
+        const uint32_t j = base[f];
+        atomicAdd(&hist[j >> 1], 1u << (16u * (j & 1u)));
+    }
+    __syncthreads();
+    uint32_t mx = 0u;
+    for (int e = tid; e < nw; e += 1024) {
+        const uint32_t w = hist[e];
+        const uint32_t lo = w & 0xffffu, hi = w >> 16;
+        mx = lo > mx ? lo : mx;
+        mx = hi > mx ? hi : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t t = (uint32_t)__shfl_xor((int)mx, o, 64);
+        mx = t > mx ? t : mx;
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < 16; ++w) mx = red[w] > mx ? red[w] : mx;
+        RC[blockIdx.x] = mx;
+    }
+}
+
+constexpr int kSpW = 128;                         // tile edge (coordinates per block)
+constexpr int kSpStride = kSpW + 1;               // accumulator words per tile row
+constexpr int kSpThreads = 1024;                  // threads per workgroup (one workgroup per CU)
+constexpr int kSpWaves = kSpThreads / 64;
+constexpr int kSpEpt = kSpW * kSpW / kSpThreads;  // accumulators per thread (FP64 flush registers)
+constexpr int kSpStage = 512;                     // staged column entries per wave (one segment)
+constexpr int kSpUnitChunks = 1;                  // chunks per wave work unit (1 or 2)
+constexpr int kSpG = 8;                           // 64-entry groups of a unit's column run loaded at once
+
+// One CU's workgroup: the tile's integer accumulators, shared by the waves
+// (integer atomics), and a private staging area per wave.  The column run of
+// a unit is staged as (value bits, byte offset of the column in a tile row),
+// two entries per uint4, each sample's entries padded with zero products (pad
+// column kSpW) to a multiple of four, so that the products loop reads four at
+// a time with no bounds.
+struct SparseLds {
+    int32_t acc[kSpW * kSpStride];
+    uint4 stg[kSpWaves][kSpStage / 2];
+    uint32_t next;  // the range's next unit (wave work queue)
+};
+
+__device__ inline void sp_atomic4(unsigned char* base, float va, const uint4& a, const uint4& b)
+{
+    atomicAdd(reinterpret_cast<int*>(base + a.y), (int)rintf(va * __uint_as_float(a.x)));
+    atomicAdd(reinterpret_cast<int*>(base + a.w), (int)rintf(va * __uint_as_float(a.z)));
+    atomicAdd(reinterpret_cast<int*>(base + b.y), (int)rintf(va * __uint_as_float(b.x)));
+    atomicAdd(reinterpret_cast<int*>(base + b.w), (int)rintf(va * __uint_as_float(b.z)));
+}
+
+// Keeps the compiler from moving this wave's LDS accesses across the point;
+// the LDS serves one wave's accesses in order, so no barrier is needed for the
+// wave to read what it wrote.
+__device__ inline void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The largest F with cnt (v 2^F)^2 (1 + 2^-22) + cnt / 2 < 2^31: at most cnt
+// products of magnitude up to v^2 (their FP32 rounding included), each
+// rounded by at most 1/2.  F stays within [-140, 100], so v 2^F is finite.
+__device__ inline int sparse_scale(float vmax, uint32_t cnt)
+{
+    if (cnt == 0u || !(vmax > 0.0f)) return 0;
+    const double lim = 2147483647.0 - 0.5 * (double)cnt;
+    const double b = (double)cnt * (double)vmax * (double)vmax * (1.0 + 0x1p-22);
+    int F = (int)floor(log2(lim / b));
+    if (F > 100) F = 100;
+    if (F < -140) F = -140;
+    while (F > -140 && ldexp(b, F) >= lim) --F;
+    while (F < 100 && ldexp(b, F + 1) < lim) ++F;
+    return F;
+}
+
+// Runs of one unit: the two chunks' row-block and column-block runs (the
+// second chunk's empty past the range).
+struct SpUnitRuns {
+    uint32_t ra0, nra, rb0, nrb;  // row runs of chunks a and b
+    uint32_t ca0, nca, cb0, ncb;  // column runs
+};
+
+__global__ __launch_bounds__(kSpThreads, 4) void k_gram_sparse(const uint32_t* __restrict__ P,
+                                                               const uint16_t* __restrict__ OA,
+                                                               const uint32_t* __restrict__ BS,
+                                                               const uint16_t* __restrict__ SS,
+                                                               const uint32_t* __restrict__ CM,
+                                                               const uint32_t* __restrict__ RC, int m, TileGeom g,
+                                                               int64_t nchunks, int nsr, int64_t sr_chunks,
+                                                               float* __restrict__ part)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    SparseLds& L = *reinterpret_cast<SparseLds*>(smem_raw);
+    const int64_t total = (int64_t)g.ntiles * nsr;
+    const int64_t item = xcd_item(blockIdx.x, total);
+    if (item >= total) return;
+    const int sr = (int)(item / g.ntiles);
+    const int tile = (int)(item % g.ntiles);
+    int ta, tb;
+    decode_rect_tile(tile, g, ta, tb);
+    const int W = g.tc;
+    const int nb1 = g.nbc + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t c0 = (int64_t)sr * sr_chunks;
+    int64_t c1 = c0 + sr_chunks;
+    if (c1 > nchunks) c1 = nchunks;
+    const int64_t cstride = (int64_t)kChunk * m;
+    const int64_t sstride = (int64_t)g.nbc * kChunk;
+    uint2* stg = reinterpret_cast<uint2*>(L.stg[wave]);
+    const uint4* stg4 = L.stg[wave];
+
+    for (int e = tid; e < kSpW * kSpStride; e += kSpThreads) L.acc[e] = 0;
+    double accd[kSpEpt];
+#pragma unroll
+    for (int k = 0; k < kSpEpt; ++k) accd[k] = 0.0;
+    bool bad = false;
+
+    for (int64_t rc0 = c0; rc0 < c1; rc0 += kSpRangeChunks) {
+        const int64_t rc1 = (rc0 + kSpRangeChunks < c1) ? rc0 + kSpRangeChunks : c1;
+        const int units = (int)((rc1 - rc0 + kSpUnitChunks - 1) / kSpUnitChunks);
+        if (tid == 0) L.next = 0u;
+        // the range's scale, from its chunks' largest |value| (every wave alike)
+        uint32_t mx = (rc0 + lane < rc1) ? CM[rc0 + lane] : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t t = (uint32_t)__shfl_xor((int)mx, o, 64);
+            mx = t > mx ? t : mx;
+        }
+        if (mx >= 0x7f800000u) bad = true;  // a non-finite value: the tile becomes NaN
+        const int F = bad ? 0 : sparse_scale(__uint_as_float(mx), RC[rc0 / kSpRangeChunks]);
+        const float scale = ldexpf(1.0f, F);
+        __syncthreads();  // L.next set; the previous range's flush done
+
+        for (;;) {
+            uint32_t u = 0;
+            if (lane == 0) u = atomicAdd(&L.next, 1u);
+            u = (uint32_t)__builtin_amdgcn_readfirstlane((int)u);
+            if ((int)u >= units) break;
+            const int64_t ca = rc0 + kSpUnitChunks * (int64_t)u;
+            const bool has_b = kSpUnitChunks == 2 && ca + 1 < rc1;
+            const int64_t cb = has_b ? ca + 1 : ca;
+            // run bounds: lanes 0..3 chunk a, lanes 4..7 chunk b
+            const int bsel = lane & 3;
+            const int bcol = bsel == 0 ? ta : bsel == 1 ? ta + 1 : bsel == 2 ? tb : tb + 1;
+            const uint32_t bv = BS[((lane & 4) ? cb : ca) * nb1 + bcol];
+            SpUnitRuns R;
+            R.ra0 = (uint32_t)__builtin_amdgcn_readlane((int)bv, 0);
+            R.nra = (uint32_t)__builtin_amdgcn_readlane((int)bv, 1) - R.ra0;
+            R.ca0 = (uint32_t)__builtin_amdgcn_readlane((int)bv, 2);
+            R.nca = (uint32_t)__builtin_amdgcn_readlane((int)bv, 3) - R.ca0;
+            R.rb0 = (uint32_t)__builtin_amdgcn_readlane((int)bv, 4);
+            R.nrb = has_b ? (uint32_t)__builtin_amdgcn_readlane((int)bv, 5) - R.rb0 : 0u;
+            R.cb0 = (uint32_t)__builtin_amdgcn_readlane((int)bv, 6);
+            R.ncb = has_b ? (uint32_t)__builtin_amdgcn_readlane((int)bv, 7) - R.cb0 : 0u;
+            const uint32_t nC = R.nca + R.ncb, nR = R.nra + R.nrb;
+            // per-sample layout, lane = sample of the unit (chunk a: 0..31, chunk b: 32..63)
+            const uint32_t ssv = SS[((lane < kChunk) ? ca : cb) * sstride + tb * kChunk + (lane & (kChunk - 1))];
+            const uint32_t cs = (lane < kChunk) ? ssv : (has_b ? R.nca + ssv : nC);
+            const uint32_t nxt = (uint32_t)__shfl_down((int)cs, 1, 64);
+            const uint32_t cn = (lane == kChunk - 1) ? R.nca : (lane == 63 ? nC : nxt);
+            const uint32_t plen = (cn - cs + 3u) & ~3u;
+            uint32_t pen = plen;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)pen, d, 64);
+                if (lane >= d) pen += t;
+            }
+            uint32_t pst = pen - plen;
+            const uint32_t ptotal = (uint32_t)__builtin_amdgcn_readlane((int)pen, 63);
+            int seg = 0, nseg = 1;
+            if (ptotal > (uint32_t)kSpStage) {
+                // greedy: a sample that would overflow the current segment starts the next
+                uint32_t base = 0, my_base = 0;
+                int id = 0;
+                for (int t = 0; t < 64; ++t) {
+                    const uint32_t tst = (uint32_t)__builtin_amdgcn_readlane((int)pst, t);
+                    const uint32_t ten = (uint32_t)__builtin_amdgcn_readlane((int)pen, t);
+                    if (ten - base > (uint32_t)kSpStage) {
+                        ++id;
+                        base = tst;
+                    }
+                    if (lane == t) {
+                        seg = id;
+                        my_base = base;
+                    }
+                }
+                pst -= my_base;
+                pen -= my_base;
+                nseg = id + 1;
+            }
+            // the unit's entries, up to kSpG groups of 64 per run, requested
+            // together so that one memory latency covers the unit
+            auto gidx = [&](uint32_t q, uint32_t na, uint32_t a0, uint32_t b0, bool& inb) -> int64_t {
+                inb = q >= na;
+                return inb ? cb * cstride + b0 + (q - na) : ca * cstride + a0 + q;
+            };
+            // column entries: up to kSpG groups (indices two to a register)
+            uint32_t cpv[kSpG], cov2[kSpG / 2];
+#pragma unroll
+            for (int gg = 0; gg < kSpG; ++gg) {
+                cpv[gg] = 0u;
+                if (gg % 2 == 0) cov2[gg / 2] = 0u;
+                const uint32_t q = (uint32_t)(64 * gg + lane);
+                bool inb;
+                if ((uint32_t)(64 * gg) < nC) {
+                    const int64_t gq = gidx(q < nC ? q : 0u, R.nca, R.ca0, R.cb0, inb);
+                    cpv[gg] = P[gq];
+                    cov2[gg / 2] |= (uint32_t)OA[gq] << (16 * (gg % 2));
+                }
+            }
+            // stage one column entry (every lane calls: the lane reads need their sources active)
+            auto stage = [&](uint32_t q, uint32_t pv, uint32_t ov, int k) {
+                const bool live = q < nC;
+                const int s = live ? (int)(ov >> 7) + (q >= R.nca ? kChunk : 0) : 0;
+                const uint32_t scs = (uint32_t)__shfl((int)cs, s, 64);
+                const uint32_t scn = (uint32_t)__shfl((int)cn, s, 64);
+                const uint32_t spst = (uint32_t)__shfl((int)pst, s, 64);
+                const uint32_t spen = (uint32_t)__shfl((int)pen, s, 64);
+                const int sseg = __shfl(seg, s, 64);
+                if (live && sseg == k) {
+                    const uint32_t pos = spst + (q - scs);
+                    stg[pos] = make_uint2(pv, (ov & 127u) * 4u);
+                    if (q + 1 == scn)
+                        for (uint32_t dd = pos + 1; dd < spen; ++dd) stg[dd] = make_uint2(0u, (uint32_t)kSpW * 4u);
+                }
+            };
+            // products of one row entry with its sample's staged entries
+            auto products = [&](uint32_t q, uint32_t pv, uint32_t ov, int k) {
+                const bool live = q < nR;
+                const int s = live ? (int)(ov >> 7) + (q >= R.nra ? kChunk : 0) : 0;
+                const uint32_t u0 = (uint32_t)__shfl((int)pst, s, 64);
+                const uint32_t u1 = (uint32_t)__shfl((int)pen, s, 64);
+                const int sseg = __shfl(seg, s, 64);
+                if (live && sseg == k) {
+                    const float va = __uint_as_float(pv) * scale;
+                    unsigned char* base =
+                        reinterpret_cast<unsigned char*>(L.acc) + (ov & 127u) * (uint32_t)(kSpStride * 4);
+                    uint32_t v = u0;
+                    // eight entries per step: their four LDS reads are issued before the adds
+                    for (; v + 8 <= u1; v += 8) {
+                        const uint4 a = stg4[v / 2], b = stg4[v / 2 + 1], c = stg4[v / 2 + 2], d = stg4[v / 2 + 3];
+                        sp_atomic4(base, va, a, b);
+                        sp_atomic4(base, va, c, d);
+                    }
+                    if (v < u1) {
+                        const uint4 a = stg4[v / 2], b = stg4[v / 2 + 1];
+                        sp_atomic4(base, va, a, b);
+                    }
+                }
+            };
+            for (int k = 0; k < nseg; ++k) {
+                wave_lds_fence();  // the previous unit's or segment's reads of the stage come first
+#pragma unroll
+                for (int gg = 0; gg < kSpG; ++gg)
+                    if ((uint32_t)(64 * gg) < nC)
+                        stage((uint32_t)(64 * gg + lane), cpv[gg], (cov2[gg / 2] >> (16 * (gg % 2))) & 0xffffu, k);
+                for (uint32_t q0 = 64u * kSpG; q0 < nC; q0 += 64u) {  // long runs: further groups one by one
+                    const uint32_t q = q0 + (uint32_t)lane;
+                    bool inb;
+                    const int64_t gq = gidx(q < nC ? q : 0u, R.nca, R.ca0, R.cb0, inb);
+                    stage(q, P[gq], OA[gq], k);
+                }
+                wave_lds_fence();
+                // row entries, one group of 64 at a time with the next group's loads in flight
+                uint32_t rp = 0u, ro = 0u;
+                if (nR > 0u) {
+                    bool inb;
+                    const int64_t gq = gidx(lane < (int)nR ? (uint32_t)lane : 0u, R.nra, R.ra0, R.rb0, inb);
+                    rp = P[gq];
+                    ro = OA[gq];
+                }
+                for (uint32_t q0 = 0; q0 < nR; q0 += 64u) {
+                    const uint32_t q = q0 + (uint32_t)lane;
+                    uint32_t np = 0u, no = 0u;
+                    if (q0 + 64u < nR) {
+                        const uint32_t qn = q + 64u;
+                        bool inb;
+                        const int64_t gq = gidx(qn < nR ? qn : 0u, R.nra, R.ra0, R.rb0, inb);
+                        np = P[gq];
+                        no = OA[gq];
+                    }
+                    products(q, rp, ro, k);
+                    rp = np;
+                    ro = no;
+                }
+            }
+        }
+        __syncthreads();  // every unit of the range is summed
+        // the range's integer sums into FP64, then cleared for the next range
+#pragma unroll
+        for (int k = 0; k < kSpEpt; ++k) {
+            const int e = tid + kSpThreads * k;
+            const int i = e / W, j = e - (e / W) * W;
+            if (e < W * W) {
+                int32_t* a = &L.acc[i * kSpStride + j];
+                accd[k] += ldexp((double)*a, -F);
+                *a = 0;
+            }
+        }
+    }
+    float* out = part + ((int64_t)sr * g.ntiles + tile) * (int64_t)W * W;
+#pragma unroll
+    for (int k = 0; k < kSpEpt; ++k) {
+        const int e = tid + kSpThreads * k;
+        if (e < W * W) out[e] = bad ? __builtin_nanf("") : (float)accd[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 Gram tile kernel (vector ALUs): 64 x 64 tiles, 4 x 4 outputs per thread.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ vals, const uint16_t* __restrict__ idx,
@@ -755,10 +1141,13 @@ __global__ __launch_bounds__(256) void k_cov_finalize(const double* __restrict__
 // ---------------------------------------------------------------------------
 struct GramPlan {
     TileGeom geom;
+    bool sparse;                    // the sparse form (k_gram_sparse) instead of dense tiles
     int nsplit, sa, sb;
     int64_t split_len, nchunks;
     size_t off_bytes;               // FP64 variant: per-sample block offsets
-    size_t pk_bytes, bs_bytes;      // matrix-core variants: packed chunks (P, then OA) and block starts
+    size_t pk_bytes, bs_bytes;      // packed variants: packed chunks (P, then OA) and block starts
+    size_t ss_bytes, cm_bytes, rc_bytes;  // sparse form: per-sample run starts, per-chunk largest |value|,
+                                          // per-range largest coordinate count
     size_t part_bytes, diag_bytes;
 };
 
@@ -786,9 +1175,74 @@ static int run_slots(int p, int m, int w)
     return k;
 }
 
-static GramPlan gram_plan(int prec, int p, int m, int64_t n, const DeviceInfo& dev)
+// Which Gram form runs (algo: 0 = the faster by the cost model below, 1 =
+// dense tiles, 2 = sparse).  FP64 plans have the dense FP64 form only.  The
+// model prices each form from rates measured on MI355X (256 CUs, scaled by
+// the CU count): dense tiles execute n p^2 / 2 multiply-adds (x 3 products
+// for split plans) at 8.2e14 (split) or 6.0e13 (FP32) per second; the sparse
+// form costs n (5.4e-11 s per output tile + 3.9e-13 s m^2 / 2).
+static bool use_sparse(int prec, int p, int m, int64_t n, int algo, const DeviceInfo& dev)
+{
+    if (prec == 0) return false;
+    if (algo == 1) return false;
+    if (algo == 2) return true;
+    const double cu = (double)dev.cus / 256.0;
+    const double dense = (double)n * 0.5 * (double)p * (double)p * (prec == 2 ? 3.0 : 1.0) /
+                         ((prec == 2 ? 8.2e14 : 6.0e13) * cu);
+    const double nb = (double)(p < kSpW ? 1 : p / kSpW);
+    const double sparse = (double)n * (5.4e-11 * nb * (nb + 1.0) / 2.0 + 3.9e-13 * 0.5 * (double)m * (double)m) / cu;
+    return sparse < dense;
+}
+
+// Super-ranges of the sparse form: work items are (super-range, tile), one
+// resident per CU; the count is chosen so that the items fill whole rounds of
+// the chip (fewer rounds preferred on ties: each item writes one partial tile).
+static int sparse_super_ranges(int64_t ntiles, int64_t nchunks, const DeviceInfo& dev)
+{
+    const int64_t slots = (int64_t)dev.cus;
+    int best = 1;
+    double best_eff = -1.0;
+    for (int R = 1; R <= 64; ++R) {
+        int64_t nsr = (R * slots) / ntiles;
+        if (nsr < 1) nsr = 1;
+        if (nsr > nchunks) nsr = nchunks;
+        const int64_t items = nsr * ntiles;
+        const double eff = (double)items / (double)(((items + slots - 1) / slots) * slots);
+        if (eff > best_eff + 1e-3) {
+            best_eff = eff;
+            best = (int)nsr;
+        }
+    }
+    return best;
+}
+
+static GramPlan gram_plan(int prec, int p, int m, int64_t n, const DeviceInfo& dev, int algo)
 {
     GramPlan g;
+    g.sparse = use_sparse(prec, p, m, n, algo, dev);
+    g.ss_bytes = g.cm_bytes = g.rc_bytes = 0;
+    if (g.sparse) {
+        g.geom = make_geom(p, kSpW, kSpW);
+        g.sa = g.sb = 0;
+        const int64_t nchunks = (n + kChunk - 1) / kChunk;
+        g.nchunks = nchunks;
+        g.nsplit = sparse_super_ranges(g.geom.ntiles, nchunks, dev);
+        // a super-range is whole fixed-point ranges (except the last)
+        int64_t per = (nchunks + g.nsplit - 1) / g.nsplit;
+        per = ((per + kSpRangeChunks - 1) / kSpRangeChunks) * kSpRangeChunks;
+        g.nsplit = (int)((nchunks + per - 1) / per);
+        g.split_len = per;  // chunks per super-range
+        const size_t nn = (size_t)(n > 0 ? n : 0);
+        g.off_bytes = 0;
+        g.pk_bytes = up256(nn * (size_t)m * 4) + up256(nn * (size_t)m * 2);
+        g.bs_bytes = up256((size_t)nchunks * (g.geom.nbc + 1) * 4);
+        g.ss_bytes = up256((size_t)nchunks * g.geom.nbc * kChunk * 2);
+        g.cm_bytes = up256((size_t)nchunks * 4);
+        g.rc_bytes = up256((size_t)((nchunks + kSpRangeChunks - 1) / kSpRangeChunks) * 4);
+        g.part_bytes = up256((size_t)g.nsplit * g.geom.ntiles * (size_t)g.geom.tr * g.geom.tc * sizeof(float));
+        g.diag_bytes = 0;
+        return g;
+    }
     g.geom = (prec == 0) ? make_geom(p, kTileF64, kTileF64) : make_geom(p, kTR, kTC);
     g.sa = run_slots(p, m, g.geom.tr);
     g.sb = run_slots(p, m, g.geom.tc);
@@ -819,11 +1273,16 @@ static GramPlan gram_plan(int prec, int p, int m, int64_t n, const DeviceInfo& d
     return g;
 }
 
-size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo& dev)
+size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo& dev, int algo)
 {
     if (n <= 0) return 0;
-    GramPlan g = gram_plan(prec, p, m, n, dev);
-    return g.off_bytes + g.pk_bytes + g.bs_bytes + g.part_bytes + g.diag_bytes;
+    GramPlan g = gram_plan(prec, p, m, n, dev, algo);
+    return g.off_bytes + g.pk_bytes + g.bs_bytes + g.ss_bytes + g.cm_bytes + g.rc_bytes + g.part_bytes + g.diag_bytes;
+}
+
+bool covariance_is_sparse(int prec, int p, int m, int64_t n, const DeviceInfo& dev, int algo)
+{
+    return use_sparse(prec, p, m, n, algo, dev);
 }
 
 template <bool SPLIT, int SA, int SB>
@@ -869,21 +1328,91 @@ constexpr int kLdsMax = 160 * 1024;  // LDS of one workgroup on gfx950
 
 static size_t pack_lds_bytes(int nbc) { return ((size_t)kChunk * (nbc + 1) + (size_t)kChunk * nbc + 4) * 4; }
 
+static void pack_attrs()
+{
+    static bool pack_attr = false;
+    if (!pack_attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)pack_lds_bytes(65536 / kSpW));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+        pack_attr = true;
+    }
+}
+
+static hipError_t launch_pack(const GramPlan& g, int m, const float* vals, const uint16_t* idx, int64_t n,
+                              int rowbytes, int eb, int split, uint32_t* P, uint16_t* OA, uint32_t* BS, uint16_t* SS,
+                              uint32_t* CM, hipStream_t s)
+{
+    const bool stage = (size_t)kChunk * m * 2 <= (size_t)kPackStageBytes &&
+                       pack_lds_bytes(g.geom.nbc) + kPackStageBytes <= (size_t)kLdsMax &&
+                       (reinterpret_cast<uintptr_t>(idx) & 15) == 0;
+    // the staged rows take what they need (more workgroups per CU than a fixed 32 KB)
+    const size_t lds = pack_lds_bytes(g.geom.nbc) + (stage ? (((size_t)kChunk * m * 2 + 15) & ~(size_t)15) : 0);
+    pack_attrs();
+    ProfScope ps_("gram_pack", s);
+    if (stage)
+        hipLaunchKernelGGL(k_gram_pack<true>, dim3((unsigned)g.nchunks), dim3(256), lds, s, vals, idx, n, m,
+                           g.geom.tr, g.geom.tc, g.geom.nbc, rowbytes, eb, split, P, OA, BS, SS, CM);
+    else
+        hipLaunchKernelGGL(k_gram_pack<false>, dim3((unsigned)g.nchunks), dim3(256), lds, s, vals, idx, n, m,
+                           g.geom.tr, g.geom.tc, g.geom.nbc, rowbytes, eb, split, P, OA, BS, SS, CM);
+    return hipGetLastError();
+}
+
 hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n,
                                         double* acc, void* ws, size_t ws_bytes, const DeviceInfo& dev,
-                                        hipStream_t s)
+                                        hipStream_t s, int algo)
 {
     (void)ws_bytes;
     if (n <= 0) return hipSuccess;
-    GramPlan g = gram_plan(prec, p, m, n, dev);
+    GramPlan g = gram_plan(prec, p, m, n, dev, algo);
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
-    void* part = w + g.off_bytes + g.pk_bytes + g.bs_bytes;
-    double* pdiag = (prec == 2) ? reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(part) + g.part_bytes)
-                                : nullptr;
+    void* part = w + g.off_bytes + g.pk_bytes + g.bs_bytes + g.ss_bytes + g.cm_bytes + g.rc_bytes;
+    // FP64 diagonal sums: split plans' dense form only
+    double* pdiag = (prec == 2 && !g.sparse)
+                        ? reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(part) + g.part_bytes)
+                        : nullptr;
     const int64_t total = (int64_t)g.geom.ntiles * g.nsplit;
     const int64_t grid = ((total + 7) / 8) * 8;
     hipError_t e;
-    if (prec == 0) {
+    if (g.sparse) {
+        uint32_t* P = reinterpret_cast<uint32_t*>(w);
+        uint16_t* OA = reinterpret_cast<uint16_t*>(w + up256((size_t)n * (size_t)m * 4));
+        uint32_t* BS = reinterpret_cast<uint32_t*>(w + g.pk_bytes);
+        uint16_t* SS = reinterpret_cast<uint16_t*>(w + g.pk_bytes + g.bs_bytes);
+        uint32_t* CM = reinterpret_cast<uint32_t*>(w + g.pk_bytes + g.bs_bytes + g.ss_bytes);
+        uint32_t* RC = reinterpret_cast<uint32_t*>(w + g.pk_bytes + g.bs_bytes + g.ss_bytes + g.cm_bytes);
+        e = launch_pack(g, m, reinterpret_cast<const float*>(vals), idx, n, 1, 128, 0, P, OA, BS, SS, CM, s);
+        if (e != hipSuccess) return e;
+        {
+            static bool rc_attr = false;
+            if (!rc_attr) {
+                (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_range_counts),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 65536 * 2);
+                rc_attr = true;
+            }
+            const int64_t nranges = (g.nchunks + kSpRangeChunks - 1) / kSpRangeChunks;
+            ProfScope ps_("range_counts", s);
+            hipLaunchKernelGGL(k_range_counts, dim3((unsigned)nranges), dim3(1024), (size_t)((p + 1) / 2) * 4, s, idx,
+                               n, m, p, RC);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        static bool sp_attr = false;
+        if (!sp_attr) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_sparse),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(SparseLds));
+            sp_attr = true;
+        }
+        const int64_t items = (int64_t)g.geom.ntiles * g.nsplit;
+        {
+            ProfScope ps_("gram_sparse", s);
+            hipLaunchKernelGGL(k_gram_sparse, dim3((unsigned)(((items + 7) / 8) * 8)), dim3(kSpThreads), sizeof(SparseLds),
+                               s, P, OA, BS, SS, CM, RC, m, g.geom, g.nchunks, g.nsplit, g.split_len,
+                               reinterpret_cast<float*>(part));
+        }
+    } else if (prec == 0) {
         uint32_t* off = reinterpret_cast<uint32_t*>(w);
         {
             const int64_t threads = n * (int64_t)(g.geom.nbc + 1);
@@ -901,32 +1430,9 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
         uint16_t* OA = reinterpret_cast<uint16_t*>(w + up256((size_t)n * (size_t)m * 4));
         uint32_t* BS = reinterpret_cast<uint32_t*>(w + g.pk_bytes);
         const bool split = (prec == 2);
-        const bool stage = (size_t)kChunk * m * 2 <= (size_t)kPackStageBytes &&
-                           pack_lds_bytes(g.geom.nbc) + kPackStageBytes <= (size_t)kLdsMax &&
-                           (reinterpret_cast<uintptr_t>(idx) & 15) == 0;
-        // the staged rows take what they need (more workgroups per CU than a fixed 32 KB)
-        const size_t lds = pack_lds_bytes(g.geom.nbc) + (stage ? (((size_t)kChunk * m * 2 + 15) & ~(size_t)15) : 0);
-        static bool pack_attr = false;
-        if (!pack_attr) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<false>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)pack_lds_bytes(65536 / kTC));
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
-            pack_attr = true;
-        }
-        {
-            ProfScope ps_("gram_pack", s);
-            const int rowbytes = split ? kBfStride * 2 : kF32Stride * 4;
-            if (stage)
-                hipLaunchKernelGGL(k_gram_pack<true>, dim3((unsigned)g.nchunks), dim3(256), lds, s,
-                                   reinterpret_cast<const float*>(vals), idx, n, m, g.geom.tr, g.geom.tc, g.geom.nbc,
-                                   rowbytes, split ? 1 : 0, P, OA, BS);
-            else
-                hipLaunchKernelGGL(k_gram_pack<false>, dim3((unsigned)g.nchunks), dim3(256), lds, s,
-                                   reinterpret_cast<const float*>(vals), idx, n, m, g.geom.tr, g.geom.tc, g.geom.nbc,
-                                   rowbytes, split ? 1 : 0, P, OA, BS);
-        }
-        e = hipGetLastError();
+        const int rowbytes = split ? kBfStride * 2 : kF32Stride * 4;
+        e = launch_pack(g, m, reinterpret_cast<const float*>(vals), idx, n, rowbytes, split ? 2 : 4, split ? 1 : 0, P,
+                        OA, BS, nullptr, nullptr, s);
         if (e != hipSuccess) return e;
         if (split)
             dispatch_mfma<true>(g, grid, P, OA, BS, m, n, reinterpret_cast<float*>(part), pdiag, s);

@@ -44,10 +44,12 @@ hipError_t launch_compress_kron(uint64_t seed, int m, const float* X, int64_t n,
                                 float* vals, const DeviceInfo& dev, hipStream_t s);
 
 // ---- covariance -----------------------------------------------------------
-size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo& dev);
+// algo: 0 = the faster form by the cost model, 1 = dense tiles, 2 = sparse
+size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo& dev, int algo);
+bool covariance_is_sparse(int prec, int p, int m, int64_t n, const DeviceInfo& dev, int algo);
 hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n,
                                         double* acc, void* ws, size_t ws_bytes, const DeviceInfo& dev,
-                                        hipStream_t s);
+                                        hipStream_t s, int algo);
 hipError_t launch_covariance_finalize(int prec, int p, int m, int64_t n_total, const double* acc, double* C,
                                       hipStream_t s);
 

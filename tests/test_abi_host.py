@@ -187,3 +187,29 @@ def test_stream_estimates_validates_on_the_host():
         stream_estimates(plan, np.zeros((10, 256), dtype=np.float32), 0)  # empty chunks
     with pytest.raises(ValueError):
         stream_estimates(plan, torch.zeros(10, dtype=torch.float32), 4)  # not 2-D
+
+
+def test_gram_form_choice():
+    """The automatic choice: FP32 plans take the sparse form at the workloads'
+    small m/p (their dense tiles run on the slower FP32 matrix cores), split
+    plans keep the BF16 matrix-core tiles at these sizes, every plan keeps the
+    dense form when every coordinate is kept, FP64 plans stay dense."""
+    assert pds.Plan(4096, 410, prec=pds.PDS_SPLIT_BF16).gram_form(1 << 20) == pds.PDS_GRAM_DENSE
+    assert pds.Plan(4096, 410, prec=pds.PDS_F32).gram_form(1 << 20) == pds.PDS_GRAM_SPARSE
+    assert pds.Plan(1024, 51, prec=pds.PDS_F32).gram_form(1 << 20) == pds.PDS_GRAM_SPARSE
+    assert pds.Plan(1024, 1024, prec=pds.PDS_SPLIT_BF16).gram_form(1 << 20) == pds.PDS_GRAM_DENSE
+    assert pds.Plan(1024, 1024, prec=pds.PDS_F32).gram_form(1 << 20) == pds.PDS_GRAM_DENSE
+    assert pds.Plan(256, 26, prec=pds.PDS_F64).gram_form(2000) == pds.PDS_GRAM_DENSE
+    assert pds.Plan(256, 26, prec=pds.PDS_F32, gram=pds.PDS_GRAM_DENSE).gram_form(2000) == pds.PDS_GRAM_DENSE
+    b = ctypes.c_int32(0)
+    L = pds.lib()
+    plan = pds.Plan(256, 26, prec=pds.PDS_F64)
+    assert L.pds_plan_set_gram(plan.handle, pds.PDS_GRAM_SPARSE) == _lib.PDS_E_UNSUPPORTED
+    assert L.pds_plan_set_gram(plan.handle, 7) == _lib.PDS_E_ARG
+    assert L.pds_plan_set_gram(None, 1) == _lib.PDS_E_ARG
+    assert L.pds_plan_gram(plan.handle, -1, ctypes.byref(b)) == _lib.PDS_E_ARG
+    assert L.pds_plan_gram(plan.handle, 10, None) == _lib.PDS_E_ARG
+    # the two forms size their workspaces differently
+    sp = pds.Plan(4096, 410, prec=pds.PDS_F32, gram=pds.PDS_GRAM_SPARSE).workspace_size(1, 1 << 20)
+    de = pds.Plan(4096, 410, prec=pds.PDS_F32, gram=pds.PDS_GRAM_DENSE).workspace_size(1, 1 << 20)
+    assert sp > 0 and de > 0 and sp != de

@@ -95,23 +95,28 @@ def check_cov_rows(C, wl, tag):
     assert e <= 1e-5 and f <= 1e-5
 
 
-@pytest.mark.parametrize("prec", ["split", "f32"])
-def test_spiked4096_full_size(spiked, prec):
+GRAM = {"dense": pds.PDS_GRAM_DENSE, "sparse": pds.PDS_GRAM_SPARSE}
+PRECS = {"split": pds.PDS_SPLIT_BF16, "f32": pds.PDS_F32}
+
+
+@pytest.mark.parametrize("prec,gram", [("split", "dense"), ("f32", "dense"), ("f32", "sparse"), ("split", "sparse")])
+def test_spiked4096_full_size(spiked, prec, gram):
     p, m = spiked["p"], spiked["m"]
-    plan = pds.Plan(p, m, seed=0, prec={"split": pds.PDS_SPLIT_BF16, "f32": pds.PDS_F32}[prec])
+    plan = pds.Plan(p, m, seed=0, prec=PRECS[prec], gram=GRAM[gram])
     vals, idx = pds.compress(plan, spiked["X"])
     C = pds.covariance(plan, vals, idx)
     torch.cuda.synchronize()
-    check_cov_rows(C, spiked, f"spiked4096 {prec}")
+    check_cov_rows(C, spiked, f"spiked4096 {prec} {gram}")
     check_compressed_rows(vals, idx, spiked["v_o"], spiked["i_o"])
 
 
-def test_mixture_full_size_covariance(mixture):
-    plan = pds.Plan(mixture["p"], mixture["m"], seed=0, prec=pds.PDS_F32)
+@pytest.mark.parametrize("gram", ["dense", "sparse"])
+def test_mixture_full_size_covariance(mixture, gram):
+    plan = pds.Plan(mixture["p"], mixture["m"], seed=0, prec=pds.PDS_F32, gram=GRAM[gram])
     vals, idx = pds.compress(plan, mixture["X"])
     C = pds.covariance(plan, vals, idx)
     torch.cuda.synchronize()
-    check_cov_rows(C, mixture, "mixture f32")
+    check_cov_rows(C, mixture, f"mixture f32 {gram}")
     check_compressed_rows(vals, idx, mixture["v_o"], mixture["i_o"])
 
 

@@ -133,13 +133,18 @@ COV_SHAPES = [(2, 2, 50), (16, 4, 33), (64, 7, 1000), (128, 20, 31), (256, 26, 2
               (256, 26, 40000), (2048, 205, 30000), (1024, 1024, 2000)]
 
 
-@pytest.mark.parametrize("prec", list(PRECS))
+# (precision, Gram form): FP64 plans have the dense form only
+GRAM_FORMS = {"dense": pds.PDS_GRAM_DENSE, "sparse": pds.PDS_GRAM_SPARSE}
+PREC_GRAM = [("f64", "dense"), ("f32", "dense"), ("f32", "sparse"), ("split", "dense"), ("split", "sparse")]
+
+
+@pytest.mark.parametrize("prec,gram", PREC_GRAM)
 @pytest.mark.parametrize("p,m,n", COV_SHAPES)
-def test_covariance_matches_oracle(p, m, n, prec):
+def test_covariance_matches_oracle(p, m, n, prec, gram):
     pr, dt, _, tol = PRECS[prec]
-    log(f"covariance p={p} m={m} n={n} prec={prec}")
+    log(f"covariance p={p} m={m} n={n} prec={prec} gram={gram}")
     d = synth.random_compressed(n, p, m, seed=p + m, dtype=dt)
-    plan = pds.Plan(p, m, seed=0, prec=pr)
+    plan = pds.Plan(p, m, seed=0, prec=pr, gram=GRAM_FORMS[gram])
     C = pds.covariance(plan, to_dev(d["vals"]), to_dev(d["idx"].view(np.int16)))
     torch.cuda.synchronize()
     C_o = ref.covariance(p, d["vals"].astype(np.float64), d["idx"])
@@ -148,12 +153,45 @@ def test_covariance_matches_oracle(p, m, n, prec):
     assert nerr(Cg, C_o) <= tol and ferr(Cg, C_o) <= tol, (nerr(Cg, C_o), ferr(Cg, C_o))
 
 
-@pytest.mark.parametrize("prec", list(PRECS))
-def test_covariance_streaming_batches(prec):
+def test_sparse_gram_deterministic_and_scale_changes():
+    """The sparse form sums integers: two runs give the same bits.  Values
+    whose size changes by 2^20 between fixed-point ranges (2048 samples) and
+    super-ranges still meet the bar against the oracle."""
+    p, m, n = 1024, 51, 70001
+    d = synth.random_compressed(n, p, m, seed=77, dtype=np.float32)
+    v = d["vals"]
+    scale = np.ones(n, dtype=np.float32)
+    scale[5000:9000] = 1024.0
+    scale[20000:20100] = 1.0 / 1024.0
+    scale[60000] = 2.0 ** 20
+    v = (v * scale[:, None]).astype(np.float32)
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F32, gram=pds.PDS_GRAM_SPARSE)
+    vals, idx = to_dev(v), to_dev(d["idx"].view(np.int16))
+    C1 = pds.covariance(plan, vals, idx).cpu().numpy()
+    C2 = pds.covariance(plan, vals, idx).cpu().numpy()
+    assert np.array_equal(C1, C2)
+    C_o = ref.covariance(p, v.astype(np.float64), d["idx"])
+    log(f"sparse Gram with scale changes: nerr {nerr(C1, C_o):.3e} ferr {ferr(C1, C_o):.3e}")
+    assert nerr(C1, C_o) <= 1e-5 and ferr(C1, C_o) <= 1e-5
+
+
+def test_sparse_gram_non_finite_value_poisons_its_tiles():
+    p, m, n = 512, 40, 3000
+    d = synth.random_compressed(n, p, m, seed=5, dtype=np.float32)
+    v = d["vals"].copy()
+    v[1234, 7] = np.nan
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F32, gram=pds.PDS_GRAM_SPARSE)
+    C = pds.covariance(plan, to_dev(v), to_dev(d["idx"].view(np.int16))).cpu().numpy()
+    j = int(d["idx"][1234, 7])
+    assert np.isnan(C[j, j])
+
+
+@pytest.mark.parametrize("prec,gram", PREC_GRAM)
+def test_covariance_streaming_batches(prec, gram):
     pr, dt, _, tol = PRECS[prec]
     p, m, n = 512, 51, 5000
     d = synth.random_compressed(n, p, m, seed=11, dtype=dt)
-    plan = pds.Plan(p, m, prec=pr)
+    plan = pds.Plan(p, m, prec=pr, gram=GRAM_FORMS[gram])
     acc = pds.CovarianceAccumulator(plan)
     vals, idx = to_dev(d["vals"]), to_dev(d["idx"].view(np.int16))
     for a, b in [(0, 1700), (1700, 1701), (1701, 5000)]:
