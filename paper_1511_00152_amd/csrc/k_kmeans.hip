@@ -24,7 +24,13 @@
 // wave per sample, and their entries go to FP64 side sums.
 //
 // When K x p is too large for LDS the centers are read from a transposed copy
-// in the workspace and the sums go to FP64 global atomics instead.
+// in the workspace and the sums go to global integer atomics instead.
+//
+// Every sum is fixed point (km_fx_*): each value is rounded once to a multiple
+// of 2^-F and added as an integer, so a sum is exact and the same in any order
+// of addition, and every result is deterministic.  FP32 values take one 64-bit
+// word per sum; FP64 values two (high and low 32-bit parts of v 2^F), which
+// keeps their rounding far below FP64's own.
 #include "pds_device.hpp"
 #include "pds_internal.hpp"
 
@@ -35,14 +41,58 @@ constexpr int kKmLdsThreads = 1024;    // LDS path: many waves share one LDS cop
 constexpr int kKmGroup = 16;  // clusters per register group
 constexpr size_t kKmLdsMax = 150 * 1024;
 
+// Fixed-point sums (see the file comment).  ev: |value| < 2^ev over the
+// values of the sum; lc: at most 2^lc values go into one sum.  One word:
+// F = 62 - ev - lc, |sum| 2^F < 2^62.  Two words: F = 94 - ev - lc,
+// v 2^F = hi 2^32 + lo with 0 <= lo <= 2^32, |sum of hi| < 2^62 and the sum
+// of lo below 2^(32 + lc).
 template <typename T>
-struct SumType {
-    using type = float;
-};
-template <>
-struct SumType<double> {
-    using type = double;
-};
+constexpr int km_words() { return sizeof(T) == 8 ? 2 : 1; }
+
+__device__ inline int km_ev(uint64_t vmax_bits)  // vmax as FP64 bits
+{
+    int ev = 0;
+    (void)frexp(__longlong_as_double((long long)vmax_bits), &ev);
+    return ev;
+}
+
+__host__ __device__ inline int km_lc(int64_t count)
+{
+    int l = 0;
+    while (l < 62 && ((int64_t)1 << l) < count) ++l;
+    return l;
+}
+
+template <typename T>
+__device__ inline int km_F(int ev, int lc)
+{
+    return (sizeof(T) == 8 ? 94 : 62) - ev - lc;
+}
+
+__device__ inline void km_fx_add(unsigned long long* s, float v, int F)
+{
+    atomicAdd(s, (unsigned long long)__double2ll_rn(ldexp((double)v, F)));
+}
+
+__device__ inline void km_fx_add(unsigned long long* s, double v, int F)
+{
+    const double x = ldexp(v, F);
+    const double h = floor(ldexp(x, -32));
+    const double r = x - ldexp(h, 32);  // exact: the low part of x, in [0, 2^32)
+    atomicAdd(&s[0], (unsigned long long)(long long)h);
+    atomicAdd(&s[1], (unsigned long long)__double2ll_rn(r));
+}
+
+template <int WORDS>
+__device__ inline double km_fx_value(const unsigned long long* s, int F)
+{
+    if constexpr (WORDS == 1)
+        return ldexp((double)(long long)s[0], -F);
+    else
+        return ldexp((double)(long long)s[0], 32 - F) + ldexp((double)(long long)s[1], -F);
+}
+
+__device__ inline uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
 
 template <int NT>
 __device__ inline double block_sum_f64(double v, double* red)
@@ -83,7 +133,10 @@ __device__ inline double dist_f64(const T* __restrict__ v, const uint16_t* __res
     return d;
 }
 
-// GLOBAL = centers from workspace copy, sums via FP64 global atomics.
+// GLOBAL = centers from workspace copy, sums via global integer atomics (scale
+// from gmax, the largest |value| of the whole call, taken by k_kmeans_vmax).
+// Otherwise the sums and counts sit in LDS with this workgroup's own scale
+// (its samples' largest |value|, kept in wvmax for the update).
 // FP32 plans: a sample whose two best distances are closer than the rounding
 // bound is appended to rlist and left to k_kmeans_recheck (its assignment,
 // distance and entries are written there), so no wave here runs the serial
@@ -94,34 +147,58 @@ __global__ __launch_bounds__(NT) void k_kmeans_assign(const T* __restrict__ vals
                                                               int p, int K, const double* __restrict__ cin,
                                                               const T* __restrict__ cT_global, int64_t per_wg,
                                                               int32_t* __restrict__ assign,
-                                                              typename SumType<T>::type* __restrict__ psum,
-                                                              uint32_t* __restrict__ pcnt, double* __restrict__ gsum,
+                                                              unsigned long long* __restrict__ psum,
+                                                              uint32_t* __restrict__ pcnt,
+                                                              unsigned long long* __restrict__ gsum,
                                                               uint32_t* __restrict__ gcnt, double* __restrict__ dist,
                                                               int64_t* __restrict__ rlist,
-                                                              uint32_t* __restrict__ rcount)
+                                                              uint32_t* __restrict__ rcount,
+                                                              uint64_t* __restrict__ wvmax,
+                                                              unsigned long long* __restrict__ gmax)
 {
-    using S = typename SumType<T>::type;
+    constexpr int WS = km_words<T>();
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float red_f[NT / 64];
+    __shared__ double red_d[NT / 64];
     const int tid = threadIdx.x;
     const int64_t KP = (int64_t)K * p;
+    const int64_t i0 = (int64_t)blockIdx.x * per_wg;
+    int64_t i1 = i0 + per_wg;
+    if (i1 > n) i1 = n;
 
     T* cT = nullptr;
-    S* sums = nullptr;
+    unsigned long long* sums = nullptr;
     uint32_t* cnts = nullptr;
+    int F = 0;
     if constexpr (!GLOBAL) {
         cT = reinterpret_cast<T*>(smem);
-        sums = reinterpret_cast<S*>(smem + ((KP * sizeof(T) + 15) & ~(int64_t)15));
-        cnts = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(sums) + ((KP * sizeof(S) + 15) & ~(int64_t)15));
+        sums = reinterpret_cast<unsigned long long*>(smem + ((KP * sizeof(T) + 15) & ~(int64_t)15));
+        cnts = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(sums) + KP * 8 * WS);
         for (int64_t e = tid; e < KP; e += NT) {
             const int64_t k = e / p, l = e - k * p;
             cT[l * K + k] = (T)cin[e];
-            sums[e] = (S)0;
             cnts[e] = 0u;
         }
+        for (int64_t e = tid; e < KP * WS; e += NT) sums[e] = 0ull;
+        // this workgroup's scale: the largest |value| of its own samples
+        double vm = 0.0;
+        const T* vb = vals + i0 * (int64_t)m;
+        const int64_t cnt = (i1 > i0 ? i1 - i0 : 0) * (int64_t)m;
+        for (int64_t e = tid; e < cnt; e += NT) vm = fmax(vm, fabs((double)vb[e]));
+        for (int off = 32; off > 0; off >>= 1) vm = fmax(vm, __shfl_down(vm, off, 64));
+        if ((tid & 63) == 0) red_d[tid >> 6] = vm;
+        __syncthreads();
+        vm = red_d[0];
+        for (int w = 1; w < NT / 64; ++w) vm = fmax(vm, red_d[w]);
+        if (tid == 0) {
+            wvmax[blockIdx.x] = dbits(vm);
+            atomicMax(gmax, (unsigned long long)dbits(vm));
+        }
+        F = km_F<T>(km_ev(dbits(vm)), km_lc(per_wg));
         __syncthreads();
     } else {
         cT = const_cast<T*>(cT_global);
+        F = km_F<T>(km_ev((uint64_t)*gmax), km_lc(n));
     }
 
     // largest |center entry| (FP32 rounding bound only)
@@ -130,10 +207,6 @@ __global__ __launch_bounds__(NT) void k_kmeans_assign(const T* __restrict__ vals
         for (int64_t e = tid; e < KP; e += NT) cmax = fmaxf(cmax, fabsf((float)cT[e]));
         cmax = block_max_f32<NT>(cmax, red_f);
     }
-
-    const int64_t i0 = (int64_t)blockIdx.x * per_wg;
-    int64_t i1 = i0 + per_wg;
-    if (i1 > n) i1 = n;
 
     for (int64_t i = i0 + tid; i < i1; i += NT) {
         const T* v = vals + i * (int64_t)m;
@@ -187,31 +260,38 @@ __global__ __launch_bounds__(NT) void k_kmeans_assign(const T* __restrict__ vals
         }
         assign[i] = bestk;
         dist[i] = (double)best;
-        if constexpr (!GLOBAL) {
-            S* sk = sums + (int64_t)bestk * p;
-            uint32_t* ck = cnts + (int64_t)bestk * p;
-            for (int a = 0; a < m; ++a) {
-                atomicAdd(&sk[ix[a]], (S)v[a]);
-                atomicAdd(&ck[ix[a]], 1u);
-            }
-        } else {
-            double* sk = gsum + (int64_t)bestk * p;
-            uint32_t* ck = gcnt + (int64_t)bestk * p;
-            for (int a = 0; a < m; ++a) {
-                atomicAdd(&sk[ix[a]], (double)v[a]);
-                atomicAdd(&ck[ix[a]], 1u);
-            }
+        unsigned long long* sk = (GLOBAL ? gsum : sums) + (int64_t)bestk * p * WS;
+        uint32_t* ck = (GLOBAL ? gcnt : cnts) + (int64_t)bestk * p;
+        for (int a = 0; a < m; ++a) {
+            km_fx_add(sk + (int64_t)ix[a] * WS, v[a], F);
+            atomicAdd(&ck[ix[a]], 1u);
         }
     }
 
     if constexpr (!GLOBAL) {
         __syncthreads();
-        S* ps = psum + (int64_t)blockIdx.x * KP;
+        unsigned long long* ps = psum + (int64_t)blockIdx.x * KP * WS;
         uint32_t* pc = pcnt + (int64_t)blockIdx.x * KP;
-        for (int64_t e = tid; e < KP; e += NT) {
-            ps[e] = sums[e];
-            pc[e] = cnts[e];
-        }
+        for (int64_t e = tid; e < KP * WS; e += NT) ps[e] = sums[e];
+        for (int64_t e = tid; e < KP; e += NT) pc[e] = cnts[e];
+    }
+}
+
+// gmax = the largest |value| of the call (GLOBAL path, before the assignment).
+template <typename T>
+__global__ __launch_bounds__(256) void k_kmeans_vmax(const T* __restrict__ vals, int64_t tot,
+                                                     unsigned long long* __restrict__ gmax)
+{
+    __shared__ double red[4];
+    double vm = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+        vm = fmax(vm, fabs((double)vals[e]));
+    for (int off = 32; off > 0; off >>= 1) vm = fmax(vm, __shfl_down(vm, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = vm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) vm = fmax(vm, red[w]);
+        atomicMax(gmax, (unsigned long long)dbits(vm));
     }
 }
 
@@ -238,18 +318,6 @@ __device__ inline float dpp_row_total(float v)
     return v;  // the row total in lane 15 of the row
 }
 
-// Fixed-point scale of a workgroup's sums: at most per_wg values of magnitude
-// below 2^ev (frexp of the largest |value|) go into one sum, so with F = 62 -
-// ev - ceil(log2 per_wg) every sum times 2^F stays below 2^62; each value is
-// rounded once, to 2^-F absolute, and the sums are exact integers, the same in
-// any order of addition.
-__device__ inline int km_fx_exp(uint32_t vmax_bits, int64_t per_wg)
-{
-    int ev = 0;
-    (void)frexpf(__uint_as_float(vmax_bits), &ev);
-    const int cb = per_wg > 1 ? 64 - __clzll((unsigned long long)(per_wg - 1)) : 0;
-    return 62 - ev - cb;
-}
 
 // One sample of the cooperative assignment (its group of W lanes): distances
 // from the entries the lanes hold (x, l: four per lane, entries u W + sl, -1
@@ -366,8 +434,8 @@ template <int NQ4>
 __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     const float* __restrict__ vals, const uint16_t* __restrict__ idx, int64_t n, int m, int p, int K,
     const double* __restrict__ cin, int64_t per_wg, int32_t* __restrict__ assign, int64_t* __restrict__ psum,
-    uint32_t* __restrict__ pcnt, uint32_t* __restrict__ wvmax, double* __restrict__ dist,
-    int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
+    uint32_t* __restrict__ pcnt, uint64_t* __restrict__ wvmax, unsigned long long* __restrict__ gmax,
+    double* __restrict__ dist, int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
 {
     constexpr int W = 16;
     constexpr int G = kKmLdsThreads / W;  // groups per workgroup
@@ -405,8 +473,11 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     for (int64_t e = tid; e < (int64_t)KP4 * p; e += kKmLdsThreads) cmax = fmaxf(cmax, fabsf(cT[e]));
     cmax = block_max_f32<kKmLdsThreads>(cmax, red_f);
     vm = block_max_f32<kKmLdsThreads>(vm, red_f);
-    if (tid == 0) wvmax[blockIdx.x] = __float_as_uint(vm);
-    const int fx = km_fx_exp(__float_as_uint(vm), per_wg);
+    if (tid == 0) {
+        wvmax[blockIdx.x] = dbits((double)vm);
+        atomicMax(gmax, (unsigned long long)dbits((double)vm));
+    }
+    const int fx = km_F<float>(km_ev(dbits((double)vm)), km_lc(per_wg));
 
     const int g = tid / W, sl = tid % W;
     // the first 4 W entries of the samples two and one steps ahead are in
@@ -450,16 +521,20 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
 
 // FP64 decision for the flagged samples: one wave per sample, lanes over
 // clusters, each distance summed in the oracle's order; ties to the lowest k.
-// The sample's entries go to the FP64 side sums (gsum_r, gcnt_r).
+// The sample's entries go to the side sums (gsum_r, gcnt_r), fixed point with
+// the call's largest |value| (gmax) and at most n values per sum.
 __global__ __launch_bounds__(256) void k_kmeans_recheck(const float* __restrict__ vals,
-                                                        const uint16_t* __restrict__ idx, int m, int p, int K,
-                                                        const double* __restrict__ cin,
+                                                        const uint16_t* __restrict__ idx, int64_t n, int m, int p,
+                                                        int K, const double* __restrict__ cin,
                                                         const int64_t* __restrict__ rlist,
                                                         const uint32_t* __restrict__ rcount,
                                                         int32_t* __restrict__ assign, double* __restrict__ dist,
-                                                        double* __restrict__ gsum_r, uint32_t* __restrict__ gcnt_r)
+                                                        unsigned long long* __restrict__ gsum_r,
+                                                        uint32_t* __restrict__ gcnt_r,
+                                                        const unsigned long long* __restrict__ gmax)
 {
     const int lane = threadIdx.x & 63;
+    const int F = km_F<float>(km_ev((uint64_t)*gmax), km_lc(n));
     const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t cnt = *rcount;
     for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < cnt; e += nw) {
@@ -488,10 +563,10 @@ __global__ __launch_bounds__(256) void k_kmeans_recheck(const float* __restrict_
             assign[i] = bk;
             dist[i] = bd;
         }
-        double* sk = gsum_r + (int64_t)bk * p;
+        unsigned long long* sk = gsum_r + (int64_t)bk * p;
         uint32_t* ck = gcnt_r + (int64_t)bk * p;
         for (int a = lane; a < m; a += 64) {
-            atomicAdd(&sk[ix[a]], (double)v[a]);
+            km_fx_add(&sk[ix[a]], v[a], F);
             atomicAdd(&ck[ix[a]], 1u);
         }
     }
@@ -514,23 +589,30 @@ __global__ __launch_bounds__(kKmThreads) void k_kmeans_objective(const double* _
 // Update: a workgroup per 64 center entries; its 16 waves each add every
 // 16th partial for the 64 entries (coalesced), then the 16 wave sums are
 // combined in a fixed order; the first workgroup also sums the objective.
+// Partial w is fixed point with its workgroup's scale (PER_WG: wvmax[w] and at
+// most 2^lc_part values per sum) or with the call's (gmax, 2^lc_part); the
+// side sums with the call's scale and 2^lc_side.
 constexpr int kUpdThreads = 1024;
 
-template <typename S>
-__global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const S* __restrict__ psum,
+template <typename T, bool PER_WG>
+__global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const unsigned long long* __restrict__ psum,
                                                                const uint32_t* __restrict__ pcnt, int nparts,
-                                                               int64_t KP, const double* __restrict__ gsum_r,
+                                                               int64_t KP, const uint64_t* __restrict__ wvmax,
+                                                               int lc_part,
+                                                               const unsigned long long* __restrict__ gsum_r,
                                                                const uint32_t* __restrict__ gcnt_r,
-                                                               const double* __restrict__ cin,
+                                                               const unsigned long long* __restrict__ gmax,
+                                                               int lc_side, const double* __restrict__ cin,
                                                                double* __restrict__ cout,
                                                                const double* __restrict__ pobj, int nobj,
-                                                               double* __restrict__ objective,
-                                                               const uint32_t* __restrict__ vmax, int64_t per_wg)
+                                                               double* __restrict__ objective)
 {
+    constexpr int WS = km_words<T>();
     __shared__ double rs[kUpdThreads / 64][64];
     __shared__ uint64_t rc[kUpdThreads / 64][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+    const int ev_g = km_ev((uint64_t)*gmax);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         double o = 0.0;
         for (int w = 0; w < nobj; ++w) o += pobj[w];
@@ -540,9 +622,8 @@ __global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const S* __restri
     uint64_t cnt = 0;
     if (g < KP) {
         for (int w = wv; w < nparts; w += kUpdThreads / 64) {
-            const double pv = (double)psum[(int64_t)w * KP + g];
-            // fixed-point partials carry their workgroup's scale
-            sum += vmax ? ldexp(pv, -km_fx_exp(vmax[w], per_wg)) : pv;
+            const int F = km_F<T>(PER_WG ? km_ev(wvmax[w]) : ev_g, lc_part);
+            sum += km_fx_value<WS>(psum + ((int64_t)w * KP + g) * WS, F);
             cnt += pcnt[(int64_t)w * KP + g];
         }
     }
@@ -556,30 +637,36 @@ __global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const S* __restri
             t += rs[w][lane];
             c += rc[w][lane];
         }
-        t += gsum_r[g];
+        t += km_fx_value<1>(gsum_r + g, km_F<float>(ev_g, lc_side));
         c += gcnt_r[g];
         cout[g] = (c > 0) ? t / (double)c : cin[g];
     }
 }
 
-// per call: side sums and counter cleared; for the GLOBAL path also the
+// per call: side sums, counter and gmax cleared; for the GLOBAL path also the
 // transposed centers and the global sums
 template <typename T>
 __global__ __launch_bounds__(256) void k_kmeans_prep(const double* __restrict__ cin, int K, int p, int global,
-                                                     T* __restrict__ cT, double* __restrict__ gsum,
-                                                     uint32_t* __restrict__ gcnt, double* __restrict__ gsum_r,
-                                                     uint32_t* __restrict__ gcnt_r, uint32_t* __restrict__ rcount)
+                                                     T* __restrict__ cT, unsigned long long* __restrict__ gsum,
+                                                     uint32_t* __restrict__ gcnt,
+                                                     unsigned long long* __restrict__ gsum_r,
+                                                     uint32_t* __restrict__ gcnt_r, uint32_t* __restrict__ rcount,
+                                                     unsigned long long* __restrict__ gmax)
 {
+    constexpr int WS = km_words<T>();
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t KP = (int64_t)K * p;
-    if (g == 0) *rcount = 0u;
+    if (g == 0) {
+        *rcount = 0u;
+        *gmax = 0ull;
+    }
     if (g >= KP) return;
-    gsum_r[g] = 0.0;
+    gsum_r[g] = 0ull;
     gcnt_r[g] = 0u;
     if (global) {
         const int64_t k = g / p, l = g - k * p;
         cT[l * K + k] = (T)cin[g];
-        gsum[g] = 0.0;
+        for (int w = 0; w < WS; ++w) gsum[g * WS + w] = 0ull;
         gcnt[g] = 0u;
     }
 }
@@ -594,7 +681,7 @@ struct KmPlan {
     int64_t per_wg;
     size_t lds;
     size_t psum_bytes, pcnt_bytes, pobj_bytes, ct_bytes, gsum_bytes, gcnt_bytes;
-    size_t dist_bytes, rlist_bytes, rcount_bytes, gsumr_bytes, gcntr_bytes, vmax_bytes;
+    size_t dist_bytes, rlist_bytes, rcount_bytes, gsumr_bytes, gcntr_bytes, vmax_bytes, gmax_bytes;
 };
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -603,9 +690,9 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
 {
     KmPlan k;
     const size_t te = (prec == 0) ? 8 : 4;  // center / value element
-    const size_t se = (prec == 0) ? 8 : 4;  // partial-sum element
+    const size_t ws = (prec == 0) ? 2 : 1;  // 64-bit words per fixed-point sum
     const int64_t KP = (int64_t)K * p;
-    const size_t lds = ((KP * te + 15) & ~(size_t)15) + ((KP * se + 15) & ~(size_t)15) + KP * 4;
+    const size_t lds = ((KP * te + 15) & ~(size_t)15) + (size_t)KP * 8 * ws + KP * 4;
     k.global = lds > kKmLdsMax;
     k.lds = k.global ? 0 : lds;
     // FP32, K <= 32: centers (rows padded to 4), 64-bit fixed-point sums and
@@ -626,11 +713,11 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
     if (k.coop && (n + want - 1) / want > 65535) want = (n + 65534) / 65535;  // 16-bit counts
     k.nwg = (int)want;
     k.per_wg = (n + k.nwg - 1) / k.nwg;
-    k.psum_bytes = k.global ? 0 : al256((size_t)k.nwg * KP * (k.coop ? 8 : se));
+    k.psum_bytes = k.global ? 0 : al256((size_t)k.nwg * KP * 8 * (k.coop ? 1 : ws));
     k.pcnt_bytes = k.global ? 0 : al256((size_t)k.nwg * KP * 4);
     k.pobj_bytes = al256((size_t)k.nwg * 8);
     k.ct_bytes = k.global ? al256(KP * te) : 0;
-    k.gsum_bytes = k.global ? al256(KP * 8) : 0;
+    k.gsum_bytes = k.global ? al256(KP * 8 * ws) : 0;
     k.gcnt_bytes = k.global ? al256(KP * 4) : 0;
     const size_t nn = (size_t)(n > 0 ? n : 1);
     k.dist_bytes = al256(nn * 8);
@@ -638,7 +725,8 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
     k.rcount_bytes = 256;
     k.gsumr_bytes = al256(KP * 8);
     k.gcntr_bytes = al256(KP * 4);
-    k.vmax_bytes = al256((size_t)k.nwg * 4);  // per-workgroup largest |value| (fixed-point scale)
+    k.vmax_bytes = al256((size_t)k.nwg * 8);  // per-workgroup largest |value| (FP64 bits)
+    k.gmax_bytes = 256;                       // the call's largest |value| (FP64 bits)
     return k;
 }
 
@@ -647,17 +735,16 @@ size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceIn
     (void)m;
     KmPlan k = km_plan(prec, p, n, K, dev);
     return k.psum_bytes + k.pcnt_bytes + k.pobj_bytes + k.ct_bytes + k.gsum_bytes + k.gcnt_bytes + k.dist_bytes +
-           k.rlist_bytes + k.rcount_bytes + k.gsumr_bytes + k.gcntr_bytes + k.vmax_bytes;
+           k.rlist_bytes + k.rcount_bytes + k.gsumr_bytes + k.gcntr_bytes + k.vmax_bytes + k.gmax_bytes;
 }
 
 template <typename T>
 static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const uint16_t* idx, int64_t n, int K,
                             const double* cin, double* cout, int32_t* assign, double* objective, void* ws,
-                            const DeviceInfo& dev, hipStream_t s)
+                            size_t ws_bytes, const DeviceInfo& dev, hipStream_t s)
 {
-    using S = typename SumType<T>::type;
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
-    S* psum = reinterpret_cast<S*>(w);
+    unsigned long long* psum = reinterpret_cast<unsigned long long*>(w);
     w += k.psum_bytes;
     uint32_t* pcnt = reinterpret_cast<uint32_t*>(w);
     w += k.pcnt_bytes;
@@ -665,7 +752,7 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
     w += k.pobj_bytes;
     T* cT = reinterpret_cast<T*>(w);
     w += k.ct_bytes;
-    double* gsum = reinterpret_cast<double*>(w);
+    unsigned long long* gsum = reinterpret_cast<unsigned long long*>(w);
     w += k.gsum_bytes;
     uint32_t* gcnt = reinterpret_cast<uint32_t*>(w);
     w += k.gcnt_bytes;
@@ -675,24 +762,39 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
     w += k.rlist_bytes;
     uint32_t* rcount = reinterpret_cast<uint32_t*>(w);
     w += k.rcount_bytes;
-    double* gsum_r = reinterpret_cast<double*>(w);
+    unsigned long long* gsum_r = reinterpret_cast<unsigned long long*>(w);
     w += k.gsumr_bytes;
     uint32_t* gcnt_r = reinterpret_cast<uint32_t*>(w);
     w += k.gcntr_bytes;
-    uint32_t* vmax = reinterpret_cast<uint32_t*>(w);  // per-workgroup largest |value| (cooperative path)
+    uint64_t* wvmax = reinterpret_cast<uint64_t*>(w);
+    w += k.vmax_bytes;
+    unsigned long long* gmax = reinterpret_cast<unsigned long long*>(w);
+    w += k.gmax_bytes;
+    // every carved buffer ends inside the caller's workspace (checked on the
+    // host, before any launch)
+    if ((size_t)(w - reinterpret_cast<unsigned char*>(ws)) > ws_bytes) return hipErrorInvalidValue;
     const int64_t KP = (int64_t)K * p;
     {
         ProfScope ps_("kmeans_prep", s);
         hipLaunchKernelGGL(k_kmeans_prep<T>, dim3((unsigned)((KP + 255) / 256)), dim3(256), 0, s, cin, K, p,
-                           k.global ? 1 : 0, cT, gsum, gcnt, gsum_r, gcnt_r, rcount);
+                           k.global ? 1 : 0, cT, gsum, gcnt, gsum_r, gcnt_r, rcount, gmax);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (k.global) {
+        {
+            ProfScope ps_("kmeans_vmax", s);
+            const int64_t tot = n * (int64_t)m;
+            int64_t blocks = (tot + 255) / 256;
+            if (blocks > (int64_t)dev.cus * 8) blocks = (int64_t)dev.cus * 8;
+            hipLaunchKernelGGL(k_kmeans_vmax<T>, dim3((unsigned)blocks), dim3(256), 0, s, vals, tot, gmax);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
         ProfScope ps_("kmeans_assign", s);
         hipLaunchKernelGGL((k_kmeans_assign<T, true, kKmThreads>), dim3(k.nwg), dim3(kKmThreads), 0, s, vals, idx, n,
-                           m, p, K,
-                           cin, cT, k.per_wg, assign, psum, pcnt, gsum, gcnt, dist, rlist, rcount);
+                           m, p, K, cin, cT, k.per_wg, assign, psum, pcnt, gsum, gcnt, dist, rlist, rcount, wvmax,
+                           gmax);
     } else {
         if constexpr (sizeof(T) == 4) {
             if (k.coop) {
@@ -716,8 +818,8 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
 #define PDS_KM_COOP(Q)                                                                                        \
     case Q:                                                                                                   \
         hipLaunchKernelGGL(k_kmeans_assign_coop<Q>, dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s, vals, idx, n, m, \
-                           p, K, cin, k.per_wg, assign, reinterpret_cast<int64_t*>(psum), pcnt, vmax, dist,     \
-                           rlist, rcount);                                                                    \
+                           p, K, cin, k.per_wg, assign, reinterpret_cast<int64_t*>(psum), pcnt, wvmax, gmax,    \
+                           dist, rlist, rcount);                                                              \
         break;
                     switch ((K + 3) / 4) {
                         PDS_KM_COOP(1)
@@ -742,17 +844,16 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
         }
         ProfScope ps_("kmeans_assign", s);
         hipLaunchKernelGGL((k_kmeans_assign<T, false, kKmLdsThreads>), dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s,
-                           vals, idx, n, m, p,
-                           K, cin, (const T*)nullptr, k.per_wg, assign, psum, pcnt, (double*)nullptr,
-                           (uint32_t*)nullptr, dist, rlist, rcount);
+                           vals, idx, n, m, p, K, cin, (const T*)nullptr, k.per_wg, assign, psum, pcnt,
+                           (unsigned long long*)nullptr, (uint32_t*)nullptr, dist, rlist, rcount, wvmax, gmax);
     }
 assigned:
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if constexpr (sizeof(T) == 4) {
         ProfScope ps_("kmeans_recheck", s);
-        hipLaunchKernelGGL(k_kmeans_recheck, dim3((unsigned)dev.cus * 4), dim3(256), 0, s, vals, idx, m, p, K, cin,
-                           rlist, rcount, assign, dist, gsum_r, gcnt_r);
+        hipLaunchKernelGGL(k_kmeans_recheck, dim3((unsigned)dev.cus * 4), dim3(256), 0, s, vals, idx, n, m, p, K,
+                           cin, rlist, rcount, assign, dist, gsum_r, gcnt_r, gmax);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -765,18 +866,17 @@ assigned:
     {
         ProfScope ps_("kmeans_update", s);
         const unsigned ublocks = (unsigned)((KP + 63) / 64);
+        const int lc_n = km_lc(n), lc_wg = km_lc(k.per_wg);
         if (k.global)
-            hipLaunchKernelGGL(k_kmeans_update<double>, dim3(ublocks), dim3(kUpdThreads), 0, s, gsum, gcnt, 1, KP,
-                               gsum_r, gcnt_r, cin, cout, pobj, k.nwg, objective, (const uint32_t*)nullptr,
-                               (int64_t)0);
+            hipLaunchKernelGGL((k_kmeans_update<T, false>), dim3(ublocks), dim3(kUpdThreads), 0, s, gsum, gcnt, 1, KP,
+                               wvmax, lc_n, gsum_r, gcnt_r, gmax, lc_n, cin, cout, pobj, k.nwg, objective);
         else if (sizeof(T) == 4 && k.coop)
-            hipLaunchKernelGGL(k_kmeans_update<int64_t>, dim3(ublocks), dim3(kUpdThreads), 0, s,
-                               reinterpret_cast<const int64_t*>(psum), pcnt, k.nwg, KP, gsum_r, gcnt_r, cin, cout, pobj,
-                               k.nwg, objective, (const uint32_t*)vmax, k.per_wg);
+            hipLaunchKernelGGL((k_kmeans_update<float, true>), dim3(ublocks), dim3(kUpdThreads), 0, s, psum, pcnt,
+                               k.nwg, KP, wvmax, lc_wg, gsum_r, gcnt_r, gmax, lc_n, cin, cout, pobj, k.nwg,
+                               objective);
         else
-            hipLaunchKernelGGL(k_kmeans_update<S>, dim3(ublocks), dim3(kUpdThreads), 0, s, psum, pcnt, k.nwg, KP,
-                               gsum_r, gcnt_r, cin, cout, pobj, k.nwg, objective, (const uint32_t*)nullptr,
-                               (int64_t)0);
+            hipLaunchKernelGGL((k_kmeans_update<T, true>), dim3(ublocks), dim3(kUpdThreads), 0, s, psum, pcnt, k.nwg,
+                               KP, wvmax, lc_wg, gsum_r, gcnt_r, gmax, lc_n, cin, cout, pobj, k.nwg, objective);
     }
     return hipGetLastError();
 }
@@ -785,13 +885,12 @@ hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const ui
                               const double* cin, double* cout, int32_t* assign, double* objective, void* ws,
                               size_t ws_bytes, const DeviceInfo& dev, hipStream_t s)
 {
-    (void)ws_bytes;
     KmPlan k = km_plan(prec, p, n, K, dev);
     if (prec == 0)
         return km_launch<double>(k, p, m, reinterpret_cast<const double*>(vals), idx, n, K, cin, cout, assign,
-                                 objective, ws, dev, s);
+                                 objective, ws, ws_bytes, dev, s);
     return km_launch<float>(k, p, m, reinterpret_cast<const float*>(vals), idx, n, K, cin, cout, assign, objective,
-                            ws, dev, s);
+                            ws, ws_bytes, dev, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -229,6 +229,31 @@ def test_compress_then_covariance_end_to_end(prec):
 
 
 # ------------------------------------------------------------------- K-means --
+# every assignment path: FP32 cooperative (K <= 32), FP32 with LDS sums (K > 32),
+# FP32 with global sums (K p beyond LDS), FP64 with LDS sums, FP64 global
+KM_PATHS = [("f32", 1024, 51, 10, 20000), ("f32", 128, 13, 40, 9000), ("f32", 2048, 205, 50, 3000),
+            ("f64", 256, 26, 5, 7000), ("f64", 1024, 51, 100, 3000)]
+
+
+@pytest.mark.parametrize("prec,p,m,K,n", KM_PATHS)
+def test_kmeans_step_deterministic(prec, p, m, K, n):
+    """Every K-means sum is fixed point (exact integers): two calls give the
+    same bits, on every assignment path."""
+    pr, dt, _, _ = PRECS[prec]
+    d = synth.random_compressed(n, p, m, seed=K + p, dtype=dt, K=K)
+    plan = pds.Plan(p, m, seed=0, prec=pr)
+    vals, idx = to_dev(d["vals"]), to_dev(d["idx"].view(np.int16))
+    C0 = to_dev(d["centers"])
+    r1 = [t.cpu().numpy().copy() for t in pds.kmeans_step(plan, vals, idx, C0)]
+    r2 = [t.cpu().numpy().copy() for t in pds.kmeans_step(plan, vals, idx, C0)]
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b)
+    mu_o, a_o, J_o, _ = ref.kmeans_step(p, d["vals"].astype(np.float64), d["idx"], d["centers"])
+    assert np.array_equal(r1[1], a_o)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert nerr(r1[0], mu_o) <= tol and abs(float(r1[2][0]) - J_o) <= tol * J_o
+
+
 KM_SHAPES = [(256, 26, 2000, 5), (1024, 51, 9000, 10), (64, 64, 500, 3), (128, 1, 300, 4), (512, 40, 1000, 1),
              (256, 30, 3000, 37), (4096, 100, 700, 100),
              # FP32 cooperative assignment, one instance per four-cluster group count

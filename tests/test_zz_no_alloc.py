@@ -1,9 +1,9 @@
 """pds_kmeans_step_noalloc (the K-means iteration for callers that cannot
 allocate) against pds_kmeans_step with a caller workspace, through the C ABI:
 two calls in a row on the library's scratch array, the second with a smaller
-input, each compared with the workspace call on the same inputs (assignments
-bit-exact; centers and objective equal where the sums are fixed-point, within
-rounding where they use floating-point atomics), for FP32 and FP64 plans; and the
+input, each compared with the workspace call on the same inputs (assignments,
+centers and objective bit for bit: every sum is fixed point), for FP32 and
+FP64 plans; and the
 size limit is reported as a workspace error before any launch."""
 import ctypes
 
@@ -69,14 +69,9 @@ def test_noalloc_matches_workspace_call(prec, p, m, K, n1, n2):
         (cw, aw, jw), (cs, as_, js) = _both(plan, vals, idx, centers)
         assert np.array_equal(aw, as_), "assignments differ between the two entry points"
         assert aw.min() >= 0 and aw.max() < K
-        if prec == pds.PDS_F32 and K <= 32:
-            # fixed-point sums: the same bits in any order
-            assert np.array_equal(cw, cs), "centers differ between the two entry points"
-            assert jw == js
-        else:
-            # these paths add with floating-point atomics: equal to rounding
-            assert np.max(np.abs(cw - cs)) <= 1e-6 * np.max(np.abs(cw))
-            assert abs(jw - js) <= 1e-12 * abs(jw)
+        # every K-means sum is fixed point: the same bits from both entry points
+        assert np.array_equal(cw, cs), "centers differ between the two entry points"
+        assert jw == js
 
 
 def test_noalloc_rejects_sizes_beyond_its_scratch():
