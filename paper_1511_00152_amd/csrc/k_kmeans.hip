@@ -319,12 +319,22 @@ __device__ inline float dpp_row_total(float v)
 }
 
 
+// 4-lane butterfly sum (DPP quad permutations): every lane of the quad ends
+// with the same total (a + b and b + a are the same in floating point).
+__device__ inline float quad_total(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, true));  // [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xf, 0xf, true));  // [2,3,0,1]
+    return v;
+}
+
 // One sample of the cooperative assignment (its group of W lanes): distances
-// from the entries the lanes hold (x, l: four per lane, entries u W + sl, -1
-// past m; further entries are loaded here when m > 4 W), the decision, and the
-// entries' sums and counts.
-template <int W, int NQ4>
-__device__ inline void coop_sample(int64_t i, const float (&x0)[4], const int (&l0)[4],
+// from the entries the lanes hold (x, l: E per lane, entries u W + sl, -1 past
+// m; further entries are loaded here when m > E W), the decision, and the
+// entries' sums and counts.  W = 16: a DPP row per sample, lane 15 decides
+// and broadcasts; W = 4: a quad per sample, every lane has the totals.
+template <int W, int E, int NQ4>
+__device__ inline void coop_sample(int64_t i, const float (&x0)[E], const int (&l0)[E],
                                    const float* __restrict__ vals, const uint16_t* __restrict__ idx, int m, int p,
                                    int K, int KP4, const float* cT, unsigned long long* sums, uint32_t* cnt2,
                                    int fx, float cmax, int sl, int32_t* __restrict__ assign,
@@ -338,45 +348,37 @@ __device__ inline void coop_sample(int64_t i, const float (&x0)[4], const int (&
 #pragma unroll
     for (int q = 0; q < NQ; ++q) d[q] = 0.0f;
     float sv = 0.0f;
-    for (int a0 = 0; a0 < m; a0 += 4 * W) {
-        float x[4];
-        int l[4];
+    auto add_entry = [&](float xv, int lv) {
+        sv = fmaf(xv, xv, sv);
+        const float4* c4 = reinterpret_cast<const float4*>(cT + __umul24((unsigned)lv, (unsigned)KP4));
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (a0 == 0) {
-                x[u] = x0[u];
-                l[u] = l0[u];
-            } else {
-                const int a = a0 + u * W + sl;
-                x[u] = (a < m) ? v[a] : 0.0f;
-                l[u] = (a < m) ? (int)ix[a] : -1;
+        for (int q4 = 0; q4 < NQ4; ++q4) {
+            const float4 c = c4[q4];
+            const float cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float diff = xv - cc[r];
+                d[4 * q4 + r] = fmaf(diff, diff, d[4 * q4 + r]);
             }
         }
+    };
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (l[u] >= 0) {
-                sv = fmaf(x[u], x[u], sv);
-                const float4* c4 = reinterpret_cast<const float4*>(cT + l[u] * KP4);
-#pragma unroll
-                for (int q4 = 0; q4 < NQ4; ++q4) {
-                    const float4 c = c4[q4];
-                    const float cc[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float diff = x[u] - cc[r];
-                        d[4 * q4 + r] = fmaf(diff, diff, d[4 * q4 + r]);
-                    }
-                }
-            }
-        }
-    }
-    sv = dpp_row_total(sv);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) d[q] = dpp_row_total(d[q]);
-    // lane W - 1 of the row holds the totals and decides; padding clusters
-    // (q >= K) take no part
+    for (int u = 0; u < E; ++u)
+        if (l0[u] >= 0) add_entry(x0[u], l0[u]);
+    for (int a = E * W + sl; a < m; a += W) add_entry(v[a], (int)ix[a]);
     float best = INFINITY, second = INFINITY;
     int bestk = 0;
+    int flag = 0;
+    if constexpr (W == 4) {
+        sv = quad_total(sv);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) d[q] = quad_total(d[q]);
+    } else {
+        sv = dpp_row_total(sv);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) d[q] = dpp_row_total(d[q]);
+    }
+    // padding clusters (q >= K) take no part
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const float dq = q < K ? d[q] : INFINITY;
@@ -385,7 +387,6 @@ __device__ inline void coop_sample(int64_t i, const float (&x0)[4], const int (&
         bestk = nb ? q : bestk;
         best = nb ? dq : best;
     }
-    int flag = 0;
     if (K > 1) {
         // |d32 - d| <= u (8 (sum v^2 + sum mu^2) + 1.01 m d), u = 2^-24, per
         // candidate; two candidates, factor 2 of slack
@@ -394,8 +395,11 @@ __device__ inline void coop_sample(int64_t i, const float (&x0)[4], const int (&
         const float bound = 2.0f * u * (16.0f * (sv + mf * cmax * cmax) + 1.01f * mf * (best + second));
         flag = !(second - best > bound);
     }
-    flag = __shfl(flag, W - 1, W);
-    bestk = __shfl(bestk, W - 1, W);
+    if constexpr (W == 16) {
+        // lane 15 of the row holds the totals
+        flag = __shfl(flag, W - 1, W);
+        bestk = __shfl(bestk, W - 1, W);
+    }
     if (flag) {
         if (sl == W - 1) rlist[atomicAdd(rcount, 1u)] = i;
         return;
@@ -405,40 +409,37 @@ __device__ inline void coop_sample(int64_t i, const float (&x0)[4], const int (&
         dist[i] = (double)best;
     }
     const int64_t kb = (int64_t)bestk * p;
-    // the first 4 W entries from registers, any others from memory
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        if (l0[u] >= 0) {
-            const int64_t e = kb + l0[u];
-            atomicAdd(&sums[e], (unsigned long long)__double2ll_rn(ldexp((double)x0[u], fx)));
-            atomicAdd(&cnt2[e >> 1], 1u << (16 * (int)(e & 1)));
-        }
-    }
-    for (int a = 4 * W + sl; a < m; a += W) {
-        const int64_t e = kb + ix[a];
-        atomicAdd(&sums[e], (unsigned long long)__double2ll_rn(ldexp((double)v[a], fx)));
+    auto add_sum = [&](float xv, int lv) {
+        const int64_t e = kb + lv;
+        atomicAdd(&sums[e], (unsigned long long)__double2ll_rn(ldexp((double)xv, fx)));
         atomicAdd(&cnt2[e >> 1], 1u << (16 * (int)(e & 1)));
-    }
+    };
+    // the first E W entries from registers, any others from memory
+#pragma unroll
+    for (int u = 0; u < E; ++u)
+        if (l0[u] >= 0) add_sum(x0[u], l0[u]);
+    for (int a = E * W + sl; a < m; a += W) add_sum(v[a], (int)ix[a]);
 }
 
 
-// FP32 assignment with coalesced rows: a group of 16 lanes (one DPP row) per
-// sample, lanes over its kept entries, each lane's partial distances to the
-// K <= 32 centers in registers, then a row sum.  The summation order differs
-// from the sequential one, but its rounding error obeys the same bound (every
-// term passes through at most m additions), so the near-tie test and the FP64
-// recheck give the FP64 argmin as before.  Centers are transposed in LDS with
-// rows padded to KP4 = ceil4(K) floats and read as float4.  Each workgroup
-// takes its own fixed-point scale from its samples' largest |value|.
-template <int NQ4>
+// FP32 assignment with coalesced rows: a group of W lanes per sample (a quad
+// for m <= 64, a DPP row otherwise), lanes over its kept entries, each lane's
+// partial distances to the K <= 32 centers in registers, then a group sum.
+// The summation order differs from the sequential one, but its rounding error
+// obeys the same bound (every term passes through at most m additions), so the
+// near-tie test and the FP64 recheck give the FP64 argmin as before.  Centers
+// are transposed in LDS with rows padded to KP4 = ceil4(K) floats and read as
+// float4.  Each workgroup takes its own fixed-point scale from its samples'
+// largest |value|.
+template <int W, int E, int NQ4>
 __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     const float* __restrict__ vals, const uint16_t* __restrict__ idx, int64_t n, int m, int p, int K,
     const double* __restrict__ cin, int64_t per_wg, int32_t* __restrict__ assign, int64_t* __restrict__ psum,
     uint32_t* __restrict__ pcnt, uint64_t* __restrict__ wvmax, unsigned long long* __restrict__ gmax,
     double* __restrict__ dist, int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
 {
-    constexpr int W = 16;
     constexpr int G = kKmLdsThreads / W;  // groups per workgroup
+    constexpr int AHEAD = (E >= 16) ? 1 : 2;  // samples whose first entries are in flight
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float red_f[kKmLdsThreads / 64];
     const int tid = threadIdx.x;
@@ -480,35 +481,39 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     const int fx = km_F<float>(km_ev(dbits((double)vm)), km_lc(per_wg));
 
     const int g = tid / W, sl = tid % W;
-    // the first 4 W entries of the samples two and one steps ahead are in
-    // flight while a sample is processed
-    auto load_first = [&](int64_t i, float (&x)[4], int (&l)[4]) {
+    auto load_first = [&](int64_t i, float (&x)[E], int (&l)[E]) {
         const float* v = vals + i * (int64_t)m;
         const uint16_t* ix = idx + i * (int64_t)m;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < E; ++u) {
             const int a = u * W + sl;
             x[u] = (a < m) ? v[a] : 0.0f;
             l[u] = (a < m) ? (int)ix[a] : -1;
         }
     };
-    float xa[4], xb[4];
-    int la[4], lb[4];
+    float xa[E], xb[E];
+    int la[E], lb[E];
     if (i0 + g < i1) load_first(i0 + g, xa, la);
-    if (i0 + g + G < i1) load_first(i0 + g + G, xb, lb);
+    if (AHEAD == 2 && i0 + g + G < i1) load_first(i0 + g + G, xb, lb);
     for (int64_t i = i0 + g; i < i1; i += G) {
-        float x[4];
-        int l[4];
+        float x[E];
+        int l[E];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < E; ++u) {
             x[u] = xa[u];
             l[u] = la[u];
-            xa[u] = xb[u];
-            la[u] = lb[u];
+            if (AHEAD == 2) {
+                xa[u] = xb[u];
+                la[u] = lb[u];
+            }
         }
-        if (i + 2 * G < i1) load_first(i + 2 * G, xb, lb);
-        coop_sample<W, NQ4>(i, x, l, vals, idx, m, p, K, KP4, cT, sums, cnt2, fx, cmax, sl, assign, dist, rlist,
-                            rcount);
+        if (AHEAD == 2) {
+            if (i + 2 * G < i1) load_first(i + 2 * G, xb, lb);
+        } else {
+            if (i + G < i1) load_first(i + G, xa, la);
+        }
+        coop_sample<W, E, NQ4>(i, x, l, vals, idx, m, p, K, KP4, cT, sums, cnt2, fx, cmax, sl, assign, dist,
+                               rlist, rcount);
     }
     __syncthreads();
     int64_t* ps = psum + (int64_t)blockIdx.x * KP;
@@ -800,36 +805,59 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
             if (k.coop) {
                 static bool coop_attr = false;
                 if (!coop_attr) {
-                    const void* fns[8] = {reinterpret_cast<const void*>(&k_kmeans_assign_coop<1>),
-                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<2>),
-                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<3>),
-                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<4>),
-                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<5>),
-                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<6>),
-                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<7>),
-                                          reinterpret_cast<const void*>(&k_kmeans_assign_coop<8>)};
+                    const void* fns[16] = {
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<16, 4, 1>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<16, 4, 2>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<16, 4, 3>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<16, 4, 4>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<16, 4, 5>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<16, 4, 6>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<16, 4, 7>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<16, 4, 8>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<4, 16, 1>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<4, 16, 2>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<4, 16, 3>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<4, 16, 4>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<4, 16, 5>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<4, 16, 6>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<4, 16, 7>),
+                        reinterpret_cast<const void*>(&k_kmeans_assign_coop<4, 16, 8>)};
                     for (const void* f : fns)
                         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kKmLdsMax);
                     coop_attr = true;
                 }
                 {
                     ProfScope ps_("kmeans_assign", s);
-                    // K <= 32 here: one instance per number of four-cluster groups
-#define PDS_KM_COOP(Q)                                                                                        \
-    case Q:                                                                                                   \
-        hipLaunchKernelGGL(k_kmeans_assign_coop<Q>, dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s, vals, idx, n, m, \
-                           p, K, cin, k.per_wg, assign, reinterpret_cast<int64_t*>(psum), pcnt, wvmax, gmax,    \
-                           dist, rlist, rcount);                                                              \
+                    // K <= 32 here: one instance per number of four-cluster groups; a
+                    // quad per sample while its entries fit sixteen per lane
+#define PDS_KM_COOP(W_, E_, Q)                                                                                 \
+    case Q:                                                                                                    \
+        hipLaunchKernelGGL((k_kmeans_assign_coop<W_, E_, Q>), dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s, vals, idx, \
+                           n, m, p, K, cin, k.per_wg, assign, reinterpret_cast<int64_t*>(psum), pcnt, wvmax, gmax,   \
+                           dist, rlist, rcount);                                                               \
         break;
-                    switch ((K + 3) / 4) {
-                        PDS_KM_COOP(1)
-                        PDS_KM_COOP(2)
-                        PDS_KM_COOP(3)
-                        PDS_KM_COOP(4)
-                        PDS_KM_COOP(5)
-                        PDS_KM_COOP(6)
-                        PDS_KM_COOP(7)
-                        default: PDS_KM_COOP(8)
+                    if (m <= 64) {
+                        switch ((K + 3) / 4) {
+                            PDS_KM_COOP(4, 16, 1)
+                            PDS_KM_COOP(4, 16, 2)
+                            PDS_KM_COOP(4, 16, 3)
+                            PDS_KM_COOP(4, 16, 4)
+                            PDS_KM_COOP(4, 16, 5)
+                            PDS_KM_COOP(4, 16, 6)
+                            PDS_KM_COOP(4, 16, 7)
+                            default: PDS_KM_COOP(4, 16, 8)
+                        }
+                    } else {
+                        switch ((K + 3) / 4) {
+                            PDS_KM_COOP(16, 4, 1)
+                            PDS_KM_COOP(16, 4, 2)
+                            PDS_KM_COOP(16, 4, 3)
+                            PDS_KM_COOP(16, 4, 4)
+                            PDS_KM_COOP(16, 4, 5)
+                            PDS_KM_COOP(16, 4, 6)
+                            PDS_KM_COOP(16, 4, 7)
+                            default: PDS_KM_COOP(16, 4, 8)
+                        }
                     }
 #undef PDS_KM_COOP
                 }

@@ -257,7 +257,9 @@ def test_kmeans_step_deterministic(prec, p, m, K, n):
 KM_SHAPES = [(256, 26, 2000, 5), (1024, 51, 9000, 10), (64, 64, 500, 3), (128, 1, 300, 4), (512, 40, 1000, 1),
              (256, 30, 3000, 37), (4096, 100, 700, 100),
              # FP32 cooperative assignment, one instance per four-cluster group count
-             (128, 12, 800, 16), (256, 20, 1500, 23), (256, 26, 1200, 32)]
+             # (a quad per sample for m <= 64, a DPP row beyond)
+             (128, 12, 800, 16), (256, 20, 1500, 23), (256, 26, 1200, 32), (256, 65, 1500, 7),
+             (512, 100, 3000, 8), (2048, 205, 2000, 20)]
 
 
 @pytest.mark.parametrize("prec", list(PRECS))
