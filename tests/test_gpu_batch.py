@@ -17,6 +17,7 @@ import paper_1511_00152_amd as pds  # noqa: E402
 from paper_1511_00152_amd import _lib  # noqa: E402
 from paper_1511_00152_amd.batch import Batch  # noqa: E402
 from oracle import ref  # noqa: E402
+import synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -191,6 +192,56 @@ def test_batch_autotune_keeps_results(data):
         assert nerr(s["centers"].cpu().numpy(), C) < 1e-5
         if d["n"] > 0:
             assert np.array_equal(s["assign"].cpu().numpy(), assign)
+
+
+@pytest.fixture(scope="module")
+def drawn():
+    """24 sets drawn (seeded) from the benched 256-set workload, each with its own
+    p, m, K and seed and that workload's data recipe, rows capped at 2000-2499
+    (ragged) so the oracle stays fast; 12 further sets keep their full n (below
+    12000 rows) so accumulation chunks and long work-queue items are exercised."""
+    prm = synth.batch_params("batch256_f32")
+    rng = np.random.default_rng(20261203)
+    small = [int(i) for i in rng.choice(len(prm), 24, replace=False)]
+    full = [i for i in range(len(prm)) if prm[i]["n"] <= 12000 and i not in small][:12]
+    out = []
+    for j, i in enumerate(small + full):
+        pr = prm[i]
+        n = pr["n"] if i in full else min(pr["n"], 2000 + (i * 37) % 500)
+        X = synth.batch_set_torch("batch256_f32", i, pr, n=n)
+        Xh = X.cpu().numpy()
+        v, ix = ref.compress(Xh, pr["seed"], pr["m"])
+        out.append(dict(p=pr["p"], n=n, m=pr["m"], K=pr["K"], seed=pr["seed"], X=X, ovals=v, oidx=ix, set=i))
+    torch.cuda.synchronize()
+    return out
+
+
+def test_batch_draw_of_benched_workload(drawn):
+    """The batched form on sets drawn from the benched workload: kept indices
+    bit-exact and values 1e-6 for every set; after T = 3 rounds (GPU seeding
+    rule on both sides) centers and objectives within 1e-5, and every
+    assignment equal to the oracle's except where the oracle's own margin is
+    below the FP32 noise of a distance (the GPU clusters its FP32 values, the
+    oracle its FP64 ones)."""
+    T = 3
+    b = Batch([dict(X=d["X"], m=d["m"], K=d["K"], seed=d["seed"]) for d in drawn], T=T)
+    b.compress()
+    b.init_centers()
+    b.kmeans()
+    torch.cuda.synchronize()
+    for d, s in zip(drawn, b.sets):
+        log(f"  set {d['set']}: p={d['p']} n={d['n']} m={d['m']} K={d['K']}")
+        assert np.array_equal(s["idx"].cpu().numpy().view(np.uint16), d["oidx"])
+        assert nerr(s["vals"].cpu().numpy(), d["ovals"]) < 1e-6
+        C = oracle_seed_centers(d["ovals"], d["oidx"], d["p"], d["K"])
+        objs = []
+        for _ in range(T):
+            C, a_o, J_o, margin = ref.kmeans_step(d["p"], d["ovals"], d["oidx"], C)
+            objs.append(J_o)
+        assert nerr(s["centers"].cpu().numpy(), C) < 1e-5
+        bad = np.nonzero(s["assign"].cpu().numpy() != a_o)[0]
+        assert np.all(margin[bad] <= 1e-4 * (J_o / d["n"])), (d["set"], bad[:5], margin[bad][:5])
+        assert np.allclose(s["objective"].cpu().numpy()[:T], objs, rtol=1e-5, atol=1e-9)
 
 
 def _create_status(p, m, K, align_off=0, reserved=0):
