@@ -93,12 +93,39 @@ typedef enum {
 
 typedef struct pds_plan_s* pds_plan;
 
+/* The plan's preconditioning transform (Sec. III): the normalized Hadamard
+ * matrix (eq. ROS; p a power of two) or the orthonormal DCT-II, which Sec. III
+ * allows as another fast orthonormal transform with entries O(1/sqrt(p))
+ * (Thm. 1 with eta = 1/2) and Sec. VII uses for p = 784. */
+typedef enum { PDS_TRANSFORM_HADAMARD = 0, PDS_TRANSFORM_DCT = 1 } pds_transform;
+#define PDS_DCT_MAX_P 8192
+
 /* Creates a plan for samples of dimension p keeping m coordinates each
  * (compression factor gamma = m / p, Sec. I setup), with random seed `seed`
  * and precision `prec`.  Host-only (no device work); *out receives the plan.
  * Errors: PDS_E_ARG (out NULL or prec unknown), PDS_E_UNSUPPORTED (p),
  * PDS_E_M (m). */
 pds_status pds_plan_create(pds_plan* out, int64_t p, int64_t m, uint64_t seed, int32_t prec);
+
+/* Creates a plan whose preconditioner is the orthonormal DCT-II in place of
+ * H (pds_transform): y_i = C D x_i with
+ *     C[j][k] = s_j cos(pi (2k + 1) j / (2p)),  s_0 = sqrt(1/p), s_j = sqrt(2/p),
+ * for any p in [2, PDS_DCT_MAX_P] (no power-of-two restriction), the same
+ * signs D (pds_signs) and the same kept sets as a Hadamard plan of this
+ * (p, m, seed).  Every plan call takes it: pds_compress transforms with C (an
+ * FP64 dense product, p^2 multiply-adds per sample, rounded once to the
+ * plan's value type; its workspace holds the p x p table), pds_unmix applies
+ * D C^T, and the covariance accumulates its Gram over the next power of two
+ * pg >= p (pds_covariance_acc_size is pg x pg doubles; kept indices are < p,
+ * so the extra rows and columns stay zero) and finalizes the p x p C_n.  The
+ * m-selector calls take Hadamard plans only.  Host-only.
+ * Errors: PDS_E_ARG (out NULL or prec unknown), PDS_E_UNSUPPORTED (p),
+ * PDS_E_M (m). */
+pds_status pds_plan_create_dct(pds_plan* out, int64_t p, int64_t m, uint64_t seed, int32_t prec);
+
+/* The plan's pds_transform into *transform.  Host-only.
+ * Errors: PDS_E_ARG (NULL plan or transform). */
+pds_status pds_plan_transform(pds_plan plan, int32_t* transform);
 
 /* Frees a plan (NULL is accepted). */
 pds_status pds_plan_destroy(pds_plan plan);
@@ -126,7 +153,8 @@ pds_status pds_plan_gram(pds_plan plan, int64_t n, int32_t* algo);
  * through pds_covariance_acc_size.  Host-only. */
 pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, size_t* bytes);
 
-/* Bytes of the covariance accumulator `acc` (p x p doubles). */
+/* Bytes of the covariance accumulator `acc` (p x p doubles; pg x pg for DCT
+ * plans, pg the next power of two >= p). */
 pds_status pds_covariance_acc_size(pds_plan plan, size_t* bytes);
 
 /* One-pass compression (Alg. 1, first loop; Sec. I setup; Sec. III eq. ROS):
@@ -144,7 +172,8 @@ pds_status pds_covariance_acc_size(pds_plan plan, size_t* bytes);
  *         double for PDS_F64, float otherwise.
  *   vals  device, n x m, same element type as X.
  *   idx   device, n x m uint16.
- *   ws    may be NULL (compress needs no workspace; ws_bytes ignored).
+ *   ws    may be NULL for Hadamard plans (no workspace; ws_bytes ignored);
+ *         DCT plans need pds_workspace_size(COMPRESS) bytes (the p x p table).
  * Errors: PDS_E_ARG (null pointers with n > 0, n < 0, ldx < p). */
 pds_status pds_compress(pds_plan plan, const void* X, int64_t n, int64_t ldx, uint64_t i0, void* vals,
                         uint16_t* idx, void* ws, size_t ws_bytes, void* stream);
@@ -300,7 +329,8 @@ pds_status pds_kmeans_step_noalloc(pds_plan plan, const void* vals, const uint16
                                    double* objective, void* stream);
 
 /* Unmixing of centers (eq. mu-mu'; Alg. 1, last step): centers_out[k] =
- * (H D)^T centers_pre[k] = D H centers_pre[k] (H is symmetric), FP64.
+ * (H D)^T centers_pre[k] = D H centers_pre[k] (H is symmetric), FP64; for
+ * DCT plans (C D)^T centers_pre[k] = D C^T centers_pre[k].
  * centers_pre / centers_out: device, K x p doubles (may not alias).
  * Errors: PDS_E_ARG (null pointers, K < 1). */
 pds_status pds_unmix(pds_plan plan, const double* centers_pre, int32_t K, double* centers_out, void* stream);

@@ -16,14 +16,15 @@ import ctypes
 
 from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_EXPLAINED_WS_BYTES, PDS_F32,
                    PDS_F64, PDS_GRAM_AUTO, PDS_GRAM_DENSE, PDS_GRAM_SPARSE, PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_KMEANS_BEST,
-                   PDS_OP_KMEANSPP, PDS_OP_MEAN, PDS_SPLIT_BF16, EXPORTS, PdsError, check, lib)
+                   PDS_OP_KMEANSPP, PDS_OP_MEAN, PDS_SPLIT_BF16, PDS_TRANSFORM_DCT, PDS_TRANSFORM_HADAMARD, PDS_DCT_MAX_P,
+                   EXPORTS, PdsError, check, lib)
 
 __all__ = [
     "Plan", "compress", "pad_rows", "covariance", "CovarianceAccumulator", "sample_mean", "kmeanspp", "kmeans_best",
     "kmeans_step", "unmix", "kmeans_2pass", "sparsified_kmeans", "top_eigenvalues", "principal_components",
     "explained_variance",
     "PdsError", "PDS_F64", "PDS_F32", "PDS_SPLIT_BF16", "PDS_GRAM_AUTO", "PDS_GRAM_DENSE", "PDS_GRAM_SPARSE", "lib",
-    "EXPORTS",
+    "PDS_TRANSFORM_HADAMARD", "PDS_TRANSFORM_DCT", "PDS_DCT_MAX_P", "EXPORTS",
 ]
 
 
@@ -38,16 +39,27 @@ def _ptr(t):
 
 
 class Plan:
-    """pds_plan: dimension p, kept coordinates m, seed, precision, and the
-    covariance's Gram form (PDS_GRAM_AUTO, PDS_GRAM_DENSE or PDS_GRAM_SPARSE)."""
+    """pds_plan: dimension p, kept coordinates m, seed, precision, the
+    covariance's Gram form (PDS_GRAM_AUTO, PDS_GRAM_DENSE or PDS_GRAM_SPARSE)
+    and the preconditioner (PDS_TRANSFORM_HADAMARD, p a power of two, or
+    PDS_TRANSFORM_DCT, any p up to PDS_DCT_MAX_P)."""
 
-    def __init__(self, p: int, m: int, seed: int = 0, prec: int = PDS_F32, gram: int = PDS_GRAM_AUTO):
+    def __init__(self, p: int, m: int, seed: int = 0, prec: int = PDS_F32, gram: int = PDS_GRAM_AUTO,
+                 transform: int = PDS_TRANSFORM_HADAMARD):
         self.p, self.m, self.seed, self.prec = int(p), int(m), int(seed), int(prec)
+        self.transform = int(transform)
         h = ctypes.c_void_p()
-        check(lib().pds_plan_create(ctypes.byref(h), self.p, self.m, self.seed, self.prec), "pds_plan_create")
+        if self.transform == PDS_TRANSFORM_DCT:
+            check(lib().pds_plan_create_dct(ctypes.byref(h), self.p, self.m, self.seed, self.prec),
+                  "pds_plan_create_dct")
+        else:
+            check(lib().pds_plan_create(ctypes.byref(h), self.p, self.m, self.seed, self.prec), "pds_plan_create")
         self._h = h
         if gram != PDS_GRAM_AUTO:
             check(lib().pds_plan_set_gram(h, int(gram)), "pds_plan_set_gram")
+        b = ctypes.c_size_t(0)
+        check(lib().pds_covariance_acc_size(h, ctypes.byref(b)), "pds_covariance_acc_size")
+        self.pg = int(round((b.value // 8) ** 0.5))  # the covariance accumulator is pg x pg
 
     def gram_form(self, n: int) -> int:
         """PDS_GRAM_DENSE or PDS_GRAM_SPARSE: the form a covariance call over n samples runs."""
@@ -147,7 +159,7 @@ class CovarianceAccumulator:
         import torch
 
         self.plan = plan
-        self.acc = torch.zeros((plan.p, plan.p), dtype=torch.float64, device=device or "cuda")
+        self.acc = torch.zeros((plan.pg, plan.pg), dtype=torch.float64, device=device or "cuda")
         self.n = 0
         self._ws = None
 
@@ -185,7 +197,7 @@ def covariance(plan: Plan, vals, idx, acc=None, ws=None, C=None):
     n = vals.shape[0]
     dev = vals.device
     if acc is None:
-        acc = torch.zeros((plan.p, plan.p), dtype=torch.float64, device=dev)
+        acc = torch.zeros((plan.pg, plan.pg), dtype=torch.float64, device=dev)
     if C is None:
         C = torch.empty((plan.p, plan.p), dtype=torch.float64, device=dev)
     if ws is None:
@@ -333,7 +345,7 @@ def kmeans_step(plan: Plan, vals, idx, centers, out=None, assign=None, objective
 
 
 def unmix(plan: Plan, centers_pre, out=None):
-    """mu = (H D)^T mu' for each row of centers_pre (FP64)."""
+    """mu = (H D)^T mu' (DCT plans: (C D)^T mu') for each row of centers_pre (FP64)."""
     import torch
 
     if out is None:

@@ -25,6 +25,10 @@ PDS_GRAM_AUTO = 0
 PDS_GRAM_DENSE = 1
 PDS_GRAM_SPARSE = 2
 
+PDS_TRANSFORM_HADAMARD = 0
+PDS_TRANSFORM_DCT = 1
+PDS_DCT_MAX_P = 8192
+
 PDS_OP_COMPRESS = 0
 PDS_OP_COVARIANCE = 1
 PDS_OP_KMEANS = 2
@@ -37,7 +41,7 @@ PDS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # every entry point declared in include/pds.h
 EXPORTS = (
-    "pds_plan_create", "pds_plan_destroy", "pds_plan_set_gram", "pds_plan_gram", "pds_signs", "pds_workspace_size", "pds_covariance_acc_size",
+    "pds_plan_create", "pds_plan_create_dct", "pds_plan_transform", "pds_plan_destroy", "pds_plan_set_gram", "pds_plan_gram", "pds_signs", "pds_workspace_size", "pds_covariance_acc_size",
     "pds_compress", "pds_covariance", "pds_kmeans_step", "pds_kmeans_step_noalloc", "pds_unmix", "pds_kmeans_2pass", "pds_sample_mean", "pds_explained_variance", "pds_kmeanspp", "pds_kmeans_best", "pds_pad_rows", "pds_profile_enable", "pds_profile_report",
     "pds_last_error", "pds_version",
     "pds_row_moments", "pds_frob_diff", "pds_msel_workspace_size", "pds_msel_label", "pds_msel_features",
@@ -82,6 +86,8 @@ def lib():
     sz = ctypes.c_size_t
     st = ctypes.c_int
     L.pds_plan_create.argtypes = [ctypes.POINTER(P), i64, i64, u64, i32]
+    L.pds_plan_create_dct.argtypes = [ctypes.POINTER(P), i64, i64, u64, i32]
+    L.pds_plan_transform.argtypes = [P, ctypes.POINTER(i32)]
     L.pds_plan_destroy.argtypes = [P]
     L.pds_plan_set_gram.argtypes = [P, i32]
     L.pds_plan_gram.argtypes = [P, i64, ctypes.POINTER(i32)]

@@ -23,7 +23,9 @@ struct pds_plan_s {
     int64_t m;
     uint64_t seed;
     int32_t prec;
-    int32_t gram;  // pds_gram_algo
+    int32_t gram;       // pds_gram_algo
+    int32_t transform;  // pds_transform
+    int64_t pg;         // Gram dimension: p, or the next power of two for DCT plans
 };
 
 struct pds_batch_s {
@@ -196,7 +198,41 @@ pds_status pds_plan_create(pds_plan* out, int64_t p, int64_t m, uint64_t seed, i
     pl->seed = seed;
     pl->prec = prec;
     pl->gram = PDS_GRAM_AUTO;
+    pl->transform = PDS_TRANSFORM_HADAMARD;
+    pl->pg = p;
     *out = pl;
+    return PDS_OK;
+}
+
+pds_status pds_plan_create_dct(pds_plan* out, int64_t p, int64_t m, uint64_t seed, int32_t prec)
+{
+    if (!out) return fail(PDS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (prec != PDS_F64 && prec != PDS_F32 && prec != PDS_SPLIT_BF16)
+        return fail(PDS_E_ARG, "unknown precision %d", (int)prec);
+    if (p < 2 || p > PDS_DCT_MAX_P)
+        return fail(PDS_E_UNSUPPORTED, "p = %lld: DCT plans take p in [2, %d]", (long long)p, (int)PDS_DCT_MAX_P);
+    if (m < 1 || m > p) return fail(PDS_E_M, "m = %lld: must satisfy 1 <= m <= p = %lld", (long long)m, (long long)p);
+    pds_plan pl = new (std::nothrow) pds_plan_s;
+    if (!pl) return fail(PDS_E_ARG, "out of host memory");
+    pl->p = p;
+    pl->m = m;
+    pl->seed = seed;
+    pl->prec = prec;
+    pl->gram = PDS_GRAM_AUTO;
+    pl->transform = PDS_TRANSFORM_DCT;
+    int64_t pg = 2;
+    while (pg < p) pg <<= 1;
+    pl->pg = pg;
+    *out = pl;
+    return PDS_OK;
+}
+
+pds_status pds_plan_transform(pds_plan plan, int32_t* transform)
+{
+    if (!plan) return fail(PDS_E_ARG, "plan is NULL");
+    if (!transform) return fail(PDS_E_ARG, "transform is NULL");
+    *transform = plan->transform;
     return PDS_OK;
 }
 
@@ -217,7 +253,7 @@ pds_status pds_plan_gram(pds_plan plan, int64_t n, int32_t* algo)
     if (!algo) return fail(PDS_E_ARG, "algo is NULL");
     if (n < 0) return fail(PDS_E_ARG, "n < 0");
     pds::DeviceInfo dev = query_dev_or_default();
-    *algo = pds::covariance_is_sparse(plan->prec, (int)plan->p, (int)plan->m, n, dev, plan->gram) ? PDS_GRAM_SPARSE
+    *algo = pds::covariance_is_sparse(plan->prec, (int)plan->pg, (int)plan->m, n, dev, plan->gram) ? PDS_GRAM_SPARSE
                                                                                                   : PDS_GRAM_DENSE;
     return PDS_OK;
 }
@@ -253,10 +289,11 @@ pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, s
     const int p = (int)plan->p, m = (int)plan->m;
     switch (op) {
         case PDS_OP_COMPRESS:
-            *bytes = pds::compress_workspace(plan->prec, p, n, dev);
+            *bytes = plan->transform == PDS_TRANSFORM_DCT ? pds::dct_compress_workspace(p)
+                                                          : pds::compress_workspace(plan->prec, p, n, dev);
             return PDS_OK;
         case PDS_OP_COVARIANCE:
-            *bytes = pds::covariance_workspace(plan->prec, p, m, n, dev, plan->gram);
+            *bytes = pds::covariance_workspace(plan->prec, (int)plan->pg, m, n, dev, plan->gram);
             return PDS_OK;
         case PDS_OP_KMEANS:
             if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
@@ -285,7 +322,7 @@ pds_status pds_covariance_acc_size(pds_plan plan, size_t* bytes)
 {
     if (pds_status st = check_plan(plan)) return st;
     if (!bytes) return fail(PDS_E_ARG, "bytes is NULL");
-    *bytes = (size_t)plan->p * (size_t)plan->p * sizeof(double);
+    *bytes = (size_t)plan->pg * (size_t)plan->pg * sizeof(double);
     return PDS_OK;
 }
 
@@ -300,12 +337,19 @@ pds_status pds_compress(pds_plan plan, const void* X, int64_t n, int64_t ldx, ui
     pds::DeviceInfo dev;
     hipError_t e = pds::device_info(dev);
     if (e != hipSuccess) return hip_fail(e, "pds_compress");
-    const size_t need = pds::compress_workspace(plan->prec, (int)plan->p, n, dev);
+    const bool dct = plan->transform == PDS_TRANSFORM_DCT;
+    const size_t need = dct ? pds::dct_compress_workspace((int)plan->p)
+                            : pds::compress_workspace(plan->prec, (int)plan->p, n, dev);
     if (need > 0 && (!ws || ws_bytes < need))
         return fail(PDS_E_WORKSPACE, "compress needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     e = pds::launch_sample_indices(plan->seed, (int)plan->p, (int)plan->m, n, i0, idx, dev, s);
     if (e != hipSuccess) return hip_fail(e, "sample_indices");
+    if (dct) {
+        e = pds::launch_dct_compress(plan->prec, plan->seed, (int)plan->p, (int)plan->m, X, n, ldx, idx, vals, ws, s);
+        if (e != hipSuccess) return hip_fail(e, "compress (DCT)");
+        return PDS_OK;
+    }
     e = pds::launch_compress(plan->prec, plan->seed, (int)plan->p, (int)plan->m, X, n, ldx, idx, vals, ws, ws_bytes,
                              dev, s);
     if (e != hipSuccess) return hip_fail(e, "compress");
@@ -325,17 +369,18 @@ pds_status pds_covariance(pds_plan plan, const void* vals, const uint16_t* idx, 
     pds::DeviceInfo dev;
     hipError_t e = pds::device_info(dev);
     if (e != hipSuccess) return hip_fail(e, "pds_covariance");
-    const size_t need = pds::covariance_workspace(plan->prec, (int)plan->p, (int)plan->m, n, dev, plan->gram);
+    const size_t need = pds::covariance_workspace(plan->prec, (int)plan->pg, (int)plan->m, n, dev, plan->gram);
     if (need > 0 && (!ws || ws_bytes < need))
         return fail(PDS_E_WORKSPACE, "covariance needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (n > 0) {
-        e = pds::launch_covariance_accumulate(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, acc, ws, ws_bytes,
+        e = pds::launch_covariance_accumulate(plan->prec, (int)plan->pg, (int)plan->m, vals, idx, n, acc, ws, ws_bytes,
                                               dev, s, plan->gram);
         if (e != hipSuccess) return hip_fail(e, "covariance accumulate");
     }
     if (finalize) {
-        e = pds::launch_covariance_finalize(plan->prec, (int)plan->p, (int)plan->m, n_total, acc, C_out, s);
+        e = pds::launch_covariance_finalize(plan->prec, (int)plan->p, (int)plan->pg, (int)plan->m, n_total, acc, C_out,
+                                            s);
         if (e != hipSuccess) return hip_fail(e, "covariance finalize");
     }
     return PDS_OK;
@@ -558,8 +603,10 @@ pds_status pds_unmix(pds_plan plan, const double* centers_pre, int32_t K, double
     if (K < 1) return fail(PDS_E_ARG, "K < 1");
     if (!centers_pre || !centers_out) return fail(PDS_E_ARG, "centers must be non-NULL");
     if (centers_pre == centers_out) return fail(PDS_E_ARG, "centers_pre and centers_out must not alias");
-    hipError_t e = pds::launch_unmix(plan->seed, (int)plan->p, centers_pre, K, centers_out,
-                                     reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = plan->transform == PDS_TRANSFORM_DCT
+                       ? pds::launch_dct_unmix(plan->seed, (int)plan->p, centers_pre, K, centers_out, s)
+                       : pds::launch_unmix(plan->seed, (int)plan->p, centers_pre, K, centers_out, s);
     if (e != hipSuccess) return hip_fail(e, "unmix");
     return PDS_OK;
 }
@@ -635,6 +682,8 @@ pds_status msel_check_plan(pds_plan plan)
     if (plan->m != plan->p) return fail(PDS_E_M, "m-selector calls need a plan with m = p (got m = %lld, p = %lld)",
                                         (long long)plan->m, (long long)plan->p);
     if (plan->prec != PDS_F32) return fail(PDS_E_ARG, "m-selector calls need a PDS_F32 plan");
+    if (plan->transform != PDS_TRANSFORM_HADAMARD)
+        return fail(PDS_E_UNSUPPORTED, "m-selector calls need a Hadamard plan");
     return PDS_OK;
 }
 
@@ -655,7 +704,7 @@ pds_status msel_exact(pds_plan plan, const float* X, int64_t n, int64_t ldx, uns
     if (e == hipSuccess) e = pds::launch_row_moments(X, n, p, ldx, reinterpret_cast<double*>(w + L.mr), dev, s);
     if (e == hipSuccess) e = pds::launch_row_moments(Y, n, p, p, reinterpret_cast<double*>(w + L.my), dev, s);
     if (e == hipSuccess) e = pds::launch_covariance_accumulate(PDS_F32, p, p, Y, idx, n, acc, cws, cws_bytes, dev, s, PDS_GRAM_DENSE);
-    if (e == hipSuccess) e = pds::launch_covariance_finalize(PDS_F32, p, p, n, acc, C, s);
+    if (e == hipSuccess) e = pds::launch_covariance_finalize(PDS_F32, p, p, p, n, acc, C, s);
     if (e == hipSuccess)
         e = pds::launch_frob_diff(C, C, (int64_t)p * p, reinterpret_cast<double*>(w + L.sums),
                                   reinterpret_cast<double*>(w + L.frob), s);

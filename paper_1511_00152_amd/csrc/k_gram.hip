@@ -1123,7 +1123,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const PT* __restrict__ part
     acc[(int64_t)(ta * g.tr + i) * g.p + (tb * g.tc + j)] += sum;
 }
 
-__global__ __launch_bounds__(256) void k_cov_finalize(const double* __restrict__ acc, int p, double sdiag,
+__global__ __launch_bounds__(256) void k_cov_finalize(const double* __restrict__ acc, int p, int lda, double sdiag,
                                                       double soff, double* __restrict__ C)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1132,7 +1132,7 @@ __global__ __launch_bounds__(256) void k_cov_finalize(const double* __restrict__
     // (min, max) lies in an upper tile; reading it for both (j, k) and (k, j)
     // makes the result exactly symmetric
     const int r = j < k ? j : k, c = j < k ? k : j;
-    const double v = acc[(int64_t)r * p + c];
+    const double v = acc[(int64_t)r * lda + c];
     C[g] = (j == k) ? sdiag * v : soff * v;
 }
 
@@ -1454,7 +1454,7 @@ hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals
     return hipGetLastError();
 }
 
-hipError_t launch_covariance_finalize(int prec, int p, int m, int64_t n_total, const double* acc, double* C,
+hipError_t launch_covariance_finalize(int prec, int p, int lda, int m, int64_t n_total, const double* acc, double* C,
                                       hipStream_t s)
 {
     (void)prec;
@@ -1463,8 +1463,8 @@ hipError_t launch_covariance_finalize(int prec, int p, int m, int64_t n_total, c
     const int64_t tot = (int64_t)p * p;
     {
         ProfScope ps_("cov_finalize", s);
-        hipLaunchKernelGGL(k_cov_finalize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, acc, p, sdiag, soff,
-                       C);
+        hipLaunchKernelGGL(k_cov_finalize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, acc, p, lda, sdiag,
+                           soff, C);
     }
     return hipGetLastError();
 }

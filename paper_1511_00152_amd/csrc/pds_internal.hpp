@@ -43,6 +43,13 @@ bool kron_transform_ok(int p, const void* X, int64_t ldx);
 hipError_t launch_compress_kron(uint64_t seed, int m, const float* X, int64_t n, int64_t ldx, const uint16_t* idx,
                                 float* vals, const DeviceInfo& dev, hipStream_t s);
 
+// DCT plans: y = C D x (orthonormal DCT-II) for any p <= 8192; ws holds the
+// p x p FP64 table (dct_compress_workspace bytes)
+size_t dct_compress_workspace(int p);
+hipError_t launch_dct_compress(int prec, uint64_t seed, int p, int m, const void* X, int64_t n, int64_t ldx,
+                               const uint16_t* idx, void* vals, void* ws, hipStream_t s);
+hipError_t launch_dct_unmix(uint64_t seed, int p, const double* cpre, int K, double* cout, hipStream_t s);
+
 // ---- covariance -----------------------------------------------------------
 // algo: 0 = the faster form by the cost model, 1 = dense tiles, 2 = sparse
 size_t covariance_workspace(int prec, int p, int m, int64_t n, const DeviceInfo& dev, int algo);
@@ -50,7 +57,8 @@ bool covariance_is_sparse(int prec, int p, int m, int64_t n, const DeviceInfo& d
 hipError_t launch_covariance_accumulate(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n,
                                         double* acc, void* ws, size_t ws_bytes, const DeviceInfo& dev,
                                         hipStream_t s, int algo);
-hipError_t launch_covariance_finalize(int prec, int p, int m, int64_t n_total, const double* acc, double* C,
+// C (p x p) from the accumulated Gram acc (row stride lda >= p)
+hipError_t launch_covariance_finalize(int prec, int p, int lda, int m, int64_t n_total, const double* acc, double* C,
                                       hipStream_t s);
 
 // ---- sample mean -------------------------------------------------------------

@@ -189,6 +189,52 @@ def test_stream_estimates_validates_on_the_host():
         stream_estimates(plan, torch.zeros(10, dtype=torch.float32), 4)  # not 2-D
 
 
+def _dct_status(p, m, prec=pds.PDS_F32):
+    h = ctypes.c_void_p()
+    st = pds.lib().pds_plan_create_dct(ctypes.byref(h), p, m, 0, prec)
+    if st == 0:
+        pds.lib().pds_plan_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("p,m,prec,expect", [
+    (784, 40, pds.PDS_F32, 0), (784, 784, pds.PDS_F64, 0), (2, 1, pds.PDS_F32, 0), (7, 3, pds.PDS_SPLIT_BF16, 0),
+    (8192, 100, pds.PDS_F32, 0), (1024, 51, pds.PDS_F32, 0),
+    (8193, 10, pds.PDS_F32, _lib.PDS_E_UNSUPPORTED), (1, 1, pds.PDS_F32, _lib.PDS_E_UNSUPPORTED),
+    (784, 0, pds.PDS_F32, _lib.PDS_E_M), (784, 785, pds.PDS_F32, _lib.PDS_E_M), (784, 40, 9, _lib.PDS_E_ARG),
+])
+def test_dct_plan_validation(p, m, prec, expect):
+    assert _dct_status(p, m, prec) == expect
+
+
+def test_dct_plan_queries():
+    """A DCT plan of any p (Sec. III's fast orthonormal transforms; Sec. VII's
+    p = 784): its transform reads back, its signs and compress workspace (the
+    p x p FP64 table), and a covariance accumulator over the next power of two;
+    the m-selector calls refuse it."""
+    L = pds.lib()
+    plan = pds.Plan(784, 40, seed=5, transform=pds.PDS_TRANSFORM_DCT)
+    t = ctypes.c_int32(-1)
+    assert L.pds_plan_transform(plan.handle, ctypes.byref(t)) == 0 and t.value == pds.PDS_TRANSFORM_DCT
+    assert L.pds_plan_transform(pds.Plan(256, 26).handle, ctypes.byref(t)) == 0 and t.value == 0
+    assert L.pds_plan_transform(None, ctypes.byref(t)) == _lib.PDS_E_ARG
+    assert L.pds_plan_transform(plan.handle, None) == _lib.PDS_E_ARG
+    assert np.array_equal(plan.signs(), ref.signs(5, 784))
+    assert plan.workspace_size(pds.PDS_OP_COMPRESS, 1000) == 784 * 784 * 8
+    b = ctypes.c_size_t()
+    assert L.pds_covariance_acc_size(plan.handle, ctypes.byref(b)) == 0 and b.value == 1024 * 1024 * 8
+    assert plan.pg == 1024
+    assert pds.Plan(1024, 51, transform=pds.PDS_TRANSFORM_DCT).pg == 1024
+    assert plan.workspace_size(pds.PDS_OP_COVARIANCE, 1000) == pds.Plan(1024, 40).workspace_size(
+        pds.PDS_OP_COVARIANCE, 1000)
+    assert plan.workspace_size(pds.PDS_OP_KMEANS, 1000, 10) > 0
+    sel = pds.Plan(784, 784, transform=pds.PDS_TRANSFORM_DCT)
+    out = ctypes.c_int32()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.pds_msel_label(sel.handle, fake, 10, 784, 0.1, ctypes.cast(ctypes.byref(out), ctypes.c_void_p), None,
+                            fake, 1 << 30, None) == _lib.PDS_E_UNSUPPORTED
+
+
 def test_gram_form_choice():
     """The automatic choice: FP32 plans take the sparse form at the workloads'
     small m/p (their dense tiles run on the slower FP32 matrix cores), split
