@@ -504,6 +504,75 @@ def run_mixture(pds, steps, warmup):
     }
 
 
+def run_dct(pds, steps, warmup):
+    """Sparsified K-means with the DCT preconditioner (Sec. VII runs it on
+    70000 digit images of p = 784 pixels; here the seeded stand-in
+    digits784_f32 of that shape): one DCT compression (gamma = 0.1), K-means++
+    seeding and T = 20 kmeans_step calls per step, then the unmixing.  The
+    DCT transform is an FP64 dense product, 2 p^2 flops per sample, priced
+    against the FP64 vector peak."""
+    import torch
+
+    import synth
+
+    name = "digits784_f32"
+    w = synth.WORKLOADS[name]
+    p, K, T = w["p"], w["K"], w["T"]
+    m = synth.m_from_gamma(w["gamma"], p)
+    X = torch.from_numpy(synth.digits_numpy(name)).cuda()
+    n = X.shape[0]
+    plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F32, transform=pds.PDS_TRANSFORM_DCT)
+    vals = torch.empty((n, m), dtype=torch.float32, device="cuda")
+    idx = torch.empty((n, m), dtype=torch.int16, device="cuda")
+    ws_c = plan.workspace(pds.PDS_OP_COMPRESS, n, device="cuda")
+    ws = plan.workspace(pds.PDS_OP_KMEANS, n, K, device="cuda")
+    ws_pp = plan.workspace(pds.PDS_OP_KMEANSPP, n, device="cuda")
+    ca = torch.zeros((K, p), dtype=torch.float64, device="cuda")
+    cb = torch.empty_like(ca)
+    assign = torch.empty(n, dtype=torch.int32, device="cuda")
+    objs = torch.empty(T, dtype=torch.float64, device="cuda")
+    chosen = torch.empty(K, dtype=torch.int64, device="cuda")
+    mu = torch.empty_like(ca)
+
+    def step():
+        pds.compress(plan, X, vals=vals, idx=idx, ws=ws_c)
+        pds.kmeanspp(plan, vals, idx, K, centers=ca, chosen=chosen, ws=ws_pp)
+        a, c = ca, cb
+        for r in range(T):
+            pds.kmeans_step(plan, vals, idx, a, out=c, assign=assign, objective=objs[r:r + 1], ws=ws)
+            a, c = c, a
+        pds.unmix(plan, a, out=mu)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lib = pds.lib()
+    lib.pds_profile_enable(1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    lib.pds_profile_enable(0)
+    kern = profile_report(lib)
+    o = objs.cpu().numpy()
+    t_dct = kern["compress"]["avg_ms"]
+    flops = 2.0 * n * p * p
+    t_k_round = sum(kern[k]["total_ms"] for k in kern if k.startswith("kmeans")) / (steps * T)
+    del X
+    return {
+        "workload": f"{name}: n={n}, p={p}, m={m}, K={K}, T={T}, FP32 plan with the DCT preconditioner; "
+                    "step = compress + K-means++ seeding + T kmeans_step + unmix",
+        "ms_per_step": wall * 1e3, "samples_per_s": n / wall,
+        "dct_compress": {"ms": t_dct, "algorithmic_tflop": flops / 1e12,
+                         "achieved_tflops": flops / (t_dct / 1e3) / 1e12,
+                         "frac_fp64_vector": flops / (t_dct / 1e3) / 1e12 / PEAK_TFLOPS["f64"]},
+        "kmeans_step_ms": t_k_round,
+        "kernels_ms": {k: d["avg_ms"] for k, d in kern.items()},
+        "objective_first_last": [float(o[0]), float(o[-1])],
+    }
+
+
 def run_mean(pds, r, n, p, m, steps):
     """The sample-mean estimator (Sec. IV) over the kept entries of the step
     just timed, timed on its own (not part of the step): per-kernel times from
@@ -616,6 +685,8 @@ def main():
     ap.add_argument("--no-mixture", action="store_true", help="skip the mixture K-means leg")
     ap.add_argument("--no-eigen", action="store_true", help="skip the eigen-solve timing (outside the step)")
     ap.add_argument("--mixture-only", action="store_true", help="run only the mixture K-means leg")
+    ap.add_argument("--no-dct", action="store_true", help="skip the DCT-preconditioned K-means leg")
+    ap.add_argument("--dct-only", action="store_true", help="run only the DCT-preconditioned K-means leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -637,6 +708,9 @@ def main():
         return
     if args.mixture_only:
         print(json.dumps({"mixture": run_mixture(pds, args.steps, args.warmup)}), flush=True)
+        return
+    if args.dct_only:
+        print(json.dumps({"dct": run_dct(pds, args.steps, args.warmup)}), flush=True)
         return
     name = "spiked4096_f32"
     w = synth.WORKLOADS[name]
@@ -732,6 +806,10 @@ def main():
     if not args.no_mixture:
         out["mixture"] = run_mixture(pds, max(1, min(args.steps, 3)), 1)
         log(f"mixture: {json.dumps(out['mixture'])}")
+        torch.cuda.empty_cache()
+    if not args.no_dct:
+        out["dct"] = run_dct(pds, max(1, min(args.steps, 5)), 1)
+        log(f"dct: {json.dumps(out['dct'])}")
         torch.cuda.empty_cache()
     if not args.no_batch:
         out["batch"] = run_batch(pds, max(1, min(args.steps, 5)), max(1, min(args.warmup, 2)))

@@ -20,6 +20,14 @@ the paper's public datasets are not used):
 * ``batch256_f32`` -- the batched form's 256 independent sets: n ~ U{1000..100000},
   p ~ U{128, 256, 512, 1024, 2048}, K ~ U{2..50}, gamma ~ U[0.02, 0.2], each set
   drawn like ``mixture`` with its own K centers; 20 K-means rounds.
+* ``digits784_f32`` -- stand-in for the handwritten-digit images of Sec. VII
+  (70000 images of 28 x 28 = 784 pixels, 10 classes; the dataset itself is
+  not used): each class is a template of five Gaussian blobs (width 1.3
+  pixels) placed in the central 20 x 20 pixels; a sample shifts its class
+  template by up to 2 pixels each way, scales it by U[0.7, 1.3], adds
+  N(0, 0.1^2) noise, clips to [0, 1] and zeroes pixels below 0.15 (about a
+  fifth of the pixels stay non-zero, as in the images).  p = 784 is not a
+  power of two: the paper preconditions such data with a DCT.
 * ``msel`` -- data blocks for the learned m-selector (not a workload of the
   paper): p = 1024, n = 8192, spike rank r ~ U{1..50}, lam_k = A / k with
   amplitude A log-uniform on [50, 5e4], unit noise.  The principal directions
@@ -45,10 +53,44 @@ WORKLOADS = {
                         spike_scale=20.0, spike_dof=3, dtype="f32", data_seed=1, gamma=0.05, T=20),
     "spiked4096_f32": dict(kind="spiked", n=1 << 20, p=4096, lam=tuple(50.0 / k for k in range(1, 21)),
                            dtype="f32", data_seed=2, gamma=0.1),
+    "digits784_f32": dict(kind="digits", n=70000, p=784, K=10, side=28, strokes=5, width=1.3, shift=2,
+                          noise=0.1, floor=0.15, dtype="f32", data_seed=4, gamma=0.1, T=20),
     "batch256_f32": dict(kind="batch", count=256, n=(1000, 100000), p=(128, 256, 512, 1024, 2048), K=(2, 50),
                          gamma=(0.02, 0.2), center_std=2.0, spike_prob=0.01, spike_scale=20.0, spike_dof=3,
                          dtype="f32", data_seed=3, T=20),
 }
+
+
+def digits_numpy(name="digits784_f32", n=None, with_labels=False):
+    """Rows of the digit-image stand-in (see the module notes), float32 in
+    [0, 1], drawn with numpy from the workload's data seed."""
+    w = WORKLOADS[name]
+    n = w["n"] if n is None else n
+    side, K = w["side"], w["K"]
+    rng = np.random.default_rng([w["data_seed"], 0xD161])
+    yy, xx = np.mgrid[0:side, 0:side].astype(np.float64)
+    templ = np.zeros((K, side, side))
+    for k in range(K):
+        for _ in range(w["strokes"]):
+            cy, cx = rng.uniform(4, side - 4, size=2)
+            templ[k] += np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * w["width"] ** 2))
+        templ[k] /= templ[k].max()
+    labels = rng.integers(0, K, size=n)
+    sh = rng.integers(-w["shift"], w["shift"] + 1, size=(n, 2))
+    amp = rng.uniform(0.7, 1.3, size=n)
+    X = np.empty((n, side * side), dtype=np.float32)
+    for r0 in range(0, n, 8192):
+        r1 = min(n, r0 + 8192)
+        img = np.empty((r1 - r0, side, side))
+        for i in range(r0, r1):
+            img[i - r0] = np.roll(templ[labels[i]], (sh[i, 0], sh[i, 1]), axis=(0, 1)) * amp[i]
+        img += w["noise"] * rng.standard_normal(img.shape)
+        img = np.clip(img, 0.0, 1.0)
+        img[img < w["floor"]] = 0.0
+        X[r0:r1] = img.reshape(r1 - r0, -1)
+    if with_labels:
+        return X, labels
+    return X
 
 
 def m_from_gamma(gamma, p):
