@@ -481,7 +481,7 @@ def run_mixture(pds, steps, warmup):
     reassigned = float((c2 != assign).double().mean().item())
     comp = n * (4 * p + 6 * m)
     per_round = n * (6 * m + 4)
-    t_c = kern["compress"]["avg_ms"] + kern["sample_indices"]["avg_ms"]
+    t_c = kern["compress"]["avg_ms"] + kern.get("sample_indices", {"avg_ms": 0.0})["avg_ms"]
     t_k = sum(kern[k]["avg_ms"] for k in kern if k.startswith("kmeans")) * 1.0
     t_k_round = sum(kern[k]["total_ms"] for k in kern if k.startswith("kmeans")) / (steps * T)
     del X

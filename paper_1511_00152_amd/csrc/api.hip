@@ -343,6 +343,12 @@ pds_status pds_compress(pds_plan plan, const void* X, int64_t n, int64_t ldx, ui
     if (need > 0 && (!ws || ws_bytes < need))
         return fail(PDS_E_WORKSPACE, "compress needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!dct && pds::compress_fused_ok(plan->prec, (int)plan->p, X, ldx)) {
+        e = pds::launch_compress_fused(plan->seed, (int)plan->p, (int)plan->m, reinterpret_cast<const float*>(X), n,
+                                       ldx, i0, reinterpret_cast<float*>(vals), idx, dev, s);
+        if (e != hipSuccess) return hip_fail(e, "compress (fused sampler)");
+        return PDS_OK;
+    }
     e = pds::launch_sample_indices(plan->seed, (int)plan->p, (int)plan->m, n, i0, idx, dev, s);
     if (e != hipSuccess) return hip_fail(e, "sample_indices");
     if (dct) {

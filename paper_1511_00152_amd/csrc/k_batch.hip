@@ -120,6 +120,97 @@ __global__ __launch_bounds__(64) void k_batch_compress(const BatchSet* __restric
     }
 }
 
+// Single-plan compression with the sampler fused in (FP32 values, p in
+// [512, 2048], 16-byte aligned rows): the group loop above for one data set,
+// the kept sets drawn for global sample indices i0 + r, so that idx is written
+// once, straight from the bitmaps, and never read back.
+__global__ __launch_bounds__(64) void k_compress_fused(uint64_t seed, int p, int m, int L, const float* __restrict__ X,
+                                                       int64_t n, int64_t ldx, uint64_t i0, float* __restrict__ vals,
+                                                       uint16_t* __restrict__ idx, int spw, int64_t ngroups)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    const int words = p >> 5;
+    const int stride = spw + 1;
+    uint32_t* bitmap = lds;                                      // [words][spw + 1]
+    uint32_t* negbits = bitmap + words * stride;                 // [words]
+    float* buf = reinterpret_cast<float*>(negbits + words);      // lds_pad(p - 1) + 1
+    const int lane = threadIdx.x;
+    for (int b = lane; b < (p + 255) / 256; b += 64) {
+        const u64x4 blk = sign_block(seed, (uint64_t)b);
+#pragma unroll
+        for (int w = 0; w < 8; ++w)
+            if (b * 8 + w < words)
+                negbits[b * 8 + w] = (w & 1) ? (uint32_t)(blk.w[w >> 1] >> 32) : (uint32_t)blk.w[w >> 1];
+    }
+    BatchSet S{};
+    S.X = X;
+    S.vals = vals;
+    S.idx = idx;
+    S.n = n;
+    S.ldx = ldx;
+    S.p = p;
+    S.m = m;
+    S.L = L;
+    S.seed = seed;
+    for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        __syncthreads();  // the previous group's reads of the bitmaps are done (and negbits is written)
+        for (int e = lane; e < words * stride; e += 64) bitmap[e] = 0u;
+        __syncthreads();
+        const int64_t r0 = g * (int64_t)spw;
+        const int64_t left = n - r0;
+        const int nrows = left < spw ? (int)left : spw;
+        if (spw <= 32) {
+            const int q = lane & 31;
+            floyd_bitmap_pair(seed, i0 + (uint64_t)(r0 + q), p, m, bitmap, stride, q, lane < 32 && q < nrows);
+        } else if (lane < nrows) {
+            floyd_bitmap(seed, i0 + (uint64_t)(r0 + lane), p, m, bitmap, stride, lane);
+        }
+        __syncthreads();
+        switch (L) {
+            case 8: batch_rows<8>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            case 9: batch_rows<9>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            case 10: batch_rows<10>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            default: batch_rows<11>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+        }
+    }
+}
+
+// samples per group of the fused single-plan compression (n = 2^20, FP32: at
+// p = 512 / 1024 / 2048, 0.62 / 1.05 / 2.21 ms with 32, 0.62 / 1.05 / 2.44 with
+// 64, against 0.68 / 1.25 / 2.37 for the separate sampler and transform; at
+// p = 256 the separate launches stay ahead, 0.44 against 0.45)
+constexpr int kFusedSpw = 32;
+
+bool compress_fused_ok(int prec, int p, const void* X, int64_t ldx)
+{
+    return prec != 0 && p >= 512 && p <= 2048 && (p & (p - 1)) == 0 && ((uintptr_t)X % 16 == 0) &&
+           ((ldx * 4) % 16 == 0);
+}
+
+hipError_t launch_compress_fused(uint64_t seed, int p, int m, const float* X, int64_t n, int64_t ldx, uint64_t i0,
+                                 float* vals, uint16_t* idx, const DeviceInfo& dev, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int spw = kFusedSpw;
+    const int words = p / 32;
+    const size_t lds = ((size_t)words * (spw + 1) + words) * 4 + (size_t)(lds_pad<float>(p - 1) + 1) * 4;
+    static int per_cu[12] = {0};
+    int L = 0;
+    while ((1 << L) < p) ++L;
+    if (per_cu[L] == 0) {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_compress_fused, 64, lds) != hipSuccess || b < 1) b = 4;
+        per_cu[L] = b;
+    }
+    const int64_t ngroups = (n + spw - 1) / spw;
+    int64_t grid = (int64_t)dev.cus * per_cu[L];
+    if (grid > ngroups) grid = ngroups;
+    ProfScope ps_("compress", s);
+    hipLaunchKernelGGL(k_compress_fused, dim3((unsigned)grid), dim3(64), lds, s, seed, p, m, L, X, n, ldx, i0, vals,
+                       idx, spw, ngroups);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // K-means
 // ---------------------------------------------------------------------------

@@ -38,6 +38,11 @@ hipError_t launch_compress(int prec, uint64_t seed, int p, int m, const void* X,
                            const uint16_t* idx, void* vals, void* ws, size_t ws_bytes, const DeviceInfo& dev,
                            hipStream_t s);
 size_t compress_workspace(int prec, int p, int64_t n, const DeviceInfo& dev);
+// FP32 values at p in [512, 2048] with aligned rows: sampler and transform in
+// one launch (writes idx and vals; no launch_sample_indices before it)
+bool compress_fused_ok(int prec, int p, const void* X, int64_t ldx);
+hipError_t launch_compress_fused(uint64_t seed, int p, int m, const float* X, int64_t n, int64_t ldx, uint64_t i0,
+                                 float* vals, uint16_t* idx, const DeviceInfo& dev, hipStream_t s);
 // split-BF16 matrix-core transform (p = 4096)
 bool kron_transform_ok(int p, const void* X, int64_t ldx);
 hipError_t launch_compress_kron(uint64_t seed, int m, const float* X, int64_t n, int64_t ldx, const uint16_t* idx,
