@@ -8,21 +8,20 @@
 //
 // The transform is a dense product Y = (X D) T with the table
 // T[k][j] = C[j][k] (p x p, FP64, built on the device from cospi of the exact
-// reduced angle), computed in FP64 on the vector ALUs: the FP64 matrix
-// throughput of the chip equals its FP64 vector rate, and FP64 keeps the
-// result within a few units of FP64 rounding of the definition, so the one
-// rounding of an FP32 plan is the final store.  Work per sample is p^2
+// reduced angle), computed in FP64 on the matrix cores: FP64 keeps the result
+// within a few units of FP64 rounding of the definition, so the one rounding
+// of an FP32 plan is the final store.  Work per sample is p^2
 // multiply-adds, against p log p for the Hadamard transform; at the sizes the
 // paper uses the DCT for (p = 784, tens of thousands of samples) that is a
 // few milliseconds.
 //
 // Tiling: a workgroup owns 64 samples x 64 outputs; 16 input coordinates at a
-// time are staged in LDS as FP64 (the sign applied on the way in), every
-// thread accumulating a 4 x 4 block of outputs (rows ty + 16a, columns
-// tx + 16b, so a wave's reads of one staged row hit 4 and 16 distinct
-// addresses).  The finished 64 x 64 block goes to LDS and each sample's kept
-// coordinates inside its 64 columns (a contiguous run of the ascending index
-// row, found by binary search) are written out, so Y never reaches memory.
+// time are staged in LDS as FP64 (the sign applied on the way in; the next
+// step's loads in flight meanwhile), each wave multiplying a 32 x 32 quarter
+// as 2 x 2 products of 16 x 16 x 4.  The finished 64 x 64 block goes to LDS
+// (over the staging buffers) and each sample's kept coordinates inside its 64
+// columns (a contiguous run of the ascending index row, found by binary
+// search) are written out, so Y never reaches memory.
 #include "pds_device.hpp"
 #include "pds_internal.hpp"
 
@@ -63,17 +62,28 @@ __device__ inline int lower_bound_u16(const uint16_t* __restrict__ row, int m, i
     return lo;
 }
 
+typedef double dct_d4 __attribute__((ext_vector_type(4)));
+
+// LDS of one workgroup: the staged operands during the product, then the
+// finished 64 x 64 block for the gather (the two never live together)
+struct DctStage {
+    double a[kDctTile][kDctK + 1];  // [sample][coordinate], signed x
+    double b[kDctK][kDctTile + 1];  // [coordinate][output]
+};
+union DctLds {
+    DctStage st;
+    double y[kDctTile][kDctTile + 1];
+};
+
 template <class TX, class TV>
 __global__ __launch_bounds__(256) void k_dct_compress(uint64_t seed, int p, int m, const TX* __restrict__ X,
                                                       int64_t n, int64_t ldx, const double* __restrict__ T,
                                                       const uint16_t* __restrict__ idx, TV* __restrict__ vals)
 {
-    __shared__ double As[kDctK][kDctTile + 1];  // [coordinate][sample], signed x
-    __shared__ double Bs[kDctK][kDctTile];      // [coordinate][output]
-    __shared__ double Ys[kDctTile][kDctTile + 1];
+    __shared__ DctLds L;
     __shared__ uint32_t neg[kDctMaxP / 32];
     const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
+    const int lane = tid & 63, wave = tid >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * kDctTile;
     const int j0 = blockIdx.y * kDctTile;
 
@@ -86,59 +96,72 @@ __global__ __launch_bounds__(256) void k_dct_compress(uint64_t seed, int p, int 
             neg[b * 8 + 2 * w + 1] = (uint32_t)(blk.w[w] >> 32);
         }
     }
-    __syncthreads();
 
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-
-    // staging assignment: X tile element (sample as, coordinate ak..ak+3),
-    // table tile element (coordinate bk, outputs bj..bj+3)
+    // staging assignment: x of sample as, coordinates ak .. ak + 3; table
+    // row bk, outputs bj .. bj + 3.  The next step's operands are loaded into
+    // registers while the matrix cores work on the current one.
     const int as = tid >> 2, ak = (tid & 3) * 4;
     const int bk = tid >> 4, bj = (tid & 15) * 4;
     const int64_t xi = i0 + as;
     const TX* xrow = X + (xi < n ? xi : 0) * ldx;
-    for (int k0 = 0; k0 < p; k0 += kDctK) {
+    TX xv[4];
+    double tv[4];
+    auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int k = k0 + ak + q;
-            double v = 0.0;
-            if (xi < n && k < p) {
-                v = (double)xrow[k];
-                if ((neg[k >> 5] >> (k & 31)) & 1u) v = -v;
-            }
-            As[ak + q][as] = v;
+            xv[q] = (xi < n && k < p) ? xrow[k] : (TX)0;
+            const int kb = k0 + bk, j = j0 + bj + q;
+            tv[q] = (kb < p && j < p) ? T[(int64_t)kb * p + j] : 0.0;
         }
-        {
-            const int k = k0 + bk;
+    };
+    load(0);
+
+    // wave (wr, wc) owns rows 32 wr .. +32 and outputs 32 wc .. +32 of the
+    // block: 2 x 2 products of 16 x 16 on v_mfma_f64_16x16x4f64 (operand lane
+    // l: row / column l mod 16, k = l div 16; result register r of lane l:
+    // row l div 16 + 4 r, column l mod 16)
+    const int wr = wave >> 1, wc = wave & 1;
+    const int li = lane & 15, lk = lane >> 4;
+    dct_d4 acc[2][2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int j = j0 + bj + q;
-                Bs[bk][bj + q] = (k < p && j < p) ? T[(int64_t)k * p + j] : 0.0;
-            }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = (dct_d4){0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < p; k0 += kDctK) {
+        __syncthreads();  // the previous step's operand reads are done (and neg is written)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + ak + q;
+            double v = (double)xv[q];
+            if (k < p && ((neg[k >> 5] >> (k & 31)) & 1u)) v = -v;
+            L.st.a[as][ak + q] = v;
+            L.st.b[bk][bj + q] = tv[q];
         }
         __syncthreads();
+        if (k0 + kDctK < p) load(k0 + kDctK);
 #pragma unroll
-        for (int kk = 0; kk < kDctK; ++kk) {
-            double a[4], b[4];
+        for (int kk = 0; kk < kDctK; kk += 4) {
+            double av[2], bv[2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[kk][ty + 16 * q];
-                b[q] = Bs[kk][tx + 16 * q];
-            }
+            for (int r = 0; r < 2; ++r) av[r] = L.st.a[32 * wr + 16 * r + li][kk + lk];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 2; ++c) bv[c] = L.st.b[kk + lk][32 * wc + 16 * c + li];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[c], acc[r][c], 0, 0, 0);
         }
-        __syncthreads();
     }
+    __syncthreads();  // every wave is done with the staged operands
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Ys[ty + 16 * r][tx + 16 * c] = acc[r][c];
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) L.y[32 * wr + 16 * r + lk + 4 * q][32 * wc + 16 * c + li] = acc[r][c][q];
     __syncthreads();
 
     // kept coordinates of each sample inside [j0, j0 + 64): four threads per sample
@@ -149,7 +172,7 @@ __global__ __launch_bounds__(256) void k_dct_compress(uint64_t seed, int p, int 
         const int t0 = lower_bound_u16(row, m, j0);
         const int t1 = lower_bound_u16(row, m, j0 + kDctTile);
         TV* out = vals + i * (int64_t)m;
-        for (int t = t0 + sub; t < t1; t += 4) out[t] = (TV)Ys[s][(int)row[t] - j0];
+        for (int t = t0 + sub; t < t1; t += 4) out[t] = (TV)L.y[s][(int)row[t] - j0];
     }
 }
 
@@ -186,8 +209,10 @@ hipError_t launch_dct_compress(int prec, uint64_t seed, int p, int m, const void
 }
 
 // mu = (C D)^T mu' = D C^T mu': out[k][j] = D_j sum_i C[i][j] mu'[k][i], FP64,
-// one thread per (center, coordinate); the coefficients from cospi directly
-// (K p^2 evaluations, small next to the compression).
+// one thread per (center, coordinate).  C[i][j] = s_i cos(i t), t = pi (2j + 1)
+// / (2p): the cosines advance by a rotation through t (two FMAs per term),
+// restarted from cospi / sinpi of the exactly reduced angle every 32 terms, so
+// no coefficient carries more than a few dozen roundings.
 __global__ __launch_bounds__(256) void k_dct_unmix(uint64_t seed, int p, const double* __restrict__ cpre,
                                                    double* __restrict__ cout)
 {
@@ -197,11 +222,24 @@ __global__ __launch_bounds__(256) void k_dct_unmix(uint64_t seed, int p, const d
     for (int i = threadIdx.x; i < p; i += 256) mu[i] = cpre[(int64_t)k * p + i];
     __syncthreads();
     if (j >= p) return;
-    double sum = 0.0;
-    for (int i = 0; i < p; ++i) sum = fma(dct_coef(p, i, j), mu[i], sum);
+    const int64_t a = 2 * (int64_t)j + 1;
+    const double ct = cospi((double)a / (2.0 * p)), st = sinpi((double)a / (2.0 * p));
+    double sum = 0.0;  // sum over i >= 1 of cos(i t) mu_i
+    for (int b = 1; b < p; b += 32) {
+        const double arg = (double)((a * b) % (4 * (int64_t)p)) / (2.0 * p);
+        double c = cospi(arg), s = sinpi(arg);
+        const int e = (b + 32 < p) ? b + 32 : p;
+        for (int i = b; i < e; ++i) {
+            sum = fma(c, mu[i], sum);
+            const double cn = c * ct - s * st;
+            s = fma(s, ct, c * st);
+            c = cn;
+        }
+    }
+    const double v = sqrt(2.0 / p) * sum + sqrt(1.0 / p) * mu[0];
     const u64x4 blk = sign_block(seed, (uint64_t)(j >> 8));
     const uint64_t w = blk.w[(j >> 6) & 3];
-    cout[(int64_t)k * p + j] = ((w >> (j & 63)) & 1ull) ? -sum : sum;
+    cout[(int64_t)k * p + j] = ((w >> (j & 63)) & 1ull) ? -v : v;
 }
 
 hipError_t launch_dct_unmix(uint64_t seed, int p, const double* cpre, int K, double* cout, hipStream_t s)

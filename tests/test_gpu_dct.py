@@ -115,9 +115,11 @@ def test_dct_compress_keeps_the_same_sets_as_hadamard():
 
 @pytest.mark.parametrize("p", [7, 100, 784, 4096])
 def test_dct_unmix_matches_oracle_and_inverts(p):
-    """unmix = D C^T against the oracle (error bound as for the forward
-    transform, from ||mu'||), and at m = p, compress then unmix of every row
-    returns the rows."""
+    """unmix = D C^T against the oracle, and at m = p, compress then unmix of
+    every row returns the rows.  The unmixing advances its cosines by a
+    rotation restarted every 32 terms, so each coefficient carries at most
+    about 64 roundings more than the forward table: bound (4p + 128) u ||mu'||
+    (twice that plus 4p u for the round trip)."""
     log(f"dct unmix p={p}")
     rng = np.random.default_rng(p)
     K = 5
@@ -125,14 +127,15 @@ def test_dct_unmix_matches_oracle_and_inverts(p):
     plan = dct_plan(p, p, 21, "f64")
     out = pds.unmix(plan, to_dev(cpre)).cpu().numpy()
     o = ref.unmix_dct(21, cpre)
-    bound = 4 * p * U64 * np.linalg.norm(cpre, axis=1, keepdims=True)
+    bound = (4 * p + 128) * U64 * np.linalg.norm(cpre, axis=1, keepdims=True)
+    log(f"    unmix: worst delta / bound = {np.max(np.abs(out - o) / bound):.3f}")
     assert np.all(np.abs(out - o) <= bound)
     n = 37
     X = rows(n, p, 5, np.float64)
     vals, idx = pds.compress(plan, to_dev(X))
     assert np.array_equal(idx.cpu().numpy(), np.tile(np.arange(p), (n, 1)))
     back = pds.unmix(plan, vals).cpu().numpy()
-    assert np.all(np.abs(back - X) <= 8 * p * U64 * np.linalg.norm(X, axis=1, keepdims=True))
+    assert np.all(np.abs(back - X) <= (12 * p + 256) * U64 * np.linalg.norm(X, axis=1, keepdims=True))
 
 
 @pytest.mark.parametrize("prec,gram", [("f64", "dense"), ("f32", "dense"), ("f32", "sparse"), ("split", "dense")])
