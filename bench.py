@@ -388,7 +388,7 @@ def run_batch(pds, steps, warmup, single_baseline=True):
 def run_mixture(pds, steps, warmup):
     """Sparsified K-means on the mixture workload (n = 2^20, p = 1024, K = 10,
     m = 51, T = 20): one compression, K-means++ seeding on the compressed
-    samples and T kmeans_step calls per step (Alg. 1)."""
+    samples and T K-means rounds per step in one pds_kmeans_run call (Alg. 1)."""
     import torch
 
     import synth
@@ -403,7 +403,7 @@ def run_mixture(pds, steps, warmup):
     plan = pds.Plan(p, m, seed=0, prec=pds.PDS_F32)
     vals = torch.empty((n, m), dtype=torch.float32, device="cuda")
     idx = torch.empty((n, m), dtype=torch.int16, device="cuda")
-    ws = plan.workspace(pds.PDS_OP_KMEANS, n, K, device="cuda")
+    ws = plan.workspace(pds.PDS_OP_KMEANS_RUN, n, K, device="cuda")
     ca = torch.zeros((K, p), dtype=torch.float64, device="cuda")
     cb = torch.empty_like(ca)
     assign = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -414,10 +414,8 @@ def run_mixture(pds, steps, warmup):
     def step():
         pds.compress(plan, X, vals=vals, idx=idx)
         pds.kmeanspp(plan, vals, idx, K, centers=ca, chosen=chosen, ws=ws_pp)
-        a, c = ca, cb
-        for r in range(T):
-            pds.kmeans_step(plan, vals, idx, a, out=c, assign=assign, objective=objs[r:r + 1], ws=ws)
-            a, c = c, a
+        # T rounds of Alg. 1 in one call (the same rounds as T kmeans_step calls)
+        pds.kmeans_run(plan, vals, idx, ca, T, out=cb, assign=assign, objectives=objs, ws=ws)
 
     for _ in range(warmup):
         step()
@@ -434,7 +432,7 @@ def run_mixture(pds, steps, warmup):
     o = objs.cpu().numpy()
     # Alg. 2's extra pass over the original rows after the one-pass run:
     # nearest one-pass center (original domain) and exact cluster means
-    mu_hat = pds.unmix(plan, ca if T % 2 == 0 else cb)  # the last round's centers (rounds alternate ca/cb)
+    mu_hat = pds.unmix(plan, cb)  # the last round's centers
     ws2 = plan.workspace(pds.PDS_OP_KMEANS2, n, K, device="cuda")
     mu2 = torch.empty_like(mu_hat)
     c2 = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -486,7 +484,7 @@ def run_mixture(pds, steps, warmup):
     t_k_round = sum(kern[k]["total_ms"] for k in kern if k.startswith("kmeans")) / (steps * T)
     del X
     return {
-        "workload": f"{name}: n={n}, p={p}, m={m}, K={K}, T={T}; step = compress + K-means++ seeding + T kmeans_step",
+        "workload": f"{name}: n={n}, p={p}, m={m}, K={K}, T={T}; step = compress + K-means++ seeding + T K-means rounds (kmeans_run)",
         "seeding_ms": sum(kern[k]["total_ms"] for k in kern if k.startswith("kmpp")) / steps,
         "ms_per_step": wall * 1e3, "samples_per_s": n / wall,
         "compress_ms": t_c, "compress_frac_hbm": comp / (t_c / 1e3) / 1e9 / PEAK_HBM_GBS,
@@ -508,7 +506,7 @@ def run_dct(pds, steps, warmup):
     """Sparsified K-means with the DCT preconditioner (Sec. VII runs it on
     70000 digit images of p = 784 pixels; here the seeded stand-in
     digits784_f32 of that shape): one DCT compression (gamma = 0.1), K-means++
-    seeding and T = 20 kmeans_step calls per step, then the unmixing.  The
+    seeding and T = 20 K-means rounds (one pds_kmeans_run call) per step, then the unmixing.  The
     DCT transform is an FP64 dense product, 2 p^2 flops per sample, priced
     against the FP64 vector peak."""
     import torch
@@ -525,7 +523,7 @@ def run_dct(pds, steps, warmup):
     vals = torch.empty((n, m), dtype=torch.float32, device="cuda")
     idx = torch.empty((n, m), dtype=torch.int16, device="cuda")
     ws_c = plan.workspace(pds.PDS_OP_COMPRESS, n, device="cuda")
-    ws = plan.workspace(pds.PDS_OP_KMEANS, n, K, device="cuda")
+    ws = plan.workspace(pds.PDS_OP_KMEANS_RUN, n, K, device="cuda")
     ws_pp = plan.workspace(pds.PDS_OP_KMEANSPP, n, device="cuda")
     ca = torch.zeros((K, p), dtype=torch.float64, device="cuda")
     cb = torch.empty_like(ca)
@@ -537,11 +535,8 @@ def run_dct(pds, steps, warmup):
     def step():
         pds.compress(plan, X, vals=vals, idx=idx, ws=ws_c)
         pds.kmeanspp(plan, vals, idx, K, centers=ca, chosen=chosen, ws=ws_pp)
-        a, c = ca, cb
-        for r in range(T):
-            pds.kmeans_step(plan, vals, idx, a, out=c, assign=assign, objective=objs[r:r + 1], ws=ws)
-            a, c = c, a
-        pds.unmix(plan, a, out=mu)
+        pds.kmeans_run(plan, vals, idx, ca, T, out=cb, assign=assign, objectives=objs, ws=ws)
+        pds.unmix(plan, cb, out=mu)
 
     for _ in range(warmup):
         step()
@@ -562,7 +557,7 @@ def run_dct(pds, steps, warmup):
     del X
     return {
         "workload": f"{name}: n={n}, p={p}, m={m}, K={K}, T={T}, FP32 plan with the DCT preconditioner; "
-                    "step = compress + K-means++ seeding + T kmeans_step + unmix",
+                    "step = compress + K-means++ seeding + T K-means rounds (kmeans_run) + unmix",
         "ms_per_step": wall * 1e3, "samples_per_s": n / wall,
         "dct_compress": {"ms": t_dct, "algorithmic_tflop": flops / 1e12,
                          "achieved_tflops": flops / (t_dct / 1e3) / 1e12,

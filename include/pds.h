@@ -88,7 +88,8 @@ typedef enum {
     PDS_OP_KMEANS2 = 3,
     PDS_OP_MEAN = 4,
     PDS_OP_KMEANSPP = 5,
-    PDS_OP_KMEANS_BEST = 6
+    PDS_OP_KMEANS_BEST = 6,
+    PDS_OP_KMEANS_RUN = 7
 } pds_op;
 
 typedef struct pds_plan_s* pds_plan;
@@ -290,6 +291,23 @@ pds_status pds_kmeanspp(pds_plan plan, const void* vals, const uint16_t* idx, in
 pds_status pds_kmeans_best(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, int32_t T,
                            int32_t R, double* centers_out, int32_t* assign_out, double* objectives, int32_t* best,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* T iterations of sparsified K-means (Alg. 1, the loop; Sec. VI) from
+ * centers_in: the same rounds as T successive pds_kmeans_step calls, each
+ * round reading the previous round's centers, with results equal to theirs
+ * bit for bit.  After the first round the rounds reuse the per-workgroup
+ * fixed-point scales the first one took from the compressed values (they are
+ * the same values), which saves one read of the values per round.
+ *   centers_out: device, K x p doubles, the last round's centers (must not
+ *   alias centers_in); assign: device, n int32, the last round's assignments;
+ *   objectives: device, T doubles, round t's objective (eq. CK_means) with the
+ *   centers entering that round.  ws: device, >= pds_workspace_size(KMEANS_RUN,
+ *   n, K) (the step's workspace and one center buffer).
+ * Errors: PDS_E_ARG (null pointers with n > 0, n < 0, K out of [1, 1024],
+ * T < 1, aliasing), PDS_E_WORKSPACE. */
+pds_status pds_kmeans_run(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, int32_t T,
+                          const double* centers_in, double* centers_out, int32_t* assign, double* objectives, void* ws,
+                          size_t ws_bytes, void* stream);
 
 /* One iteration of sparsified K-means (Sec. VI; Alg. 1, loop body) on
  * compressed data, centers in the preconditioned domain:

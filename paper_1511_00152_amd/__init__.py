@@ -15,13 +15,13 @@ the current HIP device; every call enqueues the library's kernels on
 import ctypes
 
 from ._lib import (PDS_E_ARG, PDS_E_HIP, PDS_E_M, PDS_E_UNSUPPORTED, PDS_E_WORKSPACE, PDS_EXPLAINED_WS_BYTES, PDS_F32,
-                   PDS_F64, PDS_GRAM_AUTO, PDS_GRAM_DENSE, PDS_GRAM_SPARSE, PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_KMEANS_BEST,
+                   PDS_F64, PDS_GRAM_AUTO, PDS_GRAM_DENSE, PDS_GRAM_SPARSE, PDS_OK, PDS_OP_COMPRESS, PDS_OP_COVARIANCE, PDS_OP_KMEANS, PDS_OP_KMEANS2, PDS_OP_KMEANS_BEST, PDS_OP_KMEANS_RUN,
                    PDS_OP_KMEANSPP, PDS_OP_MEAN, PDS_SPLIT_BF16, PDS_TRANSFORM_DCT, PDS_TRANSFORM_HADAMARD, PDS_DCT_MAX_P,
                    EXPORTS, PdsError, check, lib)
 
 __all__ = [
     "Plan", "compress", "pad_rows", "covariance", "CovarianceAccumulator", "sample_mean", "kmeanspp", "kmeans_best",
-    "kmeans_step", "unmix", "kmeans_2pass", "sparsified_kmeans", "top_eigenvalues", "principal_components",
+    "kmeans_step", "kmeans_run", "unmix", "kmeans_2pass", "sparsified_kmeans", "top_eigenvalues", "principal_components",
     "explained_variance",
     "PdsError", "PDS_F64", "PDS_F32", "PDS_SPLIT_BF16", "PDS_GRAM_AUTO", "PDS_GRAM_DENSE", "PDS_GRAM_SPARSE", "lib",
     "PDS_TRANSFORM_HADAMARD", "PDS_TRANSFORM_DCT", "PDS_DCT_MAX_P", "EXPORTS",
@@ -344,6 +344,29 @@ def kmeans_step(plan: Plan, vals, idx, centers, out=None, assign=None, objective
     return out, assign, objective
 
 
+def kmeans_run(plan: Plan, vals, idx, centers, T: int, out=None, assign=None, objectives=None, ws=None):
+    """T sparsified Lloyd rounds from `centers` (Alg. 1's loop, pds_kmeans_run);
+    returns (centers after the last round, its assign int32, objectives (T,)
+    FP64, round t's with the centers entering it)."""
+    import torch
+
+    n = vals.shape[0]
+    K = centers.shape[0]
+    dev = vals.device
+    if out is None:
+        out = torch.empty_like(centers)
+    if assign is None:
+        assign = torch.empty(n, dtype=torch.int32, device=dev)
+    if objectives is None:
+        objectives = torch.empty(int(T), dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = plan.workspace(PDS_OP_KMEANS_RUN, n, K, device=dev)
+    check(lib().pds_kmeans_run(plan.handle, _ptr(vals), _ptr(idx), n, K, int(T), _ptr(centers), _ptr(out),
+                               _ptr(assign), _ptr(objectives), _ptr(ws), ws.numel() if ws is not None else 0,
+                               _stream()), "pds_kmeans_run")
+    return out, assign, objectives
+
+
 def unmix(plan: Plan, centers_pre, out=None):
     """mu = (H D)^T mu' (DCT plans: (C D)^T mu') for each row of centers_pre (FP64)."""
     import torch
@@ -393,14 +416,6 @@ def sparsified_kmeans(plan: Plan, X, init_centers, iterations: int, starts: int 
             return {"vals": vals, "idx": idx, "assign": assign, "centers_pre": c, "centers": unmix(plan, c),
                     "objectives": objs, "best": best}
         init_centers, _ = kmeanspp(plan, vals, idx, K)
-    K = init_centers.shape[0]
-    ws = plan.workspace(PDS_OP_KMEANS, X.shape[0], K, device=X.device)
-    a = init_centers.clone()
-    b = torch.empty_like(a)
-    assign = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
-    objs = torch.empty(iterations, dtype=torch.float64, device=X.device)
-    for t in range(iterations):
-        kmeans_step(plan, vals, idx, a, out=b, assign=assign, objective=objs[t:t + 1], ws=ws)
-        a, b = b, a
+    a, assign, objs = kmeans_run(plan, vals, idx, init_centers, iterations)
     return {"vals": vals, "idx": idx, "assign": assign, "centers_pre": a, "centers": unmix(plan, a),
             "objectives": objs}

@@ -36,13 +36,14 @@ PDS_OP_KMEANS2 = 3
 PDS_OP_MEAN = 4
 PDS_OP_KMEANSPP = 5
 PDS_OP_KMEANS_BEST = 6
+PDS_OP_KMEANS_RUN = 7
 PDS_EXPLAINED_WS_BYTES = 16384
 PDS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # every entry point declared in include/pds.h
 EXPORTS = (
     "pds_plan_create", "pds_plan_create_dct", "pds_plan_transform", "pds_plan_destroy", "pds_plan_set_gram", "pds_plan_gram", "pds_signs", "pds_workspace_size", "pds_covariance_acc_size",
-    "pds_compress", "pds_covariance", "pds_kmeans_step", "pds_kmeans_step_noalloc", "pds_unmix", "pds_kmeans_2pass", "pds_sample_mean", "pds_explained_variance", "pds_kmeanspp", "pds_kmeans_best", "pds_pad_rows", "pds_profile_enable", "pds_profile_report",
+    "pds_compress", "pds_covariance", "pds_kmeans_step", "pds_kmeans_run", "pds_kmeans_step_noalloc", "pds_unmix", "pds_kmeans_2pass", "pds_sample_mean", "pds_explained_variance", "pds_kmeanspp", "pds_kmeans_best", "pds_pad_rows", "pds_profile_enable", "pds_profile_report",
     "pds_last_error", "pds_version",
     "pds_row_moments", "pds_frob_diff", "pds_msel_workspace_size", "pds_msel_label", "pds_msel_features",
     "pds_mlp_param_count", "pds_mlp_forward", "pds_mlp_backward", "pds_mlp_adam", "pds_mlp_pack_bf16",
@@ -97,6 +98,7 @@ def lib():
     L.pds_compress.argtypes = [P, P, i64, i64, u64, P, P, P, sz, P]
     L.pds_covariance.argtypes = [P, P, P, i64, P, i32, i64, P, P, sz, P]
     L.pds_kmeans_step.argtypes = [P, P, P, i64, i32, P, P, P, P, P, sz, P]
+    L.pds_kmeans_run.argtypes = [P, P, P, i64, i32, i32, P, P, P, P, P, sz, P]
     L.pds_kmeans_step_noalloc.argtypes = [P, P, P, i64, i32, P, P, P, P, P]
     L.pds_unmix.argtypes = [P, P, i32, P, P]
     L.pds_kmeans_2pass.argtypes = [P, P, i64, i64, i32, P, P, P, P, P, sz, P]

@@ -279,6 +279,7 @@ pds_status pds_signs(pds_plan plan, int8_t* D_host)
 }
 
 static size_t kmeans_best_workspace(int prec, int p, int m, int64_t n, int K, const pds::DeviceInfo& dev);
+static size_t kmeans_run_workspace(int prec, int p, int m, int64_t n, int K, const pds::DeviceInfo& dev);
 
 pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, size_t* bytes)
 {
@@ -312,6 +313,10 @@ pds_status pds_workspace_size(pds_plan plan, int32_t op, int64_t n, int32_t K, s
         case PDS_OP_KMEANS_BEST:
             if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
             *bytes = kmeans_best_workspace(plan->prec, p, m, n, K, dev);
+            return PDS_OK;
+        case PDS_OP_KMEANS_RUN:
+            if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
+            *bytes = kmeans_run_workspace(plan->prec, p, m, n, K, dev);
             return PDS_OK;
         default:
             return fail(PDS_E_ARG, "unknown op %d", (int)op);
@@ -478,6 +483,12 @@ static size_t kmeans_best_workspace(int prec, int p, int m, int64_t n, int K, co
            2 * al256((size_t)K * p * sizeof(double)) + al256((size_t)n * sizeof(int32_t));
 }
 
+// Workspace of pds_kmeans_run: the K-means step's and one center buffer.
+static size_t kmeans_run_workspace(int prec, int p, int m, int64_t n, int K, const pds::DeviceInfo& dev)
+{
+    return al256(pds::kmeans_workspace(prec, p, m, n, K, dev)) + al256((size_t)K * p * sizeof(double));
+}
+
 pds_status pds_kmeans_best(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, int32_t T,
                            int32_t R, double* centers_out, int32_t* assign_out, double* objectives, int32_t* best,
                            void* ws, size_t ws_bytes, void* stream)
@@ -513,8 +524,9 @@ pds_status pds_kmeans_best(pds_plan plan, const void* vals, const uint16_t* idx,
         double* a = ca;
         double* c = cb;
         for (int t = 0; t < T; ++t) {
+            // after the first round the workspace holds this data's per-workgroup scales
             e = pds::launch_kmeans_step(plan->prec, p, m, vals, idx, n, K, a, c, asg,
-                                        objectives + (int64_t)r * T + t, km_ws, km_bytes, dev, s);
+                                        objectives + (int64_t)r * T + t, km_ws, km_bytes, dev, s, r > 0 || t > 0);
             if (e != hipSuccess) return hip_fail(e, "kmeans_best round");
             std::swap(a, c);
         }
@@ -545,6 +557,41 @@ pds_status pds_kmeans_step(pds_plan plan, const void* vals, const uint16_t* idx,
     e = pds::launch_kmeans_step(plan->prec, (int)plan->p, (int)plan->m, vals, idx, n, K, centers_in, centers_out,
                                 assign, objective, ws, ws_bytes, dev, s);
     if (e != hipSuccess) return hip_fail(e, "kmeans_step");
+    return PDS_OK;
+}
+
+pds_status pds_kmeans_run(pds_plan plan, const void* vals, const uint16_t* idx, int64_t n, int32_t K, int32_t T,
+                          const double* centers_in, double* centers_out, int32_t* assign, double* objectives, void* ws,
+                          size_t ws_bytes, void* stream)
+{
+    if (pds_status st = check_plan(plan)) return st;
+    if (n < 0) return fail(PDS_E_ARG, "n < 0");
+    if (K < 1 || K > 1024) return fail(PDS_E_ARG, "K = %d: must be in [1, 1024]", (int)K);
+    if (T < 1) return fail(PDS_E_ARG, "T = %d < 1", (int)T);
+    if (n == 0) return PDS_OK;
+    if (!vals || !idx || !centers_in || !centers_out || !assign || !objectives)
+        return fail(PDS_E_ARG, "vals, idx, centers_in, centers_out, assign and objectives must be non-NULL");
+    if (centers_in == centers_out) return fail(PDS_E_ARG, "centers_in and centers_out must not alias");
+    pds::DeviceInfo dev;
+    hipError_t e = pds::device_info(dev);
+    if (e != hipSuccess) return hip_fail(e, "pds_kmeans_run");
+    const int p = (int)plan->p, m = (int)plan->m;
+    const size_t km_bytes = pds::kmeans_workspace(plan->prec, p, m, n, K, dev);
+    const size_t need = kmeans_run_workspace(plan->prec, p, m, n, K, dev);
+    if (!ws || ws_bytes < need)
+        return fail(PDS_E_WORKSPACE, "kmeans_run needs %zu workspace bytes, got %zu", need, ws ? ws_bytes : (size_t)0);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+    double* tmp = reinterpret_cast<double*>(w + al256(km_bytes));
+    const double* in = centers_in;
+    for (int t = 0; t < T; ++t) {
+        // rounds alternate between the two buffers so that the last one writes centers_out
+        double* out = ((T - 1 - t) % 2 == 0) ? centers_out : tmp;
+        e = pds::launch_kmeans_step(plan->prec, p, m, vals, idx, n, K, in, out, assign, objectives + t, w, km_bytes,
+                                    dev, s, t > 0);
+        if (e != hipSuccess) return hip_fail(e, "kmeans_run round");
+        in = out;
+    }
     return PDS_OK;
 }
 

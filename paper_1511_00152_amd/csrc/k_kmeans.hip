@@ -121,12 +121,31 @@ __device__ inline float block_max_f32(float v, float* red)
 }
 
 // FP64 distance in the oracle's order (ascending kept coordinate, fma).
+// Eight entries' loads (values, coordinates, then the center gathers) are
+// issued together before their multiply-adds, which keep that order.
 template <typename T>
 __device__ inline double dist_f64(const T* __restrict__ v, const uint16_t* __restrict__ ix, int m,
                                   const double* __restrict__ c)
 {
     double d = 0.0;
-    for (int a = 0; a < m; ++a) {
+    int a = 0;
+    for (; a + 8 <= m; a += 8) {
+        double xv[8], cv[8];
+        int iv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            xv[e] = (double)v[a + e];
+            iv[e] = ix[a + e];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cv[e] = c[iv[e]];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const double diff = xv[e] - cv[e];
+            d = fma(diff, diff, d);
+        }
+    }
+    for (; a < m; ++a) {
         double diff = (double)v[a] - c[ix[a]];
         d = fma(diff, diff, d);
     }
@@ -154,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_kmeans_assign(const T* __restrict__ vals
                                                               int64_t* __restrict__ rlist,
                                                               uint32_t* __restrict__ rcount,
                                                               uint64_t* __restrict__ wvmax,
-                                                              unsigned long long* __restrict__ gmax)
+                                                              unsigned long long* __restrict__ gmax, int reuse)
 {
     constexpr int WS = km_words<T>();
     extern __shared__ __align__(16) unsigned char smem[];
@@ -180,18 +199,23 @@ __global__ __launch_bounds__(NT) void k_kmeans_assign(const T* __restrict__ vals
             cnts[e] = 0u;
         }
         for (int64_t e = tid; e < KP * WS; e += NT) sums[e] = 0ull;
-        // this workgroup's scale: the largest |value| of its own samples
+        // this workgroup's scale: the largest |value| of its own samples (or,
+        // with reuse, the one an earlier round of the same call recorded)
         double vm = 0.0;
-        const T* vb = vals + i0 * (int64_t)m;
-        const int64_t cnt = (i1 > i0 ? i1 - i0 : 0) * (int64_t)m;
-        for (int64_t e = tid; e < cnt; e += NT) vm = fmax(vm, fabs((double)vb[e]));
-        for (int off = 32; off > 0; off >>= 1) vm = fmax(vm, __shfl_down(vm, off, 64));
-        if ((tid & 63) == 0) red_d[tid >> 6] = vm;
-        __syncthreads();
-        vm = red_d[0];
-        for (int w = 1; w < NT / 64; ++w) vm = fmax(vm, red_d[w]);
+        if (reuse) {
+            vm = __longlong_as_double((long long)wvmax[blockIdx.x]);
+        } else {
+            const T* vb = vals + i0 * (int64_t)m;
+            const int64_t cnt = (i1 > i0 ? i1 - i0 : 0) * (int64_t)m;
+            for (int64_t e = tid; e < cnt; e += NT) vm = fmax(vm, fabs((double)vb[e]));
+            for (int off = 32; off > 0; off >>= 1) vm = fmax(vm, __shfl_down(vm, off, 64));
+            if ((tid & 63) == 0) red_d[tid >> 6] = vm;
+            __syncthreads();
+            vm = red_d[0];
+            for (int w = 1; w < NT / 64; ++w) vm = fmax(vm, red_d[w]);
+        }
         if (tid == 0) {
-            wvmax[blockIdx.x] = dbits(vm);
+            if (!reuse) wvmax[blockIdx.x] = dbits(vm);
             atomicMax(gmax, (unsigned long long)dbits(vm));
         }
         F = km_F<T>(km_ev(dbits(vm)), km_lc(per_wg));
@@ -436,7 +460,7 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     const float* __restrict__ vals, const uint16_t* __restrict__ idx, int64_t n, int m, int p, int K,
     const double* __restrict__ cin, int64_t per_wg, int32_t* __restrict__ assign, int64_t* __restrict__ psum,
     uint32_t* __restrict__ pcnt, uint64_t* __restrict__ wvmax, unsigned long long* __restrict__ gmax,
-    double* __restrict__ dist, int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount)
+    double* __restrict__ dist, int64_t* __restrict__ rlist, uint32_t* __restrict__ rcount, int reuse)
 {
     constexpr int G = kKmLdsThreads / W;  // groups per workgroup
     constexpr int AHEAD = (E >= 16) ? 1 : 2;  // samples whose first entries are in flight
@@ -455,9 +479,12 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     int64_t i1 = i0 + per_wg;
     if (i1 > n) i1 = n;
     // the fixed-point scale of this workgroup's sums: the largest |value| of
-    // its own samples (kept in wvmax for the update)
+    // its own samples (kept in wvmax for the update; with reuse, the one an
+    // earlier round of the same call recorded there)
     float vm = 0.0f;
-    {
+    if (reuse) {
+        vm = (float)__longlong_as_double((long long)wvmax[blockIdx.x]);
+    } else {
         const float* vb = vals + i0 * (int64_t)m;
         const int64_t cnt = (i1 > i0 ? i1 - i0 : 0) * (int64_t)m;
 #pragma unroll 4
@@ -475,7 +502,7 @@ __global__ __launch_bounds__(kKmLdsThreads) void k_kmeans_assign_coop(
     cmax = block_max_f32<kKmLdsThreads>(cmax, red_f);
     vm = block_max_f32<kKmLdsThreads>(vm, red_f);
     if (tid == 0) {
-        wvmax[blockIdx.x] = dbits((double)vm);
+        if (!reuse) wvmax[blockIdx.x] = dbits((double)vm);
         atomicMax(gmax, (unsigned long long)dbits((double)vm));
     }
     const int fx = km_F<float>(km_ev(dbits((double)vm)), km_lc(per_wg));
@@ -746,7 +773,7 @@ size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceIn
 template <typename T>
 static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const uint16_t* idx, int64_t n, int K,
                             const double* cin, double* cout, int32_t* assign, double* objective, void* ws,
-                            size_t ws_bytes, const DeviceInfo& dev, hipStream_t s)
+                            size_t ws_bytes, const DeviceInfo& dev, hipStream_t s, bool reuse)
 {
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     unsigned long long* psum = reinterpret_cast<unsigned long long*>(w);
@@ -799,7 +826,7 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
         ProfScope ps_("kmeans_assign", s);
         hipLaunchKernelGGL((k_kmeans_assign<T, true, kKmThreads>), dim3(k.nwg), dim3(kKmThreads), 0, s, vals, idx, n,
                            m, p, K, cin, cT, k.per_wg, assign, psum, pcnt, gsum, gcnt, dist, rlist, rcount, wvmax,
-                           gmax);
+                           gmax, 0);
     } else {
         if constexpr (sizeof(T) == 4) {
             if (k.coop) {
@@ -834,7 +861,7 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
     case Q:                                                                                                    \
         hipLaunchKernelGGL((k_kmeans_assign_coop<W_, E_, Q>), dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s, vals, idx, \
                            n, m, p, K, cin, k.per_wg, assign, reinterpret_cast<int64_t*>(psum), pcnt, wvmax, gmax,   \
-                           dist, rlist, rcount);                                                               \
+                           dist, rlist, rcount, reuse ? 1 : 0);                                                \
         break;
                     if (m <= 64) {
                         switch ((K + 3) / 4) {
@@ -873,7 +900,8 @@ static hipError_t km_launch(const KmPlan& k, int p, int m, const T* vals, const 
         ProfScope ps_("kmeans_assign", s);
         hipLaunchKernelGGL((k_kmeans_assign<T, false, kKmLdsThreads>), dim3(k.nwg), dim3(kKmLdsThreads), k.lds, s,
                            vals, idx, n, m, p, K, cin, (const T*)nullptr, k.per_wg, assign, psum, pcnt,
-                           (unsigned long long*)nullptr, (uint32_t*)nullptr, dist, rlist, rcount, wvmax, gmax);
+                           (unsigned long long*)nullptr, (uint32_t*)nullptr, dist, rlist, rcount, wvmax, gmax,
+                           reuse ? 1 : 0);
     }
 assigned:
     e = hipGetLastError();
@@ -911,14 +939,14 @@ assigned:
 
 hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, int K,
                               const double* cin, double* cout, int32_t* assign, double* objective, void* ws,
-                              size_t ws_bytes, const DeviceInfo& dev, hipStream_t s)
+                              size_t ws_bytes, const DeviceInfo& dev, hipStream_t s, bool reuse_scale)
 {
     KmPlan k = km_plan(prec, p, n, K, dev);
     if (prec == 0)
         return km_launch<double>(k, p, m, reinterpret_cast<const double*>(vals), idx, n, K, cin, cout, assign,
-                                 objective, ws, ws_bytes, dev, s);
+                                 objective, ws, ws_bytes, dev, s, reuse_scale);
     return km_launch<float>(k, p, m, reinterpret_cast<const float*>(vals), idx, n, K, cin, cout, assign, objective,
-                            ws, ws_bytes, dev, s);
+                            ws, ws_bytes, dev, s, reuse_scale);
 }
 
 // ---------------------------------------------------------------------------

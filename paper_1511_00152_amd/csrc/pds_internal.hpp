@@ -91,9 +91,11 @@ hipError_t launch_keep_best(int r, int T, const double* obj, const double* cente
 
 // ---- K-means ----------------------------------------------------------------
 size_t kmeans_workspace(int prec, int p, int m, int64_t n, int K, const DeviceInfo& dev);
+// reuse_scale: the workspace holds the per-workgroup scales that an earlier
+// round recorded for these same vals / idx / n / K (rounds of one call)
 hipError_t launch_kmeans_step(int prec, int p, int m, const void* vals, const uint16_t* idx, int64_t n, int K,
                               const double* cin, double* cout, int32_t* assign, double* objective, void* ws,
-                              size_t ws_bytes, const DeviceInfo& dev, hipStream_t s);
+                              size_t ws_bytes, const DeviceInfo& dev, hipStream_t s, bool reuse_scale = false);
 
 // ---- two-pass K-means -------------------------------------------------------
 size_t kmeans2_workspace(int prec, int p, int64_t n, int K, const DeviceInfo& dev);

@@ -95,6 +95,16 @@ def test_hot_calls_validate_before_device_work():
     assert L.pds_kmeans_step_noalloc(h, fake, fake, 4, 3, fake, fake, null, fake, null) == _lib.PDS_E_ARG
     assert L.pds_kmeans_step_noalloc(h, fake, fake, 4, 3, fake, fake, fake, fake, null) == _lib.PDS_E_ARG  # alias
     assert L.pds_kmeans_step_noalloc(h, null, null, 0, 3, null, null, null, null, null) == _lib.PDS_OK
+    # several rounds in one call
+    two = ctypes.c_void_p(0x2000)
+    assert L.pds_kmeans_run(None, fake, fake, 4, 3, 2, fake, two, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_run(h, fake, fake, -1, 3, 2, fake, two, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_run(h, fake, fake, 4, 0, 2, fake, two, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_run(h, fake, fake, 4, 3, 0, fake, two, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_run(h, fake, fake, 4, 3, 2, fake, two, fake, null, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_run(h, fake, fake, 4, 3, 2, fake, fake, fake, fake, fake, 1 << 30, null) == _lib.PDS_E_ARG
+    assert L.pds_kmeans_run(h, null, null, 0, 3, 2, null, null, null, null, null, 0, null) == _lib.PDS_OK
+    assert plan.workspace_size(pds.PDS_OP_KMEANS_RUN, 1000, 5) > plan.workspace_size(pds.PDS_OP_KMEANS, 1000, 5)
     # unmix
     assert L.pds_unmix(h, fake, 0, ctypes.c_void_p(0x2000), null) == _lib.PDS_E_ARG
     assert L.pds_unmix(h, null, 2, fake, null) == _lib.PDS_E_ARG

@@ -254,6 +254,32 @@ def test_kmeans_step_deterministic(prec, p, m, K, n):
     assert nerr(r1[0], mu_o) <= tol and abs(float(r1[2][0]) - J_o) <= tol * J_o
 
 
+@pytest.mark.parametrize("prec,p,m,K,n", KM_PATHS + [("f32", 1024, 100, 10, 20000), ("f64", 4096, 100, 100, 700)])
+@pytest.mark.parametrize("T", [1, 2, 5])
+def test_kmeans_run_equals_successive_steps(prec, p, m, K, n, T):
+    """T rounds in one call (rounds after the first reuse the first round's
+    per-workgroup scales) give the bits of T successive kmeans_step calls:
+    centers, the last assignments and every round's objective, on every
+    assignment path; the centers entering the call stay untouched."""
+    pr, dt, _, _ = PRECS[prec]
+    d = synth.random_compressed(n, p, m, seed=K + p + T, dtype=dt, K=K)
+    plan = pds.Plan(p, m, seed=0, prec=pr)
+    vals, idx = to_dev(d["vals"]), to_dev(d["idx"].view(np.int16))
+    C0 = to_dev(d["centers"])
+    C0_copy = C0.clone()
+    C_r, a_r, J_r = pds.kmeans_run(plan, vals, idx, C0, T)
+    C = C0
+    Js = []
+    for _ in range(T):
+        C, a, J = pds.kmeans_step(plan, vals, idx, C)
+        Js.append(float(J.item()))
+    torch.cuda.synchronize()
+    assert torch.equal(C_r, C)
+    assert torch.equal(a_r, a)
+    assert np.array_equal(J_r.cpu().numpy(), np.array(Js))
+    assert torch.equal(C0, C0_copy)
+
+
 KM_SHAPES = [(256, 26, 2000, 5), (1024, 51, 9000, 10), (64, 64, 500, 3), (128, 1, 300, 4), (512, 40, 1000, 1),
              (256, 30, 3000, 37), (4096, 100, 700, 100),
              # FP32 cooperative assignment, one instance per four-cluster group count
