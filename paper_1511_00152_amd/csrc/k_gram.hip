@@ -33,7 +33,7 @@ constexpr int kChunk = 32;       // samples per LDS chunk
 constexpr int kBfStride = kChunk + 8;   // bf16 elements per LDS tile row (80 B: conflict-free 16 B reads)
 constexpr int kF32Stride = kChunk + 1;  // floats per LDS tile row (odd: conflict-free column reads)
 constexpr int kF64Stride = kChunk + 1;
-constexpr int64_t kMaxSamplesPerSplit = 16384;  // FP32 accumulation length before the FP64 sum
+constexpr int64_t kMaxSamplesPerSplit = 32768;  // FP32 accumulation length before the FP64 sum
 
 // ---------------------------------------------------------------------------
 // Block offsets: off[i][b] = number of kept indices of sample i below b * tw
