@@ -200,6 +200,10 @@ def covariance(plan: Plan, vals, idx, acc=None, ws=None, C=None):
         acc = torch.zeros((plan.pg, plan.pg), dtype=torch.float64, device=dev)
     if C is None:
         C = torch.empty((plan.p, plan.p), dtype=torch.float64, device=dev)
+    if acc.dtype != torch.float64 or acc.numel() < plan.pg * plan.pg or not acc.is_contiguous():
+        raise ValueError(f"acc must be a contiguous FP64 buffer of {plan.pg} x {plan.pg}")
+    if C.dtype != torch.float64 or C.numel() < plan.p * plan.p or not C.is_contiguous():
+        raise ValueError(f"C must be a contiguous FP64 buffer of {plan.p} x {plan.p}")
     if ws is None:
         ws = plan.workspace(PDS_OP_COVARIANCE, n, device=dev)
     check(lib().pds_covariance(plan.handle, _ptr(vals), _ptr(idx), n, _ptr(acc), 1, n, _ptr(C), _ptr(ws),
