@@ -3,75 +3,104 @@
 // (Sec. II), ||X U^T||_F^2 / ||X||_F^2 for k orthonormal components (the rows
 // of U) and data rows X.
 //
-// One pass over X.  A workgroup takes 64-row tiles (grid-stride, fixed
-// assignment) and walks the coordinates in chunks of 32: the X chunk (as FP64)
-// and the matching 32 coordinates of every component are staged in LDS, and
-// each thread accumulates the dot products of 4 rows with 1 or 2 components in
-// FP64.  The squared dots and the squares of X are summed per thread, then per
-// workgroup and over workgroups in a fixed order.
+// One pass over X, the dots on the FP64 matrix cores (below).  The squared
+// dots and the squares of X are summed per thread, then per workgroup and
+// over workgroups in a fixed order.
 #include "pds_device.hpp"
 #include "pds_internal.hpp"
 
 namespace pds {
 
-constexpr int kEvRows = 64;
-constexpr int kEvChunk = 32;
 constexpr int kEvThreads = 256;
 constexpr int kEvMaxK = 32;
 constexpr int kEvGrid = 1024;  // workgroups; two FP64 partials each
 
-template <typename T, int NV>
+typedef double ev_d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kEvRB = 1;   // 16-row blocks per wave: a tile of 64 kEvRB rows (2 or 4: 12.7 and 14.6 ms)
+constexpr int kEvKS = 16;  // coordinates per step (32: 10.95 ms, 64: 12.9 ms, against 10.87)
+
+// The dots on the FP64 matrix cores: a workgroup takes tiles of 64 kEvRB rows
+// (grid-stride, fixed assignment) and walks the coordinates kEvKS at a time,
+// the X chunk (as FP64) and the matching coordinates of the components staged
+// in LDS with the next chunk's loads in flight; wave w multiplies its kEvRB
+// blocks of 16 rows with NB blocks of 16 components on v_mfma_f64_16x16x4f64
+// (operand lane l: row / component l mod 16, coordinate l div 16; result
+// register r of lane l: row l div 16 + 4 r, component l mod 16).  Components
+// past k are zero rows, so their dots are zero.
+template <typename T, int NB>
 __global__ __launch_bounds__(kEvThreads) void k_explained(const double* __restrict__ U, int k,
                                                           const T* __restrict__ X, int64_t n, int p, int64_t ldx,
                                                           double* __restrict__ part)
 {
-    __shared__ double xs[kEvRows][kEvChunk + 1];
-    __shared__ double us[kEvMaxK][kEvChunk + 1];
+    constexpr int KS = kEvKS, RB = kEvRB, TR = 64 * RB;  // tile rows
+    constexpr int XPER = TR * KS / kEvThreads;          // staged x per thread
+    constexpr int XTR = KS / XPER;                       // threads per row
+    constexpr int UPER = (KS * 16 * NB) / kEvThreads;   // staged component entries per thread
+    constexpr int UTR = KS / UPER;                       // threads per component
+    __shared__ double xs[TR][KS + 1];
+    __shared__ double us[KS][16 * NB + 1];
     __shared__ double red[2][kEvThreads];
-    const int t = threadIdx.x, rg = t >> 4, vg = t & 15;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int xr = t / XTR, xc = (t % XTR) * XPER;
+    const int ur = t / UTR, uc = (t % UTR) * UPER;
     double num = 0.0, den = 0.0;
-    const int64_t ntiles = (n + kEvRows - 1) / kEvRows;
+    const int64_t ntiles = (n + TR - 1) / TR;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t r0 = tile * kEvRows;
-        double acc[4][NV];
+        const int64_t r0 = tile * TR;
+        const int64_t row = r0 + xr;
+        const T* xrow = X + (row < n ? row : 0) * ldx;
+        double xv[XPER], uv[UPER];
+        auto load = [&](int c0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[i][v] = 0.0;
-        for (int c0 = 0; c0 < p; c0 += kEvChunk) {
-            // X chunk: 8 passes of 8 rows, 32 consecutive coordinates per row
-            const int lc = t & 31, c = c0 + lc;
-#pragma unroll
-            for (int pass = 0; pass < 8; ++pass) {
-                const int lr = pass * 8 + (t >> 5);
-                const int64_t r = r0 + lr;
-                const double x = (r < n && c < p) ? (double)X[r * ldx + c] : 0.0;
-                xs[lr][lc] = x;
-                den += x * x;
+            for (int q = 0; q < XPER; ++q) {
+                const int c = c0 + xc + q;
+                xv[q] = (row < n && c < p) ? (double)xrow[c] : 0.0;
             }
-            for (int e = t; e < kEvMaxK * kEvChunk; e += kEvThreads) {
-                const int j = e / kEvChunk, cc = e % kEvChunk;
-                us[j][cc] = (j < k && c0 + cc < p) ? U[(int64_t)j * p + c0 + cc] : 0.0;
+#pragma unroll
+            for (int q = 0; q < UPER; ++q) {
+                const int c = c0 + uc + q;
+                uv[q] = (ur < k && c < p) ? U[(int64_t)ur * p + c] : 0.0;
             }
+        };
+        ev_d4 acc[RB][NB];
+#pragma unroll
+        for (int a = 0; a < RB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] = (ev_d4){0.0, 0.0, 0.0, 0.0};
+        load(0);
+        for (int c0 = 0; c0 < p; c0 += KS) {
+            __syncthreads();  // the previous step's operand reads are done
+#pragma unroll
+            for (int q = 0; q < XPER; ++q) {
+                xs[xr][xc + q] = xv[q];
+                den = fma(xv[q], xv[q], den);
+            }
+#pragma unroll
+            for (int q = 0; q < UPER; ++q) us[uc + q][ur] = uv[q];
             __syncthreads();
-#pragma unroll 8
-            for (int cc = 0; cc < kEvChunk; ++cc) {
-                double u[NV];
+            if (c0 + KS < p) load(c0 + KS);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) u[v] = us[vg + 16 * v][cc];
+            for (int kk = 0; kk < KS; kk += 4) {
+                double bv[NB];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const double x = xs[4 * rg + i][cc];
+                for (int b = 0; b < NB; ++b) bv[b] = us[kk + lk][16 * b + li];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[i][v] = fma(x, u[v], acc[i][v]);
+                for (int a = 0; a < RB; ++a) {
+                    const double av = xs[16 * (RB * wave + a) + li][kk + lk];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[b], acc[a][b], 0, 0, 0);
                 }
             }
-            __syncthreads();
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int a = 0; a < RB; ++a)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) num += acc[i][v] * acc[i][v];
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) num = fma(acc[a][b][r], acc[a][b][r], num);
     }
     red[0][t] = num;
     red[1][t] = den;
@@ -133,7 +162,7 @@ hipError_t launch_explained(const double* U, int k, const void* X, int x_f64, in
                             double* out2, void* ws, hipStream_t s)
 {
     double* part = reinterpret_cast<double*>(ws);
-    const int64_t ntiles = (n + kEvRows - 1) / kEvRows;
+    const int64_t ntiles = (n + 64 * kEvRB - 1) / (64 * kEvRB);
     const int grid = ntiles < kEvGrid ? (int)ntiles : kEvGrid;
     {
         ProfScope ps_("explained", s);
