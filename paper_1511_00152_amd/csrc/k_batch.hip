@@ -48,7 +48,10 @@ __device__ inline int owner(const int64_t* __restrict__ prefix, int nsets, int64
 // ---------------------------------------------------------------------------
 // compression
 // ---------------------------------------------------------------------------
-template <int L>
+// CALLER tells the two kernels' instantiations apart: with one caller each,
+// the compiler keeps the register allocation it gives a single kernel (shared,
+// it inlined into neither and the batched kernel lost a wave per SIMD)
+template <int L, int CALLER>
 __device__ inline void batch_rows(const BatchSet& S, int64_t r0, int nrows, int spw, int words,
                                   const uint32_t* __restrict__ bitmap, const uint32_t* __restrict__ negbits,
                                   float* __restrict__ buf, int lane)
@@ -111,11 +114,11 @@ __global__ __launch_bounds__(64) void k_batch_compress(const BatchSet* __restric
         }
         __syncthreads();
         switch (S.L) {
-            case 7: batch_rows<7>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
-            case 8: batch_rows<8>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
-            case 9: batch_rows<9>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
-            case 10: batch_rows<10>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
-            default: batch_rows<11>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            case 7: batch_rows<7, 0>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            case 8: batch_rows<8, 0>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            case 9: batch_rows<9, 0>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            case 10: batch_rows<10, 0>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            default: batch_rows<11, 0>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
         }
     }
 }
@@ -167,10 +170,10 @@ __global__ __launch_bounds__(64) void k_compress_fused(uint64_t seed, int p, int
         }
         __syncthreads();
         switch (L) {
-            case 8: batch_rows<8>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
-            case 9: batch_rows<9>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
-            case 10: batch_rows<10>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
-            default: batch_rows<11>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            case 8: batch_rows<8, 1>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            case 9: batch_rows<9, 1>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            case 10: batch_rows<10, 1>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
+            default: batch_rows<11, 1>(S, r0, nrows, spw, words, bitmap, negbits, buf, lane); break;
         }
     }
 }
