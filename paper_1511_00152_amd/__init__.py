@@ -125,13 +125,14 @@ def pad_rows(X, p_pad: int, out=None):
 
 
 def compress(plan: Plan, X, i0: int = 0, vals=None, idx=None, ws=None):
-    """Returns (vals n x m, idx n x m uint16 as torch.int16 storage).  Rows
-    narrower than the plan's p (a dimension that is not a power of two) are
-    zero-padded first (pad_rows)."""
+    """Returns (vals n x m, idx n x m uint16 as torch.int16 storage).  For a
+    Hadamard plan, rows narrower than the plan's p (a dimension that is not a
+    power of two) are zero-padded first (pad_rows); a DCT plan takes rows of
+    exactly its p."""
     import torch
 
     n, p = X.shape
-    if p < plan.p:
+    if p < plan.p and plan.transform == PDS_TRANSFORM_HADAMARD:
         X = pad_rows(X, plan.p)
         p = plan.p
     if p != plan.p:
