@@ -357,7 +357,8 @@ pds_status pds_compress(pds_plan plan, const void* X, int64_t n, int64_t ldx, ui
     e = pds::launch_sample_indices(plan->seed, (int)plan->p, (int)plan->m, n, i0, idx, dev, s);
     if (e != hipSuccess) return hip_fail(e, "sample_indices");
     if (dct) {
-        e = pds::launch_dct_compress(plan->prec, plan->seed, (int)plan->p, (int)plan->m, X, n, ldx, idx, vals, ws, s);
+        e = pds::launch_dct_compress(plan->prec, plan->seed, (int)plan->p, (int)plan->m, X, n, ldx, idx, vals, ws, dev,
+                                     s);
         if (e != hipSuccess) return hip_fail(e, "compress (DCT)");
         return PDS_OK;
     }

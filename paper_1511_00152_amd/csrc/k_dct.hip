@@ -178,16 +178,250 @@ __global__ __launch_bounds__(256) void k_dct_compress(uint64_t seed, int p, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fast form (p = 2^a 3^b 5^c 7^d, p <= 2048): O(p log p) per sample.
+// Makhoul's reordering turns the DCT-II into one complex DFT of the same
+// length: with v_n = x_{2n} (n < ceil(p/2)) and v_{p-1-n} = x_{2n+1},
+//     sum_n x_n cos(pi k (2n + 1) / (2p)) = Re(e^{-i pi k / (2p)} V_k),
+// V = DFT(v).  Two samples share one complex transform (z = v1 + i 2^e v2,
+// 2^e bringing the two norms within a factor of two, so that the rounding of
+// the one transform stays relative to each sample's own norm; V1_k =
+// (Z_k + conj Z_{-k}) / 2, V2_k = 2^-e (Z_k - conj Z_{-k}) / (2i)), which a
+// Stockham autosort FFT computes in LDS, radix 4, 2, 3, 5 or 7 per stage,
+// every stage's twiddles read from a table of e^{-2 pi i k / p} built from
+// cospi / sinpi of the exact angles, all in FP64.  One wave per pair of
+// samples; the pair's kept entries are gathered from the result in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kFftMaxP = 2048;
+constexpr int kFftMaxStages = 12;
+
+struct FftPlan {
+    int nf;
+    int r[kFftMaxStages];
+};
+
+// radices for p, largest-first among 4, 2, 3, 5, 7 (as the model of the
+// transform the tests pin); nf = 0 when p has another prime factor
+static FftPlan fft_plan(int p)
+{
+    FftPlan f{};
+    int n = p;
+    const int rs[5] = {4, 2, 3, 5, 7};
+    for (int ri = 0; ri < 5; ++ri)
+        while (n % rs[ri] == 0 && f.nf < kFftMaxStages) {
+            f.r[f.nf++] = rs[ri];
+            n /= rs[ri];
+        }
+    if (n != 1) f.nf = 0;
+    return f;
+}
+
+bool dct_fast_ok(int p)
+{
+    return p >= 2 && p <= kFftMaxP && fft_plan(p).nf > 0;
+}
+
+// W[k] = e^{-2 pi i k / p}; Q[k] = s_k (cos(pi k / (2p)), sin(pi k / (2p)))
+__global__ __launch_bounds__(256) void k_dct_fft_tables(int p, double2* __restrict__ W, double2* __restrict__ Q)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= p) return;
+    const double a = 2.0 * (double)k / (double)p;  // exact for the power-of-two part; one rounding otherwise
+    W[k] = make_double2(cospi(a), -sinpi(a));
+    const double b = (double)k / (2.0 * (double)p);
+    const double sk = (k == 0) ? sqrt(1.0 / p) : sqrt(2.0 / p);
+    Q[k] = make_double2(sk * cospi(b), sk * sinpi(b));
+}
+
+__device__ inline double2 cmul(double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// one Stockham stage of radix R: in[q + s (p + t m)] -> out[q + s (R p + u)]
+template <int R>
+__device__ inline void fft_stage(const double2* __restrict__ in, double2* __restrict__ out, int N, int m, int s,
+                                 const double2* __restrict__ W, int lane)
+{
+    double2 root[R];  // e^{-2 pi i k / R}
+#pragma unroll
+    for (int k = 0; k < R; ++k) root[k] = W[k * (N / R)];
+    const int nb = m * s;
+    for (int b = lane; b < nb; b += 64) {
+        const int pp = b / s, q = b - pp * s;
+        double2 a[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) a[t] = in[q + s * (pp + t * m)];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            double2 acc = a[0];
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                const double2 w = root[(t * u) % R];
+                acc.x = fma(a[t].x, w.x, fma(-a[t].y, w.y, acc.x));
+                acc.y = fma(a[t].x, w.y, fma(a[t].y, w.x, acc.y));
+            }
+            // pp u s < N: the twiddle of output u of butterfly pp
+            out[q + s * (R * pp + u)] = (u == 0) ? acc : cmul(acc, W[pp * u * s]);
+        }
+    }
+}
+
+template <class TX, class TV>
+__global__ __launch_bounds__(64) void k_dct_fft(uint64_t seed, int p, int m, const TX* __restrict__ X, int64_t n,
+                                                int64_t ldx, const double2* __restrict__ W,
+                                                const double2* __restrict__ Q, FftPlan fp,
+                                                const uint16_t* __restrict__ idx, TV* __restrict__ vals)
+{
+    extern __shared__ double2 fbuf[];  // 2 p complex: the two Stockham buffers
+    __shared__ uint32_t neg[kFftMaxP / 32];
+    const int lane = threadIdx.x;
+    for (int b = lane; b < (p + 255) / 256; b += 64) {
+        const u64x4 blk = sign_block(seed, (uint64_t)b);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            neg[b * 8 + 2 * w] = (uint32_t)blk.w[w];
+            neg[b * 8 + 2 * w + 1] = (uint32_t)(blk.w[w] >> 32);
+        }
+    }
+    wave_lds_sync();
+    const int64_t npairs = (n + 1) / 2;
+    const int h = (p + 1) / 2;
+    for (int64_t pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+        const int64_t i1 = 2 * pr, i2 = i1 + 1;
+        const bool two = i2 < n;
+        double2* A = fbuf;
+        double2* B = fbuf + p;
+        // signed rows, Makhoul order: x_j goes to j / 2 (j even) or p - 1 - (j - 1) / 2 (j odd)
+        const TX* x1 = X + i1 * ldx;
+        const TX* x2 = X + (two ? i2 : i1) * ldx;
+        double ss1 = 0.0, ss2 = 0.0;
+        for (int j = lane; j < p; j += 64) {
+            const double sg = ((neg[j >> 5] >> (j & 31)) & 1u) ? -1.0 : 1.0;
+            const int pos = (j & 1) ? p - 1 - (j >> 1) : (j >> 1);
+            const double a = (double)x1[j], b = two ? (double)x2[j] : 0.0;
+            ss1 = fma(a, a, ss1);
+            ss2 = fma(b, b, ss2);
+            A[pos] = make_double2(sg * a, sg * b);
+        }
+        // the joint transform's rounding is relative to the larger of the two
+        // norms: the second sample is scaled by a power of two (exact) that
+        // brings its norm within a factor of two of the first's, and scaled
+        // back after the separation
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            ss1 += __shfl_xor(ss1, off, 64);
+            ss2 += __shfl_xor(ss2, off, 64);
+        }
+        int e = 0;
+        if (ss1 > 0.0 && ss2 > 0.0 && ss1 < INFINITY && ss2 < INFINITY) {
+            int e1, e2;
+            (void)frexp(ss1, &e1);
+            (void)frexp(ss2, &e2);
+            e = (e1 - e2) / 2;
+        }
+        wave_lds_sync();
+        if (e != 0) {
+            for (int j = lane; j < p; j += 64) A[j].y = ldexp(A[j].y, e);
+            wave_lds_sync();
+        }
+        int len = p, s = 1;
+        for (int f = 0; f < fp.nf; ++f) {
+            const int r = fp.r[f];
+            const int mm = len / r;
+            switch (r) {
+                case 2: fft_stage<2>(A, B, p, mm, s, W, lane); break;
+                case 3: fft_stage<3>(A, B, p, mm, s, W, lane); break;
+                case 4: fft_stage<4>(A, B, p, mm, s, W, lane); break;
+                case 5: fft_stage<5>(A, B, p, mm, s, W, lane); break;
+                default: fft_stage<7>(A, B, p, mm, s, W, lane); break;
+            }
+            wave_lds_sync();
+            double2* t = A;
+            A = B;
+            B = t;
+            len = mm;
+            s *= r;
+        }
+        // separate the two spectra and apply e^{-i pi k / (2p)} s_k: the
+        // transforms of the two samples go to B as 2 p doubles
+        double* Y = reinterpret_cast<double*>(B);
+        for (int k = lane; k < p; k += 64) {
+            const double2 zk = A[k], zm = A[k == 0 ? 0 : p - k];
+            const double2 q = Q[k];
+            const double r1 = 0.5 * (zk.x + zm.x), i1v = 0.5 * (zk.y - zm.y);
+            const double r2 = 0.5 * (zk.y + zm.y), i2v = -0.5 * (zk.x - zm.x);
+            Y[k] = fma(q.x, r1, q.y * i1v);
+            Y[p + k] = ldexp(fma(q.x, r2, q.y * i2v), -e);
+        }
+        wave_lds_sync();
+        const uint16_t* ix1 = idx + i1 * (int64_t)m;
+        TV* o1 = vals + i1 * (int64_t)m;
+        for (int t = lane; t < m; t += 64) o1[t] = (TV)Y[ix1[t]];
+        if (two) {
+            const uint16_t* ix2 = idx + i2 * (int64_t)m;
+            TV* o2 = vals + i2 * (int64_t)m;
+            for (int t = lane; t < m; t += 64) o2[t] = (TV)Y[p + ix2[t]];
+        }
+        wave_lds_sync();  // the next pair overwrites the buffers
+    }
+}
+
 size_t dct_compress_workspace(int p)
 {
+    if (dct_fast_ok(p)) return 2 * (size_t)p * sizeof(double2) + 256;
     return (size_t)p * (size_t)p * sizeof(double);
 }
 
 hipError_t launch_dct_compress(int prec, uint64_t seed, int p, int m, const void* X, int64_t n, int64_t ldx,
-                               const uint16_t* idx, void* vals, void* ws, hipStream_t s)
+                               const uint16_t* idx, void* vals, void* ws, const DeviceInfo& dev, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     if (p > kDctMaxP) return hipErrorInvalidValue;
+    if (dct_fast_ok(p)) {
+        double2* W = reinterpret_cast<double2*>(ws);
+        double2* Q = reinterpret_cast<double2*>(reinterpret_cast<unsigned char*>(ws) +
+                                                ((p * sizeof(double2) + 255) & ~(size_t)255));
+        {
+            ProfScope ps_("dct_table", s);
+            hipLaunchKernelGGL(k_dct_fft_tables, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, s, p, W, Q);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const FftPlan fp = fft_plan(p);
+        const size_t lds = 2 * (size_t)p * sizeof(double2);
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dct_fft<double, double>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kFftMaxP * (int)sizeof(double2));
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dct_fft<float, float>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kFftMaxP * (int)sizeof(double2));
+            attr = true;
+        }
+        int per_cu = (int)((160 * 1024) / (lds + 1024));
+        if (per_cu < 1) per_cu = 1;
+        if (per_cu > 16) per_cu = 16;
+        const int64_t npairs = (n + 1) / 2;
+        int64_t grid = (int64_t)dev.cus * per_cu;
+        if (grid > npairs) grid = npairs;
+        ProfScope ps_("compress", s);
+        if (prec == 0)
+            hipLaunchKernelGGL((k_dct_fft<double, double>), dim3((unsigned)grid), dim3(64), lds, s, seed, p, m,
+                               reinterpret_cast<const double*>(X), n, ldx, W, Q, fp, idx,
+                               reinterpret_cast<double*>(vals));
+        else
+            hipLaunchKernelGGL((k_dct_fft<float, float>), dim3((unsigned)grid), dim3(64), lds, s, seed, p, m,
+                               reinterpret_cast<const float*>(X), n, ldx, W, Q, fp, idx,
+                               reinterpret_cast<float*>(vals));
+        return hipGetLastError();
+    }
     double* T = reinterpret_cast<double*>(ws);
     {
         const int64_t tot = (int64_t)p * p;

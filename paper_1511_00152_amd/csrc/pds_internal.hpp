@@ -49,10 +49,12 @@ hipError_t launch_compress_kron(uint64_t seed, int m, const float* X, int64_t n,
                                 float* vals, const DeviceInfo& dev, hipStream_t s);
 
 // DCT plans: y = C D x (orthonormal DCT-II) for any p <= 8192; ws holds the
-// p x p FP64 table (dct_compress_workspace bytes)
+// FFT twiddle tables (p = 2^a 3^b 5^c 7^d <= 2048) or the p x p FP64 table
+// of the dense form (dct_compress_workspace bytes)
 size_t dct_compress_workspace(int p);
+bool dct_fast_ok(int p);
 hipError_t launch_dct_compress(int prec, uint64_t seed, int p, int m, const void* X, int64_t n, int64_t ldx,
-                               const uint16_t* idx, void* vals, void* ws, hipStream_t s);
+                               const uint16_t* idx, void* vals, void* ws, const DeviceInfo& dev, hipStream_t s);
 hipError_t launch_dct_unmix(uint64_t seed, int p, const double* cpre, int K, double* cout, hipStream_t s);
 
 // ---- covariance -----------------------------------------------------------

@@ -220,8 +220,9 @@ def test_dct_plan_validation(p, m, prec, expect):
 def test_dct_plan_queries():
     """A DCT plan of any p (Sec. III's fast orthonormal transforms; Sec. VII's
     p = 784): its transform reads back, its signs and compress workspace (the
-    p x p FP64 table), and a covariance accumulator over the next power of two;
-    the m-selector calls refuse it."""
+    FFT form's two p-point complex FP64 tables when p = 2^a 3^b 5^c 7^d <= 2048,
+    else the dense form's p x p FP64 table), and a covariance accumulator over
+    the next power of two; the m-selector calls refuse it."""
     L = pds.lib()
     plan = pds.Plan(784, 40, seed=5, transform=pds.PDS_TRANSFORM_DCT)
     t = ctypes.c_int32(-1)
@@ -230,7 +231,10 @@ def test_dct_plan_queries():
     assert L.pds_plan_transform(None, ctypes.byref(t)) == _lib.PDS_E_ARG
     assert L.pds_plan_transform(plan.handle, None) == _lib.PDS_E_ARG
     assert np.array_equal(plan.signs(), ref.signs(5, 784))
-    assert plan.workspace_size(pds.PDS_OP_COMPRESS, 1000) == 784 * 784 * 8
+    assert plan.workspace_size(pds.PDS_OP_COMPRESS, 1000) == 2 * 784 * 16 + 256
+    for q, fast in ((2, True), (1000, True), (2048, True), (4096, False), (129, False), (11, False), (2058, False)):
+        w = pds.Plan(q, 1, transform=pds.PDS_TRANSFORM_DCT).workspace_size(pds.PDS_OP_COMPRESS, 10)
+        assert w == (2 * q * 16 + 256 if fast else q * q * 8), q
     b = ctypes.c_size_t()
     assert L.pds_covariance_acc_size(plan.handle, ctypes.byref(b)) == 0 and b.value == 1024 * 1024 * 8
     assert plan.pg == 1024

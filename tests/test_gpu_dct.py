@@ -3,12 +3,17 @@ Sec. III; the paper's p = 784 runs of Sec. VII) against the FP64 oracle's
 compress_dct / unmix_dct and its estimators, on the same seeded inputs.
 
 Bars (derived from the arithmetic): kept indices and FP64 K-means assignments
-bit-exact.  The transform is an FP64 dense product over p terms, so an FP64
-plan's values lie within 4 p u ||x_i|| of the oracle's (u = 2^-53; every
-|C[j][k]| <= sqrt(2/p), so the terms of y_j sum in absolute value to at most
-sqrt(2) ||x_i||, and both sides round each of p additions); an FP32 plan's
-values are that result rounded once, within 2^-24 |y| more.  Estimators on top
-take the bars of the Hadamard plans: 1e-12 (FP64), 1e-5 (FP32, split).
+bit-exact.  In its dense form (p with a prime factor above 7, or p > 2048) the
+transform is an FP64 product over p terms, so an FP64 plan's values lie within
+4 p u ||x_i|| of the oracle's (u = 2^-53; every |C[j][k]| <= sqrt(2/p), so the
+terms of y_j sum in absolute value to at most sqrt(2) ||x_i||, and both sides
+round each of p additions).  The FFT form (other p) rounds in each of its at
+most log2 p radix stages and in the pre- and post-rotations, a few u ||x_i||
+per stage (the usual FFT error analysis, e.g. Higham, Accuracy and Stability
+of Numerical Algorithms, ch. 24), which stays under the same bar for every p
+>= 2.  An FP32 plan's values are that result rounded once, within 2^-24 |y|
+more.  Estimators on top take the bars of the Hadamard plans: 1e-12 (FP64),
+1e-5 (FP32, split).
 """
 import numpy as np
 import pytest

@@ -150,6 +150,27 @@ def test_mixture_full_size_kmeans_identical_inputs(mixture):
         assert ec <= 1e-5 and eJ <= 1e-5
 
 
+def test_mixture_full_size_kmeans_run_equals_steps(mixture):
+    """At the mixture size the 20 rounds of one kmeans_run call (rounds after
+    the first reuse the per-workgroup scales of the first) give the bits of 20
+    kmeans_step calls: centers, last assignments, every objective."""
+    p, n, K, T = mixture["p"], mixture["n"], mixture["w"]["K"], mixture["w"]["T"]
+    v32 = mixture["v_o"].astype(np.float32)
+    i_o = mixture["i_o"]
+    mu0, _ = ref.kmeanspp(0, p, v32.astype(np.float64), i_o, K)
+    plan = pds.Plan(p, mixture["m"], seed=0, prec=pds.PDS_F32)
+    vals, idx = torch.from_numpy(v32).cuda(), torch.from_numpy(i_o.view(np.int16)).cuda()
+    C0 = torch.from_numpy(mu0).cuda()
+    C_r, a_r, J_r = pds.kmeans_run(plan, vals, idx, C0, T)
+    C, Js = C0, []
+    for _ in range(T):
+        C, a, J = pds.kmeans_step(plan, vals, idx, C)
+        Js.append(float(J.item()))
+    torch.cuda.synchronize()
+    assert torch.equal(C_r, C) and torch.equal(a_r, a)
+    assert np.array_equal(J_r.cpu().numpy(), np.array(Js))
+
+
 def test_mixture_full_size_kmeans_pipeline(mixture):
     """The bench's pipeline: GPU compression, then 20 rounds from the oracle's
     K-means++ centers; objectives and final centers against the oracle's run
