@@ -76,6 +76,16 @@ def algorithmic_work(name, n, p, m, prec):
     return "hbm", 0.0, "GB/s", PEAK_HBM_GBS
 
 
+def compress_summary(kern, n, p, m):
+    """Sampler + compression against HBM: read x_i (FP32), write the m kept
+    values (FP32) and indices (16-bit) -- one launch when the sampler is fused
+    into the transform, two otherwise."""
+    t = kern["compress"]["avg_ms"] + kern.get("sample_indices", {"avg_ms": 0.0})["avg_ms"]
+    b = n * (4.0 * p + 6.0 * m)
+    return {"ms": t, "launches": 1 if "sample_indices" not in kern else 2, "algorithmic_gb": b / 1e9,
+            "achieved_gbs": b / (t / 1e3) / 1e9, "frac_hbm": b / (t / 1e3) / 1e9 / PEAK_HBM_GBS}
+
+
 def source_digest():
     h = hashlib.sha1()
     d = os.path.join(ROOT, "paper_1511_00152_amd", "csrc")
@@ -757,6 +767,7 @@ def main():
         "roofline": roofline(res[head]["kernels"], n, p, m, head, args.steps),
         "kernels_ms": {k: d["avg_ms"] for k, d in res[head]["kernels"].items()},
         "gpu_ms_per_step": res[head]["gpu_ms_per_step"],
+        "compress": compress_summary(res[head]["kernels"], n, p, m),
     }
     for v in variants[1:]:
         out[f"{v}_variant"] = {"value": res[v]["value"], "ms_per_step": res[v]["ms_per_step"],

@@ -60,6 +60,16 @@ __device__ inline int zrow(int rb, int kk, int h, int j) { return 32 * rb + 16 *
 
 constexpr int kKronP = 4096;
 constexpr int kKronPad = kKronP + kKronP / 32;
+constexpr int kKronIdxRegs = 8;  // kept indices per lane requested ahead (m <= 512 entirely)
+
+// Half rb of a lane's share of row x (8 x 16 B): element 64 (32 rb + i32) +
+// 16 kb + 8 h + j in cur[8 rb + 2 kb + j / 4], the layout stage 1 consumes
+__device__ inline void kron_load_half(float4 (&cur)[16], const float* __restrict__ x, int rb, int i32, int h)
+{
+#pragma unroll
+    for (int q = 8 * rb; q < 8 * rb + 8; ++q)
+        cur[q] = reinterpret_cast<const float4*>(x + 64 * (32 * rb + i32) + 16 * ((q >> 1) & 3) + 8 * h)[q & 1];
+}
 
 __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int m, const float* __restrict__ X,
                                                               int64_t n, int64_t ldx, const uint16_t* __restrict__ idx,
@@ -122,11 +132,24 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
                 negmask |= (uint64_t)((negbits[e >> 5] >> (e & 31)) & 1u) << (32 * rb + 8 * kb + j);
             }
 
-    // A lane's whole share of the row (16 x 16 B) is requested at once, so a
-    // sample waits on memory once; the second wave of the SIMD computes
-    // meanwhile.
+    // A lane's share of a row (16 x 16 B) is requested as the previous row's
+    // registers free up: half once stage 1 has consumed it, half once stage 2
+    // has consumed half of Z, so the loads fly during stage 2 and the gather
+    // of the previous sample.  The first kKronIdxRegs x 64 kept indices of a
+    // sample are requested when its stage 1 starts.
     const int64_t nwaves = (int64_t)gridDim.x * 4;
+    float4 cur[16];
+    if ((int64_t)blockIdx.x * 4 + wave < n) {
+        kron_load_half(cur, X + ((int64_t)blockIdx.x * 4 + wave) * ldx, 0, i32, h);
+        kron_load_half(cur, X + ((int64_t)blockIdx.x * 4 + wave) * ldx, 1, i32, h);
+    }
     for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < n; i += nwaves) {
+        const uint16_t* ix = idx + i * (int64_t)m;
+        uint32_t ixr[kKronIdxRegs];
+#pragma unroll
+        for (int u = 0; u < kKronIdxRegs; ++u) ixr[u] = lane + 64 * u < m ? ix[lane + 64 * u] : 0u;
+        // the next row (this one again at the wave's last sample, a harmless reload)
+        const float* xn = X + (i + nwaves < n ? i + nwaves : i) * ldx;
         // the sign bits are re-read from this register every sample: otherwise
         // the 64 per-element sign words are hoisted out of the loop and take
         // 64 registers for the whole kernel
@@ -139,14 +162,8 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) z[rb][cb][r] = 0.0f;
-        float4 cur[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            cur[q] = reinterpret_cast<const float4*>(X + i * ldx + 64 * (32 * (q >> 3) + i32) + 16 * ((q >> 1) & 3) +
-                                                     8 * h)[q & 1];
-        // the loads stay here (not sunk to their uses), and each split-and-
-        // multiply block below is scheduled on its own, which bounds the
-        // registers live at once
+        // each split-and-multiply block below is scheduled on its own, which
+        // bounds the registers live at once
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
@@ -174,6 +191,8 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
+        kron_load_half(cur, xn, 0, i32, h);
+        __builtin_amdgcn_sched_barrier(0);
         // stage 2: Y = H Z, K over Z's rows in accumulator order.  Column block
         // cb of Y needs only column block cb of Z, so each is finished and
         // written out (Y[r][c] = y_{64 r + c}; the lane holds column
@@ -207,6 +226,10 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
+            if (cb == 0) {
+                kron_load_half(cur, xn, 1, i32, h);
+                __builtin_amdgcn_sched_barrier(0);
+            }
 #pragma unroll
             for (int rb2 = 0; rb2 < 2; ++rb2)
 #pragma unroll
@@ -218,9 +241,11 @@ __global__ __launch_bounds__(256, 2) void k_compress_kron4096(uint64_t seed, int
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint16_t* ix = idx + i * (int64_t)m;
         float* out = vals + i * (int64_t)m;
-        for (int t = lane; t < m; t += 64) out[t] = yb[lds_pad<float>((int)ix[t])];
+#pragma unroll
+        for (int u = 0; u < kKronIdxRegs; ++u)
+            if (lane + 64 * u < m) out[lane + 64 * u] = yb[lds_pad<float>((int)ixr[u])];
+        for (int t = lane + 64 * kKronIdxRegs; t < m; t += 64) out[t] = yb[lds_pad<float>((int)ix[t])];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -118,6 +118,38 @@ def test_compress_strided_rows(p):
     assert nerr(vals.cpu().numpy().astype(np.float64), v_o) <= 1e-6
 
 
+# Split plans at p = 4096 take the Kronecker matrix-core transform (one wave
+# per sample, persistent, the next row and the first 512 kept indices requested
+# ahead): fewer samples than waves, m = 1 and 2, m past the 512 requested ahead,
+# m = p.
+KRON_SHAPES = [(410, 1), (410, 31), (410, 33), (1, 100), (2, 65), (600, 300), (1000, 97), (3840, 40), (4096, 20)]
+
+
+@pytest.mark.parametrize("m,n", KRON_SHAPES)
+def test_split_4096_kron_matches_oracle(m, n):
+    p = 4096
+    log(f"split p=4096 m={m} n={n}")
+    X = np.random.default_rng([m, n]).standard_normal((n, p)).astype(np.float32)
+    plan = pds.Plan(p, m, seed=5 + m, prec=pds.PDS_SPLIT_BF16)
+    vals, idx = pds.compress(plan, to_dev(X))
+    torch.cuda.synchronize()
+    v_o, i_o = ref.compress(X, 5 + m, m)
+    assert np.array_equal(u16(idx), i_o)
+    assert nerr(vals.cpu().numpy().astype(np.float64), v_o) <= 1e-6
+
+
+def test_split_4096_chunked_equals_one_shot():
+    """Chunked calls (i0 > 0, ragged chunk sizes) reproduce a one-shot call bit for bit."""
+    p, m, n = 4096, 410, 1000
+    X = to_dev(np.random.default_rng(3).standard_normal((n, p)).astype(np.float32))
+    plan = pds.Plan(p, m, seed=8, prec=pds.PDS_SPLIT_BF16)
+    v1, i1 = pds.compress(plan, X)
+    parts = [pds.compress(plan, X[a:b], i0=a) for a, b in [(0, 45), (45, 46), (46, 517), (517, 1000)]]
+    torch.cuda.synchronize()
+    assert torch.equal(i1, torch.cat([q[1] for q in parts]))
+    assert torch.equal(v1, torch.cat([q[0] for q in parts]))
+
+
 def test_compress_empty_is_noop():
     plan = pds.Plan(256, 26, prec=pds.PDS_F32)
     X = torch.empty((0, 256), dtype=torch.float32, device="cuda")
