@@ -183,8 +183,10 @@ constexpr int kPackStageBytes = 32768;  // chunk index rows staged in LDS up to 
 // rowbytes = 1 and eb = 128, so that OA = (sample << 7) | coordinate-in-block,
 // and also takes SS[c][b][s] (start of sample s inside block b's run, uint16)
 // and CM[c] (the chunk's largest |value|, FP32 bits); both are skipped when
-// NULL.
-template <bool STAGE>
+// NULL.  VREG > 0 (chunks of at most 256 VREG entries): each thread's values
+// are requested into registers before the index tables are built, so their
+// loads fly during the table and scan phases instead of stalling the writes.
+template <bool STAGE, int VREG>
 __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
                                                    int64_t n, int m, int tr, int tc, int nbc, int rowbytes, int eb,
                                                    int split, uint32_t* __restrict__ P, uint16_t* __restrict__ OA,
@@ -204,6 +206,10 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
 
     const int tot = ns * m;
     const float inv_m = 1.0f / (float)m;
+    const float* cval = vals + i0 * (int64_t)m;
+    float pv[VREG > 0 ? VREG : 1];
+#pragma unroll
+    for (int k = 0; k < VREG; ++k) pv[k] = tid + 256 * k < tot ? cval[tid + 256 * k] : 0.0f;
     const uint16_t* gidx = idx + i0 * (int64_t)m;
     const uint16_t* cidx = gidx;
     if constexpr (STAGE) {
@@ -276,20 +282,25 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
 
     uint32_t* Pc = P + c * (int64_t)kChunk * m;
     uint16_t* OAc = OA + c * (int64_t)kChunk * m;
-    const float* cval = vals + i0 * (int64_t)m;
     uint32_t vmax = 0u;  // largest |value| as FP32 bits: NaN and infinity order above every finite value
-#pragma unroll 4
-    for (int f = tid; f < tot; f += 256) {
+    auto put = [&](int f, float v) {
         int s = (int)((float)f * inv_m);
         if (s * m > f) --s;
         if ((s + 1) * m <= f) ++s;
         const uint32_t j = cidx[f];
         const uint32_t q = seg[((int)j >> sh_c) * kChunk + s] + (uint32_t)(f - s * m);
-        const float v = cval[f];
         const uint32_t vb = __float_as_uint(v) & 0x7fffffffu;
         vmax = vb > vmax ? vb : vmax;
         Pc[q] = split ? split_bits(v) : __float_as_uint(v);
         OAc[q] = (uint16_t)((j & (uint32_t)(tr - 1)) * rowbytes + s * eb);
+    };
+    if constexpr (VREG > 0) {
+#pragma unroll
+        for (int k = 0; k < VREG; ++k)
+            if (tid + 256 * k < tot) put(tid + 256 * k, pv[k]);
+    } else {
+#pragma unroll 4
+        for (int f = tid; f < tot; f += 256) put(f, cval[f]);
     }
     if (CM) {
 #pragma unroll
@@ -1332,10 +1343,13 @@ static void pack_attrs()
 {
     static bool pack_attr = false;
     if (!pack_attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<false>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<false, 0>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)pack_lds_bytes(65536 / kSpW));
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+        const void* staged[] = {reinterpret_cast<const void*>(&k_gram_pack<true, 0>),
+                                reinterpret_cast<const void*>(&k_gram_pack<true, 16>),
+                                reinterpret_cast<const void*>(&k_gram_pack<true, 32>),
+                                reinterpret_cast<const void*>(&k_gram_pack<true, 64>)};
+        for (const void* k : staged) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
         pack_attr = true;
     }
 }
@@ -1351,12 +1365,21 @@ static hipError_t launch_pack(const GramPlan& g, int m, const float* vals, const
     const size_t lds = pack_lds_bytes(g.geom.nbc) + (stage ? (((size_t)kChunk * m * 2 + 15) & ~(size_t)15) : 0);
     pack_attrs();
     ProfScope ps_("gram_pack", s);
-    if (stage)
-        hipLaunchKernelGGL(k_gram_pack<true>, dim3((unsigned)g.nchunks), dim3(256), lds, s, vals, idx, n, m,
-                           g.geom.tr, g.geom.tc, g.geom.nbc, rowbytes, eb, split, P, OA, BS, SS, CM);
+    const int64_t tot = (int64_t)kChunk * m;  // entries of a full chunk
+#define PDS_PACK(ST, VR)                                                                                        \
+    hipLaunchKernelGGL((k_gram_pack<ST, VR>), dim3((unsigned)g.nchunks), dim3(256), lds, s, vals, idx, n, m,    \
+                       g.geom.tr, g.geom.tc, g.geom.nbc, rowbytes, eb, split, P, OA, BS, SS, CM)
+    if (!stage)
+        PDS_PACK(false, 0);
+    else if (tot <= 256 * 16)
+        PDS_PACK(true, 16);
+    else if (tot <= 256 * 32)
+        PDS_PACK(true, 32);
+    else if (tot <= 256 * 64)
+        PDS_PACK(true, 64);
     else
-        hipLaunchKernelGGL(k_gram_pack<false>, dim3((unsigned)g.nchunks), dim3(256), lds, s, vals, idx, n, m,
-                           g.geom.tr, g.geom.tc, g.geom.nbc, rowbytes, eb, split, P, OA, BS, SS, CM);
+        PDS_PACK(true, 0);
+#undef PDS_PACK
     return hipGetLastError();
 }
 
