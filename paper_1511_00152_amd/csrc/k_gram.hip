@@ -613,6 +613,11 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
     int64_t c_prev = c0;
 
     const int brow0 = (inner ? boff : 0) + wc * 64;
+    // a wave whose 128 x 64 block lies wholly below the diagonal (inner tiles:
+    // its first row past its last column) has nothing to add to the upper
+    // triangle, the only part the reduction keeps: it loads and scatters with
+    // the others but leaves its accumulators at zero
+    const bool below = inner && wr * 128 > brow0 + 63;
 
     for (int64_t c = c0; c < c1; ++c) {
         __syncthreads();
@@ -644,8 +649,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint32_t* __restrict
         // workgroups of a CU reach it together, one runs ahead and the two
         // fall back into alternating scatter and matrix-core phases
         __builtin_amdgcn_s_setprio(1);
-        mfma_step<SPLIT>(L, acc, 0, wr, brow0, inner, lane);
-        mfma_step<SPLIT>(L, acc, 1, wr, brow0, inner, lane);
+        if (!below) {
+            mfma_step<SPLIT>(L, acc, 0, wr, brow0, inner, lane);
+            mfma_step<SPLIT>(L, acc, 1, wr, brow0, inner, lane);
+        }
         __builtin_amdgcn_s_setprio(0);
     }
 
