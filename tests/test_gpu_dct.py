@@ -76,11 +76,16 @@ def check_values(vals, ovals, X, prec, p):
 
 
 # (p, m, n, prec): non-powers of two, a power of two, the paper's 784, the
-# largest p, m = p, m = 1, one row, ragged tiles in both directions
+# largest p, m = p, m = 1, one row, ragged tiles in both directions.  The FFT
+# form takes p = 2^a 3^b 5^c 7^d <= 2048 (every radix: 768 = 2^8 3, 945 =
+# 3^3 5 7, 9, the largest 2048, an odd count of samples for the pairing); the
+# dense form every other p (4096, 8192, 129, 65, the prime 11, 2058 > 2048).
 SHAPES = [(784, 78, 1000, "f32"), (784, 40, 130, "f64"), (784, 784, 65, "f64"), (7, 3, 65, "f64"),
           (100, 37, 1, "f32"), (1000, 100, 257, "f64"), (1024, 51, 300, "f32"), (2, 1, 5, "f64"),
           (4096, 410, 70, "f32"), (784, 80, 64, "split"), (8192, 100, 9, "f32"), (129, 1, 200, "f64"),
-          (65, 64, 63, "f32")]
+          (65, 64, 63, "f32"), (768, 77, 99, "f64"), (945, 94, 101, "f64"), (9, 4, 33, "f64"),
+          (2048, 205, 65, "f32"), (2048, 100, 17, "f64"), (11, 5, 40, "f64"), (2058, 200, 21, "f64"),
+          (3, 3, 7, "f64"), (5, 2, 3, "f32")]
 
 
 @pytest.mark.parametrize("p,m,n,prec", SHAPES)
@@ -118,7 +123,7 @@ def test_dct_compress_keeps_the_same_sets_as_hadamard():
     assert torch.equal(i_d, i_h)
 
 
-@pytest.mark.parametrize("p", [7, 100, 784, 4096])
+@pytest.mark.parametrize("p", [7, 100, 784, 945, 4096])
 def test_dct_unmix_matches_oracle_and_inverts(p):
     """unmix = D C^T against the oracle, and at m = p, compress then unmix of
     every row returns the rows.  The unmixing advances its cosines by a
