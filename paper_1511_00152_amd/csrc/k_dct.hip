@@ -186,11 +186,14 @@ __global__ __launch_bounds__(256) void k_dct_compress(uint64_t seed, int p, int 
 // V = DFT(v).  Two samples share one complex transform (z = v1 + i 2^e v2,
 // 2^e bringing the two norms within a factor of two, so that the rounding of
 // the one transform stays relative to each sample's own norm; V1_k =
-// (Z_k + conj Z_{-k}) / 2, V2_k = 2^-e (Z_k - conj Z_{-k}) / (2i)), which a
-// Stockham autosort FFT computes in LDS, radix 4, 2, 3, 5 or 7 per stage,
-// every stage's twiddles read from a table of e^{-2 pi i k / p} built from
-// cospi / sinpi of the exact angles, all in FP64.  One wave per pair of
-// samples; the pair's kept entries are gathered from the result in LDS.
+// (Z_k + conj Z_{-k}) / 2, V2_k = 2^-e (Z_k - conj Z_{-k}) / (2i)).  The FFT
+// is a mixed-radix decimation in frequency done in place in one LDS buffer
+// (radix 4, 2, 3, 5 or 7 per stage; each butterfly reads and rewrites its own
+// R positions, so a stage needs no second buffer), every twiddle read from a
+// table of e^{-2 pi i k / p} built from cospi / sinpi of the exact angles, all
+// in FP64.  Its output is in digit-reversed order, so Z_k is read at
+// rev(k); only the kept coordinates are separated and rotated, straight into
+// vals.  One wave per pair of samples.
 // ---------------------------------------------------------------------------
 constexpr int kFftMaxP = 2048;
 constexpr int kFftMaxStages = 12;
@@ -200,8 +203,8 @@ struct FftPlan {
     int r[kFftMaxStages];
 };
 
-// radices for p, largest-first among 4, 2, 3, 5, 7 (as the model of the
-// transform the tests pin); nf = 0 when p has another prime factor
+// radices of p, in the order the stages run: fours, then a two, then threes,
+// fives and sevens; nf = 0 when p has another prime factor
 static FftPlan fft_plan(int p)
 {
     FftPlan f{};
@@ -245,20 +248,56 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// one Stockham stage of radix R: in[q + s (p + t m)] -> out[q + s (R p + u)]
+// quotient of k by a radix of the plan (compile-time divisors)
+__device__ inline int div_radix(int k, int R)
+{
+    switch (R) {
+        case 2: return k >> 1;
+        case 3: return k / 3;
+        case 4: return k >> 2;
+        case 5: return k / 5;
+        default: return k / 7;
+    }
+}
+
+// position of frequency k in the in-place transform's output: with k =
+// u_1 + R_1 (u_2 + R_2 (u_3 + ...)), at sum_i u_i p / (R_1 ... R_i)
+__device__ inline int digit_rev(int k, const FftPlan& fp, int p)
+{
+    int pos = 0, len = p;
+    for (int f = 0; f < fp.nf; ++f) {
+        const int R = fp.r[f];
+        const int q = div_radix(k, R);
+        len = div_radix(len, R);
+        pos += (k - q * R) * len;
+        k = q;
+    }
+    return pos;
+}
+
+// One in-place decimation-in-frequency stage of radix R over sub-transforms
+// of length L = R mm: butterfly (block, j) reads positions base + j + t mm
+// (t < R) and writes y_u = (sum_t a_t e^{-2 pi i t u / R}) e^{-2 pi i j u / L}
+// back to base + j + u mm.  Butterflies own disjoint positions, so lanes need
+// no ordering inside a stage.
 template <int R>
-__device__ inline void fft_stage(const double2* __restrict__ in, double2* __restrict__ out, int N, int m, int s,
-                                 const double2* __restrict__ W, int lane)
+__device__ inline void dif_stage(double2* __restrict__ A, int N, int L, const double2* __restrict__ W, int lane)
 {
     double2 root[R];  // e^{-2 pi i k / R}
 #pragma unroll
     for (int k = 0; k < R; ++k) root[k] = W[k * (N / R)];
-    const int nb = m * s;
-    for (int b = lane; b < nb; b += 64) {
-        const int pp = b / s, q = b - pp * s;
+    const int mm = L / R;
+    const int tw = N / L;  // W step of e^{-2 pi i / L}
+    const float inv_mm = 1.0f / (float)mm;
+    for (int b = lane; b < N / R; b += 64) {
+        int blk = (int)((float)b * inv_mm);  // b < 2^11: exact up to one step, corrected below
+        if (blk * mm > b) --blk;
+        if ((blk + 1) * mm <= b) ++blk;
+        const int j = b - blk * mm;
+        const int base = blk * L + j;
         double2 a[R];
 #pragma unroll
-        for (int t = 0; t < R; ++t) a[t] = in[q + s * (pp + t * m)];
+        for (int t = 0; t < R; ++t) a[t] = A[base + t * mm];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             double2 acc = a[0];
@@ -268,19 +307,22 @@ __device__ inline void fft_stage(const double2* __restrict__ in, double2* __rest
                 acc.x = fma(a[t].x, w.x, fma(-a[t].y, w.y, acc.x));
                 acc.y = fma(a[t].x, w.y, fma(a[t].y, w.x, acc.y));
             }
-            // pp u s < N: the twiddle of output u of butterfly pp
-            out[q + s * (R * pp + u)] = (u == 0) ? acc : cmul(acc, W[pp * u * s]);
+            // j u < L: the twiddle index stays below N
+            A[base + u * mm] = (u == 0 || j == 0) ? acc : cmul(acc, W[tw * j * u]);
         }
     }
 }
 
-template <class TX, class TV>
+// KQ: row elements per lane held in registers (p <= 64 KQ).  The next pair's
+// rows are requested as soon as the current pair's are in LDS, so their loads
+// fly during the transform.
+template <class TX, class TV, int KQ>
 __global__ __launch_bounds__(64) void k_dct_fft(uint64_t seed, int p, int m, const TX* __restrict__ X, int64_t n,
                                                 int64_t ldx, const double2* __restrict__ W,
                                                 const double2* __restrict__ Q, FftPlan fp,
                                                 const uint16_t* __restrict__ idx, TV* __restrict__ vals)
 {
-    extern __shared__ double2 fbuf[];  // 2 p complex: the two Stockham buffers
+    extern __shared__ double2 fbuf[];  // p complex: the transform, in place
     __shared__ uint32_t neg[kFftMaxP / 32];
     const int lane = threadIdx.x;
     for (int b = lane; b < (p + 255) / 256; b += 64) {
@@ -293,24 +335,38 @@ __global__ __launch_bounds__(64) void k_dct_fft(uint64_t seed, int p, int m, con
     }
     wave_lds_sync();
     const int64_t npairs = (n + 1) / 2;
-    const int h = (p + 1) / 2;
+    TX xa[KQ], xb[KQ];
+    auto load_pair = [&](int64_t pr) {
+        const int64_t i1 = 2 * pr, i2 = i1 + 1;
+        const TX* x1 = X + i1 * ldx;
+        const TX* x2 = X + (i2 < n ? i2 : i1) * ldx;
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int j = lane + 64 * q;
+            xa[q] = j < p ? x1[j] : (TX)0;
+            xb[q] = (j < p && i2 < n) ? x2[j] : (TX)0;
+        }
+    };
+    if ((int64_t)blockIdx.x < npairs) load_pair(blockIdx.x);
     for (int64_t pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
         const int64_t i1 = 2 * pr, i2 = i1 + 1;
         const bool two = i2 < n;
         double2* A = fbuf;
-        double2* B = fbuf + p;
         // signed rows, Makhoul order: x_j goes to j / 2 (j even) or p - 1 - (j - 1) / 2 (j odd)
-        const TX* x1 = X + i1 * ldx;
-        const TX* x2 = X + (two ? i2 : i1) * ldx;
         double ss1 = 0.0, ss2 = 0.0;
-        for (int j = lane; j < p; j += 64) {
-            const double sg = ((neg[j >> 5] >> (j & 31)) & 1u) ? -1.0 : 1.0;
-            const int pos = (j & 1) ? p - 1 - (j >> 1) : (j >> 1);
-            const double a = (double)x1[j], b = two ? (double)x2[j] : 0.0;
-            ss1 = fma(a, a, ss1);
-            ss2 = fma(b, b, ss2);
-            A[pos] = make_double2(sg * a, sg * b);
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int j = lane + 64 * q;
+            if (j < p) {
+                const double sg = ((neg[j >> 5] >> (j & 31)) & 1u) ? -1.0 : 1.0;
+                const int pos = (j & 1) ? p - 1 - (j >> 1) : (j >> 1);
+                const double a = (double)xa[q], b = (double)xb[q];
+                ss1 = fma(a, a, ss1);
+                ss2 = fma(b, b, ss2);
+                A[pos] = make_double2(sg * a, sg * b);
+            }
         }
+        if (pr + gridDim.x < npairs) load_pair(pr + gridDim.x);
         // the joint transform's rounding is relative to the larger of the two
         // norms: the second sample is scaled by a power of two (exact) that
         // brings its norm within a factor of two of the first's, and scaled
@@ -332,45 +388,43 @@ __global__ __launch_bounds__(64) void k_dct_fft(uint64_t seed, int p, int m, con
             for (int j = lane; j < p; j += 64) A[j].y = ldexp(A[j].y, e);
             wave_lds_sync();
         }
-        int len = p, s = 1;
+        int len = p;
         for (int f = 0; f < fp.nf; ++f) {
-            const int r = fp.r[f];
-            const int mm = len / r;
-            switch (r) {
-                case 2: fft_stage<2>(A, B, p, mm, s, W, lane); break;
-                case 3: fft_stage<3>(A, B, p, mm, s, W, lane); break;
-                case 4: fft_stage<4>(A, B, p, mm, s, W, lane); break;
-                case 5: fft_stage<5>(A, B, p, mm, s, W, lane); break;
-                default: fft_stage<7>(A, B, p, mm, s, W, lane); break;
+            switch (fp.r[f]) {
+                case 2: dif_stage<2>(A, p, len, W, lane); break;
+                case 3: dif_stage<3>(A, p, len, W, lane); break;
+                case 4: dif_stage<4>(A, p, len, W, lane); break;
+                case 5: dif_stage<5>(A, p, len, W, lane); break;
+                default: dif_stage<7>(A, p, len, W, lane); break;
             }
             wave_lds_sync();
-            double2* t = A;
-            A = B;
-            B = t;
-            len = mm;
-            s *= r;
+            len = div_radix(len, fp.r[f]);
         }
-        // separate the two spectra and apply e^{-i pi k / (2p)} s_k: the
-        // transforms of the two samples go to B as 2 p doubles
-        double* Y = reinterpret_cast<double*>(B);
-        for (int k = lane; k < p; k += 64) {
-            const double2 zk = A[k], zm = A[k == 0 ? 0 : p - k];
-            const double2 q = Q[k];
-            const double r1 = 0.5 * (zk.x + zm.x), i1v = 0.5 * (zk.y - zm.y);
-            const double r2 = 0.5 * (zk.y + zm.y), i2v = -0.5 * (zk.x - zm.x);
-            Y[k] = fma(q.x, r1, q.y * i1v);
-            Y[p + k] = ldexp(fma(q.x, r2, q.y * i2v), -e);
+        // kept coordinates only: separate the two spectra at k and apply
+        // e^{-i pi k / (2p)} s_k (Z_k and Z_{p-k} sit at their digit-reversed positions)
+        {
+            const uint16_t* ix1 = idx + i1 * (int64_t)m;
+            TV* o1 = vals + i1 * (int64_t)m;
+            for (int t = lane; t < m; t += 64) {
+                const int k = ix1[t];
+                const double2 zk = A[digit_rev(k, fp, p)], zm = A[digit_rev(k == 0 ? 0 : p - k, fp, p)];
+                const double2 q = Q[k];
+                const double r1 = 0.5 * (zk.x + zm.x), i1v = 0.5 * (zk.y - zm.y);
+                o1[t] = (TV)fma(q.x, r1, q.y * i1v);
+            }
         }
-        wave_lds_sync();
-        const uint16_t* ix1 = idx + i1 * (int64_t)m;
-        TV* o1 = vals + i1 * (int64_t)m;
-        for (int t = lane; t < m; t += 64) o1[t] = (TV)Y[ix1[t]];
         if (two) {
             const uint16_t* ix2 = idx + i2 * (int64_t)m;
             TV* o2 = vals + i2 * (int64_t)m;
-            for (int t = lane; t < m; t += 64) o2[t] = (TV)Y[p + ix2[t]];
+            for (int t = lane; t < m; t += 64) {
+                const int k = ix2[t];
+                const double2 zk = A[digit_rev(k, fp, p)], zm = A[digit_rev(k == 0 ? 0 : p - k, fp, p)];
+                const double2 q = Q[k];
+                const double r2 = 0.5 * (zk.y + zm.y), i2v = -0.5 * (zk.x - zm.x);
+                o2[t] = (TV)ldexp(fma(q.x, r2, q.y * i2v), -e);
+            }
         }
-        wave_lds_sync();  // the next pair overwrites the buffers
+        wave_lds_sync();  // the next pair overwrites the buffer
     }
 }
 
@@ -396,13 +450,15 @@ hipError_t launch_dct_compress(int prec, uint64_t seed, int p, int m, const void
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const FftPlan fp = fft_plan(p);
-        const size_t lds = 2 * (size_t)p * sizeof(double2);
+        const size_t lds = (size_t)p * sizeof(double2);
         static bool attr = false;
         if (!attr) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dct_fft<double, double>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kFftMaxP * (int)sizeof(double2));
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dct_fft<float, float>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kFftMaxP * (int)sizeof(double2));
+            const void* ks[] = {reinterpret_cast<const void*>(&k_dct_fft<double, double, 16>),
+                                reinterpret_cast<const void*>(&k_dct_fft<double, double, 32>),
+                                reinterpret_cast<const void*>(&k_dct_fft<float, float, 16>),
+                                reinterpret_cast<const void*>(&k_dct_fft<float, float, 32>)};
+            for (const void* k : ks)
+                (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kFftMaxP * (int)sizeof(double2));
             attr = true;
         }
         int per_cu = (int)((160 * 1024) / (lds + 1024));
@@ -412,14 +468,21 @@ hipError_t launch_dct_compress(int prec, uint64_t seed, int p, int m, const void
         int64_t grid = (int64_t)dev.cus * per_cu;
         if (grid > npairs) grid = npairs;
         ProfScope ps_("compress", s);
-        if (prec == 0)
-            hipLaunchKernelGGL((k_dct_fft<double, double>), dim3((unsigned)grid), dim3(64), lds, s, seed, p, m,
-                               reinterpret_cast<const double*>(X), n, ldx, W, Q, fp, idx,
-                               reinterpret_cast<double*>(vals));
-        else
-            hipLaunchKernelGGL((k_dct_fft<float, float>), dim3((unsigned)grid), dim3(64), lds, s, seed, p, m,
-                               reinterpret_cast<const float*>(X), n, ldx, W, Q, fp, idx,
-                               reinterpret_cast<float*>(vals));
+#define PDS_DCT_FFT(T, KQ)                                                                                   \
+    hipLaunchKernelGGL((k_dct_fft<T, T, KQ>), dim3((unsigned)grid), dim3(64), lds, s, seed, p, m,            \
+                       reinterpret_cast<const T*>(X), n, ldx, W, Q, fp, idx, reinterpret_cast<T*>(vals))
+        if (prec == 0) {
+            if (p <= 64 * 16)
+                PDS_DCT_FFT(double, 16);
+            else
+                PDS_DCT_FFT(double, 32);
+        } else {
+            if (p <= 64 * 16)
+                PDS_DCT_FFT(float, 16);
+            else
+                PDS_DCT_FFT(float, 32);
+        }
+#undef PDS_DCT_FFT
         return hipGetLastError();
     }
     double* T = reinterpret_cast<double*>(ws);
