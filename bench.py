@@ -160,15 +160,39 @@ def run_variant(pds, X, p, m, prec_name, steps, warmup):
             "value": n / (wall_ms / 1e3), "kernels": kern, "plan": plan, "vals": vals, "idx": idx, "C": C}
 
 
+def dense_gram_executed_flops(p, n, products):
+    """Flops the dense matrix-core Gram tiles execute (not the method's work):
+    256 x 128 upper tiles (row block a, column blocks b >= 2a), four waves of
+    128 x 64 each, a wave of an inner tile wholly below the diagonal skipped;
+    `products` matrix-core products per pair of entries (3 for split-BF16)."""
+    tr, tc = min(p, 256), min(p, 128)
+    ratio, macs = tr // tc, 0
+    for a in range(p // tr):
+        for b in range(a * ratio, p // tc):
+            inner = b < (a + 1) * ratio
+            boff = b * tc - a * tr
+            for wr in range(2):
+                for wc in range(2):
+                    if not (inner and wr * 128 > boff + wc * 64 + 63):
+                        macs += 128 * 64
+    return 2.0 * macs * products * n
+
+
 def roofline(kern, n, p, m, prec_name, steps):
     name, info = max(kern.items(), key=lambda kv: kv[1]["total_ms"])
     bound, units, unit, peak = algorithmic_work(name, n, p, m, prec_name)
     avg_s = info["avg_ms"] / 1e3
     achieved = units / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
     traffic = load_traffic(name, info["launches"] // max(steps, 1))
-    return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": traffic, "avg_ms": info["avg_ms"],
-            "algorithmic_per_launch": units}
+    out = {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+           "frac": achieved / peak, "traffic": traffic, "avg_ms": info["avg_ms"],
+           "algorithmic_per_launch": units}
+    if name in ("gram_bf16x3", "gram_f32"):
+        # what the dense tiles execute on the matrix cores, against the same peak
+        ex = dense_gram_executed_flops(p, n, 3 if name == "gram_bf16x3" else 1)
+        out["executed_per_launch"] = ex
+        out["executed_frac"] = ex / avg_s / 1e12 / peak
+    return out
 
 
 def cpu_model():
