@@ -601,7 +601,7 @@ def run_dct(pds, steps, warmup):
         "workload": f"{name}: n={n}, p={p}, m={m}, K={K}, T={T}, FP32 plan with the DCT preconditioner; "
                     "step = compress + K-means++ seeding + T K-means rounds (kmeans_run) + unmix",
         "ms_per_step": wall * 1e3, "samples_per_s": n / wall,
-        "dct_compress": ({"ms": t_dct, "form": "fft (Makhoul + mixed-radix Stockham, FP64)",
+        "dct_compress": ({"ms": t_dct, "form": "fft (Makhoul reordering + in-place mixed-radix decimation in frequency, FP64)",
                           "algorithmic_gb": hbm / 1e9, "achieved_gbs": hbm / (t_dct / 1e3) / 1e9,
                           "frac_hbm": hbm / (t_dct / 1e3) / 1e9 / PEAK_HBM_GBS} if fast else
                          {"ms": t_dct, "form": "dense FP64 product on the matrix cores",
