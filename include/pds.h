@@ -113,9 +113,12 @@ pds_status pds_plan_create(pds_plan* out, int64_t p, int64_t m, uint64_t seed, i
  *     C[j][k] = s_j cos(pi (2k + 1) j / (2p)),  s_0 = sqrt(1/p), s_j = sqrt(2/p),
  * for any p in [2, PDS_DCT_MAX_P] (no power-of-two restriction), the same
  * signs D (pds_signs) and the same kept sets as a Hadamard plan of this
- * (p, m, seed).  Every plan call takes it: pds_compress transforms with C (an
- * FP64 dense product, p^2 multiply-adds per sample, rounded once to the
- * plan's value type; its workspace holds the p x p table), pds_unmix applies
+ * (p, m, seed).  Every plan call takes it: pds_compress transforms with C in
+ * FP64, rounded once to the plan's value type -- for p = 2^a 3^b 5^c 7^d <=
+ * 2048 in O(p log p) (Makhoul's reordering of the DCT-II into one complex DFT,
+ * two samples per mixed-radix FFT; its workspace holds 2p complex twiddles and
+ * rotations), for every other p as a dense product of p^2 multiply-adds per
+ * sample (its workspace holds the p x p table) -- pds_unmix applies
  * D C^T, and the covariance accumulates its Gram over the next power of two
  * pg >= p (pds_covariance_acc_size is pg x pg doubles; kept indices are < p,
  * so the extra rows and columns stay zero) and finalizes the p x p C_n.  The
@@ -173,8 +176,11 @@ pds_status pds_covariance_acc_size(pds_plan plan, size_t* bytes);
  *         double for PDS_F64, float otherwise.
  *   vals  device, n x m, same element type as X.
  *   idx   device, n x m uint16.
- *   ws    may be NULL for Hadamard plans (no workspace; ws_bytes ignored);
- *         DCT plans need pds_workspace_size(COMPRESS) bytes (the p x p table).
+ *   ws    device, >= pds_workspace_size(COMPRESS, n) bytes; NULL when that
+ *         size is 0 (Hadamard plans whose row buffer fits in LDS, i.e. every
+ *         p up to 8192 in FP32 and 4096 in FP64).  Larger Hadamard p need a
+ *         row buffer per workgroup; DCT plans the FFT form's tables or the
+ *         dense form's p x p table.
  * Errors: PDS_E_ARG (null pointers with n > 0, n < 0, ldx < p). */
 pds_status pds_compress(pds_plan plan, const void* X, int64_t n, int64_t ldx, uint64_t i0, void* vals,
                         uint16_t* idx, void* ws, size_t ws_bytes, void* stream);

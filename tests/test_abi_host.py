@@ -124,8 +124,12 @@ def test_workspace_queries():
     assert pds.lib().pds_workspace_size(plan.handle, 2, 10, 0, ctypes.byref(b)) == _lib.PDS_E_ARG
     assert pds.lib().pds_workspace_size(plan.handle, 9, 10, 1, ctypes.byref(b)) == _lib.PDS_E_ARG
     assert pds.lib().pds_covariance_acc_size(plan.handle, ctypes.byref(b)) == 0 and b.value == 4096 * 4096 * 8
-    # huge p needs a compress workspace (transform staging outside LDS)
+    # huge p needs a compress workspace (transform staging outside LDS): the
+    # row buffer fits in LDS up to p = 8192 in FP32 and 4096 in FP64
     assert pds.Plan(65536, 10).workspace_size(0, 1000) > 0
+    for p, prec, zero in ((8192, pds.PDS_F32, True), (16384, pds.PDS_F32, False), (4096, pds.PDS_F64, True),
+                          (8192, pds.PDS_F64, False), (8192, pds.PDS_SPLIT_BF16, True)):
+        assert (pds.Plan(p, 10, prec=prec).workspace_size(0, 1000) == 0) == zero, (p, prec)
 
 
 def test_estimator_calls_validate_before_device_work():
