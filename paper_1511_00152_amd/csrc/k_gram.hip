@@ -159,7 +159,8 @@ __device__ inline uint32_t split_bits(float v)
     return (uint32_t)h | ((uint32_t)l << 16);
 }
 
-__device__ inline uint32_t block_exclusive_scan256(uint32_t v, uint32_t* wsum)
+template <int NT>
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint32_t incl = v;
@@ -183,11 +184,13 @@ constexpr int kPackStageBytes = 32768;  // chunk index rows staged in LDS up to 
 // rowbytes = 1 and eb = 128, so that OA = (sample << 7) | coordinate-in-block,
 // and also takes SS[c][b][s] (start of sample s inside block b's run, uint16)
 // and CM[c] (the chunk's largest |value|, FP32 bits); both are skipped when
-// NULL.  VREG > 0 (chunks of at most 256 VREG entries): each thread's values
+// NULL.  VREG > 0 (chunks of at most NT VREG entries): each thread's values
 // are requested into registers before the index tables are built, so their
 // loads fly during the table and scan phases instead of stalling the writes.
-template <bool STAGE, int VREG>
-__global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
+// NT threads per chunk: 512 for large chunks, so that more waves per CU keep
+// loads and stores in flight while others build their tables.
+template <bool STAGE, int VREG, int NT>
+__global__ __launch_bounds__(NT) void k_gram_pack(const float* __restrict__ vals, const uint16_t* __restrict__ idx,
                                                    int64_t n, int m, int tr, int tc, int nbc, int rowbytes, int eb,
                                                    int split, uint32_t* __restrict__ P, uint16_t* __restrict__ OA,
                                                    uint32_t* __restrict__ BS, uint16_t* __restrict__ SS,
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     const int nb1 = nbc + 1;
     uint32_t* off = pk_sh;              // [32][nb1]: first entry of block b in the sample's row
     uint32_t* seg = pk_sh + 32 * nb1;   // [nbc][32]: chunk position of segment (b, s) minus off[s][b]
-    uint32_t* wsum = seg + 32 * nbc;    // 4 wave totals
+    uint32_t* wsum = seg + 32 * nbc;    // NT / 64 wave totals
     const int64_t c = blockIdx.x;
     const int64_t i0 = c * kChunk;
     const int ns = (int)((n - i0) < kChunk ? (n - i0) : kChunk);
@@ -209,16 +212,16 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     const float* cval = vals + i0 * (int64_t)m;
     float pv[VREG > 0 ? VREG : 1];
 #pragma unroll
-    for (int k = 0; k < VREG; ++k) pv[k] = tid + 256 * k < tot ? cval[tid + 256 * k] : 0.0f;
+    for (int k = 0; k < VREG; ++k) pv[k] = tid + NT * k < tot ? cval[tid + NT * k] : 0.0f;
     const uint16_t* gidx = idx + i0 * (int64_t)m;
     const uint16_t* cidx = gidx;
     if constexpr (STAGE) {
-        uint16_t* sidx = reinterpret_cast<uint16_t*>(wsum + 4);  // 16-byte aligned (byte offset 256 nbc + 144)
+        uint16_t* sidx = reinterpret_cast<uint16_t*>(wsum + NT / 64);  // 16-byte aligned (byte offset 256 nbc + 128 + NT / 16)
         const int nvec = (tot * 2) / 16;
         const uint4* src = reinterpret_cast<const uint4*>(gidx);
         uint4* dst = reinterpret_cast<uint4*>(sidx);
-        for (int v = tid; v < nvec; v += 256) dst[v] = src[v];
-        for (int f = nvec * 8 + tid; f < tot; f += 256) sidx[f] = gidx[f];
+        for (int v = tid; v < nvec; v += NT) dst[v] = src[v];
+        for (int f = nvec * 8 + tid; f < tot; f += NT) sidx[f] = gidx[f];
         cidx = sidx;
         __syncthreads();
     }
@@ -228,9 +231,9 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     // chunk's index rows are one contiguous range, walked flat (entry f of the
     // chunk is entry e = f - s m of sample s) so that loads stay in flight.
     for (int s = ns; s < kChunk; ++s)
-        for (int b = tid; b < nb1; b += 256) off[s * nb1 + b] = 0;
+        for (int b = tid; b < nb1; b += NT) off[s * nb1 + b] = 0;
 #pragma unroll 4
-    for (int f = tid; f < tot; f += 256) {
+    for (int f = tid; f < tot; f += NT) {
         int s = (int)((float)f * inv_m);
         if (s * m > f) --s;
         if ((s + 1) * m <= f) ++s;
@@ -245,7 +248,7 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
 
     // exclusive scan of the segment sizes in (block, sample) order
     const int Q = nbc * kChunk;
-    const int per = (Q + 255) / 256;
+    const int per = (Q + NT - 1) / NT;
     const int q0 = tid * per;
     uint32_t run = 0;
     for (int k = 0; k < per; ++k) {
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
             run += off[s * nb1 + b + 1] - off[s * nb1 + b];
         }
     }
-    uint32_t pos = block_exclusive_scan256(run, wsum);
+    uint32_t pos = block_exclusive_scan<NT>(run, wsum);
     uint32_t* bs = BS + c * nb1;
     for (int k = 0; k < per; ++k) {
         const int q = q0 + k;
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     if (SS) {
         // start of segment (b, s) relative to block b's run
         uint16_t* ssc = SS + c * (int64_t)Q;
-        for (int q = tid; q < Q; q += 256) {
+        for (int q = tid; q < Q; q += NT) {
             const int b = q >> 5, s = q & 31;
             const uint32_t st = seg[q] + off[s * nb1 + b];
             const uint32_t s0 = seg[b * kChunk] + off[b];
@@ -297,10 +300,10 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
     if constexpr (VREG > 0) {
 #pragma unroll
         for (int k = 0; k < VREG; ++k)
-            if (tid + 256 * k < tot) put(tid + 256 * k, pv[k]);
+            if (tid + NT * k < tot) put(tid + NT * k, pv[k]);
     } else {
 #pragma unroll 4
-        for (int f = tid; f < tot; f += 256) put(f, cval[f]);
+        for (int f = tid; f < tot; f += NT) put(f, cval[f]);
     }
     if (CM) {
 #pragma unroll
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(256) void k_gram_pack(const float* __restrict__ val
         __syncthreads();
         if (tid == 0) {
             uint32_t mx = wsum[0];
-            for (int w = 1; w < 4; ++w) mx = wsum[w] > mx ? wsum[w] : mx;
+            for (int w = 1; w < NT / 64; ++w) mx = wsum[w] > mx ? wsum[w] : mx;
             CM[c] = mx;
         }
     }
@@ -1344,18 +1347,21 @@ static void dispatch_mfma(const GramPlan& g, int64_t grid, const uint32_t* P, co
 
 constexpr int kLdsMax = 160 * 1024;  // LDS of one workgroup on gfx950
 
-static size_t pack_lds_bytes(int nbc) { return ((size_t)kChunk * (nbc + 1) + (size_t)kChunk * nbc + 4) * 4; }
+static size_t pack_lds_bytes(int nbc, int nt = 256)
+{
+    return ((size_t)kChunk * (nbc + 1) + (size_t)kChunk * nbc + (size_t)nt / 64) * 4;
+}
 
 static void pack_attrs()
 {
     static bool pack_attr = false;
     if (!pack_attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<false, 0>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_pack<false, 0, 256>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)pack_lds_bytes(65536 / kSpW));
-        const void* staged[] = {reinterpret_cast<const void*>(&k_gram_pack<true, 0>),
-                                reinterpret_cast<const void*>(&k_gram_pack<true, 16>),
-                                reinterpret_cast<const void*>(&k_gram_pack<true, 32>),
-                                reinterpret_cast<const void*>(&k_gram_pack<true, 64>)};
+        const void* staged[] = {reinterpret_cast<const void*>(&k_gram_pack<true, 0, 256>),
+                                reinterpret_cast<const void*>(&k_gram_pack<true, 16, 256>),
+                                reinterpret_cast<const void*>(&k_gram_pack<true, 32, 256>),
+                                reinterpret_cast<const void*>(&k_gram_pack<true, 32, 512>)};
         for (const void* k : staged) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
         pack_attr = true;
     }
@@ -1366,26 +1372,27 @@ static hipError_t launch_pack(const GramPlan& g, int m, const float* vals, const
                               uint32_t* CM, hipStream_t s)
 {
     const bool stage = (size_t)kChunk * m * 2 <= (size_t)kPackStageBytes &&
-                       pack_lds_bytes(g.geom.nbc) + kPackStageBytes <= (size_t)kLdsMax &&
+                       pack_lds_bytes(g.geom.nbc, 512) + kPackStageBytes <= (size_t)kLdsMax &&
                        (reinterpret_cast<uintptr_t>(idx) & 15) == 0;
+    const int64_t tot = (int64_t)kChunk * m;  // entries of a full chunk
+    const int nt = (stage && tot > 256 * 32) ? 512 : 256;
     // the staged rows take what they need (more workgroups per CU than a fixed 32 KB)
-    const size_t lds = pack_lds_bytes(g.geom.nbc) + (stage ? (((size_t)kChunk * m * 2 + 15) & ~(size_t)15) : 0);
+    const size_t lds = pack_lds_bytes(g.geom.nbc, nt) + (stage ? (((size_t)kChunk * m * 2 + 15) & ~(size_t)15) : 0);
     pack_attrs();
     ProfScope ps_("gram_pack", s);
-    const int64_t tot = (int64_t)kChunk * m;  // entries of a full chunk
-#define PDS_PACK(ST, VR)                                                                                        \
-    hipLaunchKernelGGL((k_gram_pack<ST, VR>), dim3((unsigned)g.nchunks), dim3(256), lds, s, vals, idx, n, m,    \
+#define PDS_PACK(ST, VR, NT)                                                                                    \
+    hipLaunchKernelGGL((k_gram_pack<ST, VR, NT>), dim3((unsigned)g.nchunks), dim3(NT), lds, s, vals, idx, n, m,  \
                        g.geom.tr, g.geom.tc, g.geom.nbc, rowbytes, eb, split, P, OA, BS, SS, CM)
     if (!stage)
-        PDS_PACK(false, 0);
+        PDS_PACK(false, 0, 256);
     else if (tot <= 256 * 16)
-        PDS_PACK(true, 16);
+        PDS_PACK(true, 16, 256);
     else if (tot <= 256 * 32)
-        PDS_PACK(true, 32);
-    else if (tot <= 256 * 64)
-        PDS_PACK(true, 64);
+        PDS_PACK(true, 32, 256);
+    else if (tot <= 512 * 32)
+        PDS_PACK(true, 32, 512);
     else
-        PDS_PACK(true, 0);
+        PDS_PACK(true, 0, 256);
 #undef PDS_PACK
     return hipGetLastError();
 }
