@@ -653,6 +653,8 @@ __global__ __launch_bounds__(kUpdThreads) void k_kmeans_update(const unsigned lo
     double sum = 0.0;
     uint64_t cnt = 0;
     if (g < KP) {
+        // eight partials' loads in flight per thread; the sum keeps partial order
+#pragma unroll 8
         for (int w = wv; w < nparts; w += kUpdThreads / 64) {
             const int F = km_F<T>(PER_WG ? km_ev(wvmax[w]) : ev_g, lc_part);
             sum += km_fx_value<WS>(psum + ((int64_t)w * KP + g) * WS, F);
