@@ -741,7 +741,8 @@ static KmPlan km_plan(int prec, int p, int64_t n, int K, const DeviceInfo& dev)
     const int nt = k.global ? kKmThreads : kKmLdsThreads;
     // the cooperative kernel takes a quad of lanes per sample: a workgroup per
     // nt / 4 samples until every CU has one (at n = 70000 that halves the
-    // assignment, 64 -> 33 us, against 10 -> 25 us more partials to sum)
+    // assignment, 64 -> 33 us per round, for about 9 us more in the update,
+    // which sums 3.7 times as many partials)
     int64_t want = k.coop ? (n + nt / 4 - 1) / (nt / 4) : (n + nt - 1) / nt;
     int64_t cap = (int64_t)dev.cus * (k.global ? 8 : 1);
     if (!k.global && lds * 2 <= kKmLdsMax) cap = (int64_t)dev.cus * 2;
